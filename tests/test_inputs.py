@@ -1,0 +1,72 @@
+"""Host-side input generators: sphere packings, voxeliser, probes."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_0809_1547_amd import inputs as I
+
+
+def _min_gap(p):
+    c, r = p.centres, p.radii
+    d = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    return np.min(d - (r[:, None] + r[None, :]))
+
+
+@pytest.mark.parametrize("n,seed", [(48, 0), (64, 3)])
+def test_rsa_fill_no_overlap_and_diameters(n, seed):
+    p = I.rsa_pack(n, seed=seed, fill=0.4)
+    assert p.nominal_fill() >= 0.4
+    assert _min_gap(p) >= 0.0
+    d = 2 * p.radii
+    assert np.all(np.abs(d - 15.0) <= 3 * 1.5 + 1e-12)
+    assert abs(d.mean() - 15.0) < 1.0
+    assert np.all((p.centres >= 0) & (p.centres < n))
+
+
+def test_rsa_is_deterministic_per_seed():
+    a = I.rsa_pack(40, seed=7, fill=0.3)
+    b = I.rsa_pack(40, seed=7, fill=0.3)
+    c = I.rsa_pack(40, seed=8, fill=0.3)
+    assert np.array_equal(a.centres, b.centres)
+    assert not np.array_equal(a.centres[:5], c.centres[:5])
+
+
+def test_c1_packing_has_eight_equal_spheres():
+    p = I.packing_for("c1", 32, 0)
+    assert p.count == 8 and np.all(p.radii == 7.5)
+    assert _min_gap(p) >= 0
+
+
+def test_voxelize_marks_cell_centres_inside_spheres():
+    p = I.Packing((10, 10, 10), np.array([[5.0, 5.0, 5.0]]), np.array([2.2]))
+    eps, gain = I.voxelize(p)
+    kk, jj, ii = np.meshgrid(np.arange(10), np.arange(10), np.arange(10), indexing="ij")
+    inside = (ii + 0.5 - 5) ** 2 + (jj + 0.5 - 5) ** 2 + (kk + 0.5 - 5) ** 2 < 2.2 ** 2
+    assert np.array_equal(gain == 0, inside)
+    assert np.all(eps[inside] == np.float32(8.41)) and np.all(eps[~inside] == 1.0)
+
+
+def test_probes_are_distinct_void_interior_sites():
+    p = I.rsa_pack(32, seed=1, fill=0.3)
+    eps, gain = I.voxelize(p)
+    pr = I.select_probes(eps, gain, 256, seed=0)
+    assert len({tuple(r) for r in pr}) == 256
+    for c, i, j, k in pr:
+        assert c == 2 and gain[k, j, i] == 1 and 1 <= i < 32 and 1 <= j < 32 and 0 <= k < 32
+
+
+def test_batch_size_and_pump_draws():
+    s = I.batch_sizes(64, 0)
+    assert set(s) <= {48, 64, 80, 96} and len(set(s)) == 4
+    assert s == I.batch_sizes(64, 0)
+    lv = I.batch_pump_levels(16, 1.0)
+    assert lv[0] == pytest.approx(0.5) and lv[7] == pytest.approx(4.0) and lv[8] == lv[0]
+
+
+def test_dft_grid_resolution():
+    w = I.dft_omegas(450e-9, 800e-9, 5000, 3.81315e-17)
+    df = np.diff(w) / (2 * math.pi)
+    assert np.allclose(df, 1 / (5000 * 3.81315e-17))
+    assert 50 <= len(w) <= 60

@@ -1,0 +1,149 @@
+"""Pins of the oracle's boundary, source and monitors (rows a6, a7).
+
+* P7: the running DFT (sign e^{+i w t}, the Fourier convention of the
+  Gross-Pitaevskii section) of a single discrete cavity mode equals the
+  closed-form geometric sum; on a random series it equals numpy's FFT at the
+  FFT bins.
+* P8: the soft source's sampled spectrum equals the analytic Fourier
+  transform of a Gaussian-modulated sinusoid; the first-order Mur wall
+  reflects a guided TE10 wave with the exact discrete reflection coefficient
+  of the Mur recurrence on the Yee grid.
+* the loss-box monitor is the time sum of |E|^2 over the box.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_1547_amd import inputs as I
+from test_oracle_yee import cavity_mode, vacuum_oracle
+
+
+def test_p7_dft_of_a_cavity_mode_is_a_geometric_sum():
+    n, m = (12, 10, 8), (1, 2, 1)
+    o = vacuum_oracle(n)
+    mode = cavity_mode(n, m)
+    for c in range(3):
+        o.set_field(c, mode[c])
+    probe = (1, 5, 4, 3)
+    v = mode[1][probe[3], probe[2], probe[1]]
+    assert abs(v) > 0.05
+    dt = o.coefficients()[O.C_DT]
+    S = o.coefficients()[O.C_S]
+    theta = 2 * math.asin(S * math.sqrt(sum(math.sin(m[a] * math.pi / (2 * n[a])) ** 2
+                                             for a in range(3))))
+    om = np.array([0.3, 0.9, 1.0, 1.1, 2.5]) * theta / dt
+    o.set_probes(np.array([probe]), om)
+    M = 1500
+    o.step(M)
+    got = o.spectrum()[0]
+    # with H^{-1/2} = 0 the amplitude is e_m = cos(m theta + theta/2) / cos(theta/2)
+    expect = []
+    for w in om:
+        tot = 0
+        for sgn in (+1, -1):
+            r = np.exp(1j * (sgn * theta + w * dt))
+            geo = M if abs(1 - r) < 1e-13 else r * (1 - r ** M) / (1 - r)
+            tot += np.exp(1j * sgn * theta / 2) * geo
+        expect.append(v * tot / (2 * math.cos(theta / 2)))
+    expect = np.array(expect)
+    assert np.max(np.abs(got - expect)) < 1e-9 * np.max(np.abs(expect))
+
+
+def test_p7_dft_matches_fft_bins():
+    n = (8, 8, 8)
+    o = O.Oracle(O.default_params(n, noise=False))
+    pk = I.rsa_pack(n, seed=4, count=2, radius=2.0)
+    eps, _ = I.voxelize(pk)
+    o.set_material(eps, np.zeros_like(eps, dtype=np.uint8))
+    o.set_pump(2e24, O.GROUND)
+    f = I.random_fields(n, seed=5)
+    for c in range(3):
+        o.set_field(c, f[c])
+    M = 256
+    dt = o.coefficients()[O.C_DT]
+    ks = np.array([0, 3, 17, 64, 101, 128])
+    om = 2 * math.pi * ks / (M * dt)
+    probe = (0, 3, 4, 5)
+    o.set_probes(np.array([probe]), om)
+    series = []
+    for _ in range(M):
+        o.step(1)
+        series.append(o.field(0)[probe[3], probe[2], probe[1]])
+    x = np.array(series)
+    # sum_{m=1}^{M} x_m e^{2 pi i k m / M} = e^{2 pi i k/M} M ifft(x)[k]
+    ref = np.exp(2j * math.pi * ks / M) * M * np.fft.ifft(x)[ks]
+    assert np.max(np.abs(o.spectrum()[0] - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_p8_source_spectrum_is_the_analytic_transform():
+    o = vacuum_oracle((8, 8, 8))
+    lam, tau, t0, amp = 532e-9, 1e-15, 8e-15, 0.7
+    o.set_source(2, 4, 4, 3, amp=amp, lambda_s=lam, tau_p=tau, t0=t0)
+    dt = o.coefficients()[O.C_DT]
+    N = int(2 * t0 / dt) + 200
+    s = np.array([o.source_value(k) for k in range(N)])
+    t = (np.arange(N) + 1) * dt
+    ws = 2 * math.pi * 299792458.0 / lam
+    for w in np.array([0.2, 0.7, 1.0, 1.3, 2.0]) * ws:
+        got = np.sum(s * np.exp(1j * w * t)) * dt
+        expect = amp * np.exp(1j * w * t0) * math.sqrt(math.pi) * tau / 2j * (
+            math.exp(-tau ** 2 * (w + ws) ** 2 / 4) - math.exp(-tau ** 2 * (w - ws) ** 2 / 4))
+        assert abs(got - expect) < 1e-9 * amp * tau
+
+
+def _mur_reflection(theta, beta, m):
+    q = np.exp(-1j * theta)
+    p = np.exp(1j * beta)
+    return (1 / p + m * q / p - m - q) / (q - p - m * q * p + m)
+
+
+def test_p8_mur_reflection_of_a_guided_wave():
+    nx, ny, nz = 8, 2, 1200
+    n = (nx, ny, nz)
+    o = O.Oracle(O.default_params(n, noise=False, bc=(O.PEC, O.PEC, O.MUR1)))
+    o.set_material(*I.homogeneous(n, 1.0, 0))
+    o.set_pump(2e24, O.GROUND)
+    kc, sig, beta0, kp = 500, 40.0, 2 * math.pi / 12, 900
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                             indexing="ij")
+    ey = np.sin(math.pi * ii / nx) * np.exp(-0.5 * ((kk - kc) / sig) ** 2) * np.cos(beta0 * kk)
+    ey[~I.interior_e_mask(n, 1)] = 0.0
+    o.set_field(1, ey)
+    S = o.coefficients()[O.C_S]
+    dt = o.coefficients()[O.C_DT]
+    betas = beta0 + np.linspace(-0.04, 0.04, 9)
+    thetas = 2 * np.arcsin(S * np.sqrt(np.sin(math.pi / (2 * nx)) ** 2 + np.sin(betas / 2) ** 2))
+    o.set_probes(np.array([(1, nx // 2, 0, kp)]), thetas / dt)
+    # incident packet passes the probe, then its reflection from the z = nz
+    # wall returns before the reflection from the z = 0 wall can arrive
+    o.step(1560)
+    f_inc = o.spectrum()[0].copy()
+    o.step(1106)
+    f_ref = o.spectrum()[0] - f_inc
+    R_meas = f_ref / f_inc * np.exp(2j * betas * (kp - nz))
+    m = (S - 1) / (S + 1)
+    R_th = _mur_reflection(thetas, betas, m)
+    assert np.all(np.abs(R_th) > 1e-3) and np.all(np.abs(R_th) < 0.2)
+    assert np.max(np.abs(R_meas - R_th) / np.abs(R_th)) < 1e-4
+
+
+def test_loss_box_is_time_sum_of_e_squared():
+    n = (8, 8, 8)
+    o = O.Oracle(O.default_params(n, noise=False))
+    o.set_material(*I.homogeneous(n, 2.0, 0))
+    o.set_pump(2e24, O.GROUND)
+    f = I.random_fields(n, seed=7)
+    for c in range(3):
+        o.set_field(c, f[c])
+    lo, hi = (2, 3, 1), (6, 7, 5)
+    o.set_loss_box(lo, hi)
+    tot = 0.0
+    for _ in range(30):
+        o.step(1)
+        for c in range(3):
+            e = o.field(c)[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+            msk = I.interior_e_mask(n, c)[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+            tot += float(np.sum(e[msk] ** 2))
+    assert o.loss() == pytest.approx(tot, rel=1e-13)

@@ -1,0 +1,60 @@
+"""The oracle's pins have teeth: each plausible mistake planted in a copy of
+the oracle source (a sign, an index, a dropped term, a swapped operand) must
+make at least one pin test fail.  Everything here runs on the CPU; the
+mutated libraries live in a temporary directory."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mb_oracle.c")
+PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_yee.py", "tests/test_oracle_bloch.py",
+        "tests/test_oracle_monitors.py"]
+
+# (name, original text, mutated text)
+MUTATIONS = [
+    ("faraday_sign", "s->Hn[0][x] = Hx[x] - S * cx;", "s->Hn[0][x] = Hx[x] + S * cx;"),
+    ("curl_index", "double cx = (Ez[xj] - Ez[x])", "double cx = (Ez[xi] - Ez[x])"),
+    ("curl_operand_order", "double cz = (Ey[xi] - Ey[x]) - (Ex[xj] - Ex[x]);",
+     "double cz = (Ex[xj] - Ex[x]) - (Ey[xi] - Ey[x]);"),
+    ("ampere_index", "curl = (Hz[x] - Hz[at(s, i, j - 1, k)])", "curl = (Hz[x] - Hz[at(s, i - 1, j, k)])"),
+    ("ampere_polarisation_sign", "ie * (S * curl - dP)", "ie * (S * curl + dP)"),
+    ("ampere_missing_inv_eps", "s->Eold[c][x] + ie * (S * curl - dP)", "s->Eold[c][x] + (S * curl - dP)"),
+    ("lorentz_history", "c[ORC_C_B] * Pprev", "c[ORC_C_B] * P"),
+    ("lorentz_inversion_sign", "double dN = s->f[12 + c][x] - s->f[15 + c][x];",
+     "double dN = s->f[15 + c][x] - s->f[12 + c][x];"),
+    ("lorentz_damping", "c[ORC_C_A] = rnd(s, (2.0 - wa * wa * dt * dt) / D);",
+     "c[ORC_C_A] = rnd(s, (2.0 - wa * wa * dt * dt));"),
+    ("rate_work_sign", "c[ORC_C_DT10] * n1 - W;", "c[ORC_C_DT10] * n1 + W;"),
+    ("rate_dropped_decay", "N[3] = n3 + c[ORC_C_DTWP] * n0 - c[ORC_C_DT32] * n3;",
+     "N[3] = n3 + c[ORC_C_DTWP] * n0;"),
+    ("rate_work_factor", "double W = c[ORC_C_BETA] * Ebar * dP;", "double W = c[ORC_C_BETA] * Ebar * Ebar * dP;"),
+    ("energy_missing_eps", "acc += e * s->f[c][x] * s->f[c][x];", "acc += s->f[c][x] * s->f[c][x];"),
+    ("mur_new_neighbour", "E[xb] = Eo[x1] + m * (E[x1] - Eo[xb]);", "E[xb] = Eo[x1] + m * (Eo[x1] - Eo[xb]);"),
+    ("mur_coefficient_sign", "return rnd(s, (sp - 1.0) / (sp + 1.0));", "return rnd(s, (1.0 - sp) / (sp + 1.0));"),
+    ("dft_sign", "s->spec[o + 1] += e * sin(ph);", "s->spec[o + 1] -= e * sin(ph);"),
+    ("dft_time_index", "const double tn = (double)(s->step + 1) * dt;", "const double tn = (double)(s->step) * dt;"),
+    ("source_phase", "s->src_amp * sin(s->src_ws * t)", "s->src_amp * cos(s->src_ws * t)"),
+    ("philox_weyl", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;"),
+    ("philox_word_order", "uint32_t y1 = lo1;", "uint32_t y1 = lo0;"),
+    ("rate_work_factor_only", "double W = c[ORC_C_BETA] * Ebar * dP;", "double W = 0.5 * c[ORC_C_BETA] * Ebar * dP;"),
+    ("prepump_fixed_point", "N[2] = rnd(s, dwp * n0 / d21);", "N[2] = rnd(s, dwp * n0 / d32);"),
+]
+
+
+@pytest.mark.parametrize("name,orig,mut", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(tmp_path, name, orig, mut):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
+    bad = tmp_path / "mb_oracle.c"
+    bad.write_text(src.replace(orig, mut))
+    (tmp_path / "mb_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "mb_oracle.h")).read())
+    lib = tmp_path / "libbad.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-o", str(lib), str(bad), "-lm"], check=True)
+    env = dict(os.environ, MB_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
