@@ -1,0 +1,212 @@
+"""Throughput benchmark of the Maxwell-Bloch FDTD step on one MI355X.
+
+Workload (default): the paper-scale realization -- 320^3 cells (6.4 um box,
+~8800 RSA spheres of mean diameter 300 nm, index 2.9, fill 0.4, gain in the
+voids), ground-state start, spontaneous-emission noise, 256 probe sites with
+running DFT spectra over 450-800 nm at the resolution of the full 3 ps run,
+graded absorbing walls -- advanced as a batch of 5 pump levels
+N_a in {1, 2, 3.5, 5, 7} x 1e24 m^-3.  One bench step = one time step of all
+5 realizations (5 x 320^3 cell-updates).
+
+Prints ONE JSON line: cell-updates/s, the roofline of the dominant kernel
+(the fused step kernel, HBM bound: algorithmic bytes per launch / average
+launch duration from HIP events on its stream) and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+NA_LEVELS = [1e24, 2e24, 3.5e24, 5e24, 7e24]
+RUN_STEPS_3PS = 78675          # 3 ps at dt = 3.81315e-17 s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=192)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--n", type=int, default=320, help="cells per side")
+    ap.add_argument("--batch", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_sha):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "fused_step_c5_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    s = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    if not m or not s or s.group(1) != kernel_sha:
+        return None
+    return float(m.group(1))
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mbf_kernels.hpp", "mbf.hip"):
+        h.update(open(os.path.join(ROOT, "paper_0809_1547_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n, eps, gain, seconds):
+    """The FP64 oracle, as it stands, on a bounded number of steps of one
+    realization of the same workload."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    p = O.default_params(n, bc=(O.ABSORB,) * 3, seed=0, realization=0)
+    o = O.Oracle(p)
+    o.set_material(eps, gain)
+    o.set_pump(NA_LEVELS[1], O.GROUND)
+    o.step(1)                      # first touch of the arrays
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": n ** 3 * steps / dt, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} steps of one {n}^3 realization (N_a = 2e24, FP64, "
+                      f"{threads} OpenMP threads), after one untimed step"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_0809_1547_amd import inputs as I
+    from paper_0809_1547_amd import mbf
+
+    n = args.n
+    t0 = time.perf_counter()
+    pk = I.rsa_pack(n, seed=0, fill=0.4)
+    eps, gain = I.voxelize(pk)
+    log(f"packing: {pk.count} spheres, voxel fill {1 - gain.mean():.3f} ({time.perf_counter() - t0:.1f} s)")
+    probes = I.select_probes(eps, gain, 256, seed=0)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    sims = []
+    for r in range(args.batch):
+        s = mbf.Sim(n, boundary="absorb", seed=0, realization=r, stream=stream.cuda_stream)
+        s.set_material(eps, gain)
+        s.set_pump(NA_LEVELS[r % len(NA_LEVELS)], "ground")
+        dt = s.coefficients()[mbf.MBF_C_DT]
+        om = I.dft_omegas(450e-9, 800e-9, RUN_STEPS_3PS, dt)
+        s.set_probes(probes, om, decim=32)
+        sims.append(s)
+    log(f"set-up of {args.batch} x {n}^3 done ({time.perf_counter() - t0:.1f} s), "
+        f"{len(om)} DFT bins, tuning {sims[0].tuning()}")
+    tuning = sims[0].tuning()
+    for s in sims:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    log("warm-up done")
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kern_ms = 0.0
+    launches = 0
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for s in sims:
+        ms, cnt = s.step_timed(args.steps)
+        kern_ms += ms
+        launches += cnt
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = ev0.elapsed_time(ev1)
+    for s in sims:
+        W, _ = s.energy()                 # raises on a non-finite energy
+    cells = n ** 3
+    cu = cells * args.batch * args.steps
+    value = cu / (wall_ms / 1e3)
+    alg_bytes = sims[0].step_bytes()      # same material map for every member
+    avg_kern_s = kern_ms / launches / 1e3
+    achieved = alg_bytes / avg_kern_s / 1e9
+    sha = kernel_source_sha()
+    traffic = traffic_from_profiles(sha)
+    log(f"timed {args.steps} steps x {args.batch}: {wall_ms:.1f} ms, kernel avg "
+        f"{avg_kern_s * 1e3:.3f} ms, {alg_bytes / cells:.1f} alg. B/cell")
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        for s in sims:
+            s.close()
+        cpu = cpu_baseline(n, eps, gain, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"paper-scale realization {n}^3 x batch of {args.batch} pump levels "
+                        f"(RSA spheres d=300nm n=2.9 fill 0.4, gain in voids, ground start, "
+                        f"noise, 256 probes x {len(om)} DFT bins, absorbing walls)",
+            "cells_per_realization": cells,
+            "batch": args.batch,
+            "pump_levels_m3": [NA_LEVELS[r % len(NA_LEVELS)] for r in range(args.batch)],
+            "tuning": tuning,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_step_fused (rows a1-a5, one launch per realization and step)",
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": avg_kern_s * 1e3,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

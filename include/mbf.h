@@ -1,0 +1,265 @@
+/*
+ * mbf -- Maxwell-Bloch FDTD on one MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  One handle = one simulation: a Yee grid of
+ * nx*ny*nz cells carrying the 21 fields of the vectorial Maxwell-Bloch model
+ * of the paper's Simulations section (E, H, the polarisation P with its
+ * previous value, and populations N1, N2, N3 of a four-level gain medium at
+ * every E-site of a gain cell; N0 = N_a - N1 - N2 - N3 is derived), dielectric
+ * spheres with gain only in the voids, and spontaneous-emission noise from a
+ * counter-based Philox4x32-10 stream keyed by (seed, realization, cell, step).
+ *
+ * One step n (scaled units: x in dx, t in dt, E in E_ref, H in E_ref/eta0,
+ * P in eps0 E_ref, N in N_ref):
+ *   a1  H^{n+1/2} = H^{n-1/2} - S curl+ E^n
+ *   a2  P^{n+1} = a P^n + b P^{n-1} + ck (N1-N2) E^n + cF xi^n   (gain sites)
+ *   a3  E^{n+1} = E^n + (1/eps_r)(S curl- H^{n+1/2} - (P^{n+1} - P^n))
+ *   a6  PEC or first-order Mur walls, then the soft source, on E^{n+1}
+ *   a4  four-level rates with the field work beta (E^{n+1}+E^n)/2 (P^{n+1}-P^n)
+ *   a7  FP64 monitors: energy, running DFT at probe sites, loss-box sum
+ *
+ * Conventions
+ *  - Every call returns an int status: MBF_OK (0) or a negative MBF_E* code.
+ *    mbf_last_error(h) returns a message owned by the handle, valid until the
+ *    next call on it; mbf_global_error() covers failures before a handle
+ *    exists.  No C++ exception crosses this interface.
+ *  - The handle owns all device memory it allocates and frees it in
+ *    mbf_destroy.  The caller owns every buffer it passes; sizes are implied
+ *    by the grid and checked where a size is passed.
+ *  - Pointers tagged MBF_MEM_DEVICE are device addresses (for instance a torch
+ *    tensor's data_ptr()); MBF_MEM_HOST pointers are ordinary host memory.
+ *    The caller keeps device buffers alive until the work queued on the
+ *    handle's stream has finished.
+ *  - `stream` is a hipStream_t passed as void*.  NULL makes the handle create
+ *    and own a stream of default priority.  All work is queued on that stream;
+ *    reads into host memory synchronise it.
+ *  - Site arrays (mbf_read_field / mbf_write_field) span the extended Yee
+ *    index range (nx+1)*(ny+1)*(nz+1), x fastest, in the handle's precision
+ *    (float for MBF_FP32, double for MBF_FP64).  E-site (c; i,j,k) of
+ *    component c lies at the cell edge (i,j,k) + e_c/2, H-site at the face
+ *    (i,j,k) + (1 - e_c)/2.  Cell arrays (material) span nx*ny*nz.
+ *  - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef MBF_H
+#define MBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MBF_OK 0
+#define MBF_EINVAL (-1)      /* bad argument or configuration */
+#define MBF_ECFL (-2)        /* Courant number outside (0, 1] */
+#define MBF_ENOMEM (-3)      /* device or host allocation failed */
+#define MBF_EHIP (-4)        /* a HIP runtime call failed */
+#define MBF_ENONFINITE (-5)  /* the energy monitor saw a NaN or infinity */
+#define MBF_ESTATE (-6)      /* call not valid in the handle's current state */
+#define MBF_ENODEV (-7)      /* no usable gfx950 device */
+
+/* boundary per axis */
+#define MBF_PEC 0
+#define MBF_MUR1 1    /* first-order Mur on the wall E-sites */
+#define MBF_ABSORB 2  /* graded impedance-matched lossy layer of absorb_cells
+                         cells, backed by a conducting wall: in the layer H and
+                         E lose a fraction 2a/(1+a) per step (a = absorb_rate
+                         ((depth)/absorb_cells)^absorb_order summed over axes),
+                         the same for E and H so that every medium stays matched */
+
+/* initial populations for mbf_set_pump */
+#define MBF_INIT_GROUND 0     /* N0 = N_a, N1 = N2 = N3 = 0 */
+#define MBF_INIT_PREPUMPED 1  /* E = 0 fixed point of the discrete rates */
+
+/* precision of the fields */
+#define MBF_FP32 0
+#define MBF_FP64 1
+
+#define MBF_MEM_HOST 0
+#define MBF_MEM_DEVICE 1
+
+/* flags */
+#define MBF_FLAG_FROZEN_POP 1  /* populations held fixed (row a4 skipped) */
+
+/* field ids for mbf_read_field / mbf_write_field */
+#define MBF_EX 0
+#define MBF_EY 1
+#define MBF_EZ 2
+#define MBF_HX 3
+#define MBF_HY 4
+#define MBF_HZ 5
+#define MBF_PX 6        /* P^n */
+#define MBF_PPREVX 9    /* P^{n-1} */
+#define MBF_N1X 12
+#define MBF_N2X 15
+#define MBF_N3X 18
+#define MBF_NFIELDS 21
+
+/* coefficient vector returned by mbf_coefficients (values as used on the
+ * device, promoted to double) */
+enum {
+    MBF_C_DT, MBF_C_S, MBF_C_A, MBF_C_B, MBF_C_CK, MBF_C_CF, MBF_C_BETA,
+    MBF_C_DT32, MBF_C_DT21, MBF_C_DT10, MBF_C_DTWP, MBF_C_NA, MBF_C_COUNT
+};
+
+typedef struct mbf_config {
+    int32_t nx, ny, nz;        /* cells per axis, each >= 2 */
+    int32_t boundary[3];       /* MBF_PEC or MBF_MUR1 per axis */
+    int32_t precision;         /* MBF_FP32 or MBF_FP64 */
+    int32_t noise;             /* 1: spontaneous-emission source on */
+    int32_t flags;             /* MBF_FLAG_* */
+    int32_t reserved0;
+    double dx;                 /* cell size [m] */
+    double courant;            /* c dt sqrt(3)/dx, in (0, 1] */
+    double lambda0, dlambda;   /* gain centre wavelength and bandwidth [m] */
+    double tau32, tau21, tau10;/* level lifetimes [s]; tau21 also fixes the coupling */
+    double Wp;                 /* pump rate 0 -> 3 [1/s] */
+    double N_ref, E_ref;       /* scaling density [m^-3] and field [V/m] */
+    double E_sp;               /* noise amplitude in units of E_ref */
+    uint64_t seed;             /* Philox key */
+    uint32_t realization;      /* third Philox counter word */
+    int32_t reserved1;
+    int64_t energy_history;    /* steps of per-step energy kept on device (0: none) */
+    int32_t absorb_cells;      /* depth of the MBF_ABSORB layer in cells (>= 1) */
+    int32_t absorb_order;      /* grading exponent of the layer (>= 0) */
+    double absorb_rate;        /* loss a at the wall, per step (>= 0) */
+} mbf_config;
+
+typedef struct mbf_handle mbf_handle;
+typedef struct mbf_batch mbf_batch;
+
+/* Library version string; never fails. */
+const char* mbf_version(void);
+
+/* Message of the last failure that happened without a handle (create). */
+const char* mbf_global_error(void);
+
+/* Message of the last failure on h (empty string when none). */
+const char* mbf_last_error(const mbf_handle* h);
+
+/* Fill *cfg with the workload defaults (dx 20 nm, Courant 0.99, lambda0
+ * 590 nm, bandwidth 230 nm, tau32 = tau10 = 100 fs, tau21 = 1 ns,
+ * Wp = 1e12 /s, N_ref 1e24 m^-3, E_ref 1e8 V/m, E_sp 1e-6, PEC, FP32, noise
+ * on, seed 0, lossy layer 8 cells deep, quadratic, a = 0.25 at the wall).
+ * Returns MBF_EINVAL for NULL or sizes < 2. */
+int mbf_config_default(mbf_config* cfg, int nx, int ny, int nz);
+
+/* Validate cfg (sizes, Courant number, finite positive parameters) before any
+ * allocation, then allocate the device state on the current device and zero
+ * it.  *out receives the handle.  Errors: MBF_EINVAL, MBF_ECFL, MBF_ENODEV,
+ * MBF_ENOMEM, MBF_EHIP. */
+int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out);
+
+/* Free everything the handle owns.  NULL is ignored. */
+void mbf_destroy(mbf_handle* h);
+
+/* Coefficients as stored on the device (MBF_C_COUNT doubles into out[n]). */
+int mbf_coefficients(const mbf_handle* h, double* out, int n);
+
+/* Material map (Simulations section: spheres of index 2.9 in a background,
+ * gain only in the voids).  eps_r[nx*ny*nz] relative permittivity (> 0) and
+ * gain[nx*ny*nz] (0 or 1) per cell, x fastest; an E-site takes the values of
+ * the cell whose edge it lies on.  At most 255 distinct (eps_r, gain) pairs.
+ * Copies; the caller's buffers are not retained. */
+int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int mem_kind);
+
+/* Pump density N_a [m^-3] (Simulations section: the pump is set through the
+ * atomic density and is constant over the run).  Zeroes E, H, P and the
+ * monitors, sets the populations of every gain E-site per `init`, and resets
+ * the step counter to 0. */
+int mbf_set_pump(mbf_handle* h, double Na, int init);
+
+/* Soft point source on E-site (comp; i,j,k), which must be interior:
+ * amp * sin(w_s (t - t0)) * exp(-((t - t0)/tau_p)^2) with w_s = 2 pi c /
+ * lambda_s, added to E^{n+1} at t = (n+1) dt (passive broadband run of the
+ * Simulations section: single-cycle ~1 fs pulse at 532 nm).  One source per
+ * handle; amp = 0 removes it. */
+int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double amp,
+                         double lambda_s, double tau_p, double t0);
+
+/* Running DFT monitor: F[p][w] += E_c(site_p)^{m} exp(+i omega_w m dt) for
+ * every sample m (the Fourier sign of the Gross-Pitaevskii section).
+ * sites[4*n_probes] rows (comp, i, j, k); omega[n_freq] in rad/s; samples are
+ * buffered `decim` steps on the device (1..1024) and folded into FP64
+ * accumulators.  Replaces any previous probe set and zeroes the spectrum. */
+int mbf_set_probes(mbf_handle* h, const int32_t* sites, int n_probes, const double* omega,
+                   int n_freq, int decim);
+
+/* Loss-box monitor: L += sum of |E|^2 over the interior E-sites of cells in
+ * [i0,i1) x [j0,j1) x [k0,k1), every step, in FP64. */
+int mbf_set_loss_box(mbf_handle* h, int i0, int j0, int k0, int i1, int j1, int k1);
+
+/* Queue nsteps steps on the handle's stream (asynchronous).  Requires
+ * mbf_set_material and mbf_set_pump first (MBF_ESTATE otherwise). */
+int mbf_step(mbf_handle* h, int64_t nsteps);
+
+/* Block until the handle's stream is idle. */
+int mbf_sync(mbf_handle* h);
+
+/* Steps taken since the last mbf_set_pump. */
+int mbf_step_index(const mbf_handle* h, int64_t* out);
+
+/* W_now = energy W^n of the last step, W_int = sum of W over all steps
+ * (scaled units; multiply by eps0 E_ref^2 dx^3 for joules).  Synchronises.
+ * MBF_ENONFINITE once any step produced a NaN or infinite energy. */
+int mbf_read_energy(mbf_handle* h, double* W_now, double* W_int);
+
+/* Per-step energy history (capacity set by cfg.energy_history); *count
+ * receives the number of stored steps, min(count, cap) are copied. */
+int mbf_read_energy_history(mbf_handle* h, double* out, int64_t cap, int64_t* count);
+
+/* Spectrum re_im[2 * n_probes * n_freq] (probe-major, interleaved re, im). */
+int mbf_read_spectrum(mbf_handle* h, double* re_im);
+
+/* Loss-box integral. */
+int mbf_read_loss(mbf_handle* h, double* out);
+
+/* Copy one site array out of / into the device state (see field ids).
+ * Reading P gives P^n, MBF_PPREVX+c gives P^{n-1}. */
+int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind);
+int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
+
+/* Kernel schedule.  MBF_VARIANT_FUSED runs rows a1-a5 in one z-marching
+ * kernel per step (tiles of 64 x tile_y columns, z segments of zseg planes,
+ * workgroups grouped per XCD when xcd_remap = 1); MBF_VARIANT_TWO_PASS runs a1
+ * and a2-a5 as two kernels.  Both give bitwise identical fields.  zseg = 0
+ * picks a segment length from the grid size.  tile_y must be 2, 4, 8 or 16. */
+#define MBF_VARIANT_TWO_PASS 0
+#define MBF_VARIANT_FUSED 1
+typedef struct mbf_tuning {
+    int32_t variant;
+    int32_t tile_y;
+    int32_t zseg;
+    int32_t xcd_remap;
+} mbf_tuning;
+int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t);
+int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
+
+/* Queue nsteps steps without graph capture, bracketing the dominant kernel of
+ * every step with a pair of HIP events on the handle's stream; on return
+ * (synchronised) *kernel_ms holds the summed duration of those kernels and
+ * *launches their count.  Used to time the kernel against its roofline. */
+int mbf_step_timed(mbf_handle* h, int64_t nsteps, double* kernel_ms, int64_t* launches);
+
+/* Algorithmic HBM bytes of one step: what the step must move if every value
+ * is read and written exactly once.  Per cell: E and H read and written
+ * (4 x 3 values) and 1 material byte; per interior gain E-site: P^n and
+ * P^{n-1} read, P^{n+1} written, N1..N3 read and written (9 values).  A value
+ * is 4 B in FP32 and 8 B in FP64, so a cell whose three E-sites carry gain
+ * costs 157 B in FP32.  Counted from the current material map. */
+int mbf_step_bytes(const mbf_handle* h, double* bytes);
+
+/* Checkpoint: bytes needed, save into / load from a caller buffer.  The
+ * image holds all 21 fields, the step index and the monitors, with a
+ * checksum; noise needs no state (it is keyed by the step index), so a
+ * resumed run is bitwise identical to an uninterrupted one. */
+int mbf_state_size(const mbf_handle* h, size_t* out);
+int mbf_save_state(mbf_handle* h, void* buf, size_t n);
+int mbf_load_state(mbf_handle* h, const void* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

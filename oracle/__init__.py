@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # MB_ORACLE_LIB lets the mutation test load a deliberately broken build
 LIB_PATH = os.environ.get("MB_ORACLE_LIB") or os.path.join(HERE, "libmboracle.so")
 
-PEC, MUR1 = 0, 1
+PEC, MUR1, ABSORB = 0, 1, 2
 GROUND, PREPUMPED = 0, 1
 NFIELDS = 24
 # coefficient vector indices (mb_oracle.h)
@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("Wp", C.c_double), ("N_ref", C.c_double), ("E_ref", C.c_double),
         ("E_sp", C.c_double),
         ("seed", C.c_uint64), ("realization", C.c_uint32), ("noise", C.c_int32),
+        ("absorb_cells", C.c_int32), ("absorb_order", C.c_int32), ("absorb_rate", C.c_double),
     ]
 
 
@@ -93,7 +94,7 @@ def default_params(n, *, bc=(PEC, PEC, PEC), round_f32=False, frozen_pop=False,
     """Parameter block with the workload defaults (dx 20 nm, Courant 0.99,
     lambda0 590 nm, 230 nm gain bandwidth, tau32 = tau10 = 100 fs,
     tau21 = 1 ns, W_p = 1e12 /s, E_ref = 1e8 V/m, N_ref = 1e24 m^-3,
-    E_sp = 1e-6)."""
+    E_sp = 1e-6; lossy layer of 8 cells, quadratic grading, a_max = 0.25)."""
     if isinstance(n, int):
         n = (n, n, n)
     p = Params()
@@ -113,6 +114,9 @@ def default_params(n, *, bc=(PEC, PEC, PEC), round_f32=False, frozen_pop=False,
     p.N_ref = kw.pop("N_ref", 1e24)
     p.E_ref = kw.pop("E_ref", 1e8)
     p.E_sp = kw.pop("E_sp", 1e-6)
+    p.absorb_cells = kw.pop("absorb_cells", 8)
+    p.absorb_order = kw.pop("absorb_order", 2)
+    p.absorb_rate = kw.pop("absorb_rate", 0.25)
     if kw:
         raise TypeError(f"unknown parameters {sorted(kw)}")
     p.seed = seed

@@ -47,6 +47,7 @@ struct orc_sim {
     double* hist;
     int64_t hist_len, hist_cap;
     double* plane_sum;         /* per-plane partial sums, summed in order */
+    double* prof[3][2];        /* loss profile per axis at integer / half positions */
 };
 
 static double rnd(const orc_sim* s, double v) { return s->p.round_f32 ? (double)(float)v : v; }
@@ -73,6 +74,31 @@ static int e_interior(const orc_sim* s, int c, int i, int j, int k) {
         }
     }
     return 1;
+}
+
+/* Loss a = sigma dt / (2 eps) of the graded layer at coordinate x (cells) on
+ * axis a: a_max ((L - x)/L)^p near the low wall, a_max ((x - (n - L))/L)^p near
+ * the high wall, 0 in between. */
+static double layer_profile(const orc_sim* s, int a, double x) {
+    if (s->p.bc[a] != ORC_ABSORB || s->p.absorb_cells <= 0) return 0.0;
+    const double L = (double)s->p.absorb_cells;
+    const double n = (double)dim(s, a);
+    double v = 0.0;
+    if (x < L) v += pow((L - x) / L, (double)s->p.absorb_order);
+    if (x > n - L) v += pow((x - (n - L)) / L, (double)s->p.absorb_order);
+    return s->p.absorb_rate * v;
+}
+
+/* loss of an E-site (half position along its own axis) or H-site (half
+ * positions along the two other axes) */
+static double site_loss(const orc_sim* s, int is_h, int c, int i, int j, int k) {
+    const int idx[3] = {i, j, k};
+    double a = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int half = is_h ? (ax != c) : (ax == c);
+        a += s->prof[ax][half][idx[ax]];
+    }
+    return a;
 }
 
 /* ---------------------------------------------------------------- Philox */
@@ -212,6 +238,13 @@ orc_sim* orc_create(const orc_params* p) {
     s->gain = (uint8_t*)calloc(ncell, 1);
     s->plane_sum = (double*)calloc((size_t)p->nz + 1, sizeof(double));
     for (size_t q = 0; q < ncell; ++q) { s->eps[q] = 1.0; s->inv_eps[q] = 1.0; }
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) {
+            const int n = dim(s, a);
+            s->prof[a][h] = (double*)calloc((size_t)n + 1, sizeof(double));
+            for (int q = 0; q <= n; ++q)
+                s->prof[a][h][q] = rnd(s, layer_profile(s, a, (double)q + (h ? 0.5 : 0.0)));
+        }
     compute_coefficients(s);
     return s;
 }
@@ -221,6 +254,7 @@ void orc_destroy(orc_sim* s) {
     for (int q = 0; q < ORC_NFIELDS; ++q) free(s->f[q]);
     for (int q = 0; q < 3; ++q) { free(s->Hn[q]); free(s->Eold[q]); }
     free(s->eps); free(s->inv_eps); free(s->gain); free(s->plane_sum);
+    for (int a = 0; a < 3; ++a) { free(s->prof[a][0]); free(s->prof[a][1]); }
     free(s->probes); free(s->omega); free(s->spec); free(s->hist);
     free(s);
 }
@@ -389,9 +423,17 @@ static void update_h(orc_sim* s) {
                 double cx = (Ez[xj] - Ez[x]) - (Ey[xk] - Ey[x]);
                 double cy = (Ex[xk] - Ex[x]) - (Ez[xi] - Ez[x]);
                 double cz = (Ey[xi] - Ey[x]) - (Ex[xj] - Ex[x]);
-                s->Hn[0][x] = Hx[x] - S * cx;
-                s->Hn[1][x] = Hy[x] - S * cy;
-                s->Hn[2][x] = Hz[x] - S * cz;
+                const double c3[3] = {cx, cy, cz};
+                const double* H3[3] = {Hx, Hy, Hz};
+                for (int c = 0; c < 3; ++c) {
+                    const double a = site_loss(s, 1, c, i, j, k);
+                    if (a == 0.0) {
+                        s->Hn[c][x] = H3[c][x] - S * c3[c];
+                    } else {
+                        /* semi-implicit loss: (H' - H) = -S curl - a (H' + H) */
+                        s->Hn[c][x] = ((1.0 - a) / (1.0 + a)) * H3[c][x] - (1.0 / (1.0 + a)) * (S * c3[c]);
+                    }
+                }
             }
 }
 
@@ -467,7 +509,12 @@ static void update_e(orc_sim* s) {
                     else
                         curl = (Hy[x] - Hy[at(s, i - 1, j, k)]) - (Hx[x] - Hx[at(s, i, j - 1, k)]);
                     double dP = g ? s->f[6 + c][x] - s->f[9 + c][x] : 0.0;
-                    s->f[c][x] = s->Eold[c][x] + ie * (S * curl - dP);
+                    const double a = site_loss(s, 0, c, i, j, k);
+                    if (a == 0.0)
+                        s->f[c][x] = s->Eold[c][x] + ie * (S * curl - dP);
+                    else
+                        s->f[c][x] = ((1.0 - a) / (1.0 + a)) * s->Eold[c][x] +
+                                     (1.0 / (1.0 + a)) * (ie * (S * curl - dP));
                 }
             }
     for (int c = 0; c < 3; ++c) memcpy(s->f[3 + c], s->Hn[c], sizeof(double) * s->ntot);
@@ -484,7 +531,8 @@ static double mur_coef(const orc_sim* s, int i, int j, int k) {
 
 /* a6: first-order Mur on the faces of Mur axes, applied face by face in x, y,
  * z order in place (so an edge keeps the value of its last face).  A site on
- * any PEC wall is never written and stays zero. */
+ * any PEC wall (or the conducting wall behind a lossy layer) is never written
+ * and stays zero. */
 static void apply_mur(orc_sim* s) {
     const int n[3] = {s->nx, s->ny, s->nz};
     for (int a = 0; a < 3; ++a) {
@@ -504,8 +552,8 @@ static void apply_mur(orc_sim* s) {
                         for (int i = lo[0]; i < hi[0]; ++i) {
                             int idx[3] = {i, j, k};
                             int on_pec = 0;
-                            for (int b = 0; b < 3; ++b)
-                                if (b != c && s->p.bc[b] == ORC_PEC && (idx[b] == 0 || idx[b] == n[b]))
+                            for (int b = 0; b < 3; ++b)   /* PEC and lossy-layer walls conduct */
+                                if (b != c && s->p.bc[b] != ORC_MUR1 && (idx[b] == 0 || idx[b] == n[b]))
                                     on_pec = 1;
                             if (on_pec) continue;
                             int jdx[3] = {i, j, k};

@@ -19,7 +19,11 @@
  *                                         (Lorentz oscillator, gain E-sites)
  *   a3  E^{n+1}   = E^n + (1/eps_r)(S curl- H^{n+1/2} - (P^{n+1}-P^n))
  *                                                                (Ampere)
- *   a6  boundary (PEC walls or first-order Mur) and soft source on E^{n+1}
+ *   a6  boundary (PEC walls, first-order Mur, or a graded impedance-matched
+ *       lossy layer backed by PEC) and soft source on E^{n+1}.  In the lossy
+ *       layer a1 and a3 become H' = da H - db S curl E and
+ *       E' = ca E + cb (1/eps)(S curl H - dP) with ca = da = (1-a)/(1+a),
+ *       cb = db = 1/(1+a), a = a_max sum over axes of (depth/L)^p.
  *   a4  four-level rate equations with field work W = beta Ebar (P^{n+1}-P^n)
  *       N3 += dtWp N0 - dt32 N3;  N2 += dt32 N3 - dt21 N2 + W
  *       N1 += dt21 N2 - dt10 N1 - W;  N0 += dt10 N1 - dtWp N0
@@ -40,7 +44,7 @@
 extern "C" {
 #endif
 
-enum { ORC_PEC = 0, ORC_MUR1 = 1 };
+enum { ORC_PEC = 0, ORC_MUR1 = 1, ORC_ABSORB = 2 };
 enum { ORC_INIT_GROUND = 0, ORC_INIT_PREPUMPED = 1 };
 
 /* field ids: E 0-2, H 3-5, P^n 6-8, P^{n-1} 9-11, N1 12-14, N2 15-17,
@@ -49,7 +53,7 @@ enum { ORC_NFIELDS = 24 };
 
 typedef struct orc_params {
     int32_t nx, ny, nz;
-    int32_t bc[3];          /* per axis: ORC_PEC or ORC_MUR1 */
+    int32_t bc[3];          /* per axis: ORC_PEC, ORC_MUR1 or ORC_ABSORB */
     int32_t round_f32;      /* 1: every coefficient rounded to binary32 */
     int32_t frozen_pop;     /* 1: populations held fixed (a4 skipped) */
     double dx;              /* m */
@@ -61,6 +65,9 @@ typedef struct orc_params {
     uint64_t seed;
     uint32_t realization;
     int32_t noise;          /* 1: spontaneous-emission source on */
+    int32_t absorb_cells;   /* depth L of the graded lossy layer on ORC_ABSORB faces */
+    int32_t absorb_order;   /* grading exponent p */
+    double absorb_rate;     /* a_max: loss per step sigma dt/(2 eps) at the wall */
 } orc_params;
 
 /* coefficient vector layout returned by orc_coefficients */

@@ -1,0 +1,1065 @@
+// Host runtime and C ABI of the Maxwell-Bloch FDTD library (see include/mbf.h).
+//
+// A handle owns one simulation's device state: 27 site arrays (E and H
+// double-buffered, P^n/P^{n-1}, N1..N3 per component), the material bytes and
+// table, the control block and the monitor buffers.  Steps are queued on the
+// handle's stream; chunks of steps are captured once into a hipGraph and
+// replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mbf.h"
+#include "mbf_kernels.hpp"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kHbar = 1.054571817e-34;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;
+
+struct Coef {
+    double dt, S, a, b, ck, cF, beta, dt32, dt21, dt10, dtWp, Na;
+    double wa, dwa, omp2;
+    double rates[4];  // dt32, dt21, dt10, dtWp before freezing
+};
+
+}  // namespace
+
+struct mbf_handle {
+    mbf_config cfg{};
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t sx = 0, sxy = 0, nsite = 0;
+    size_t esz = 4;
+    void* pool = nullptr;
+    void* arr[27] = {};       // E_a[3] E_b[3] H_a[3] H_b[3] P_a[3] P_b[3] N1[3] N2[3] N3[3]
+    uint8_t* mat = nullptr;
+    void* lut = nullptr;      // inv_eps[256], eps[256], mur[256] in the field type
+    uint8_t* lut_gain = nullptr;
+    mbf::Ctl* ctl = nullptr;
+    double* e_part = nullptr;
+    double* l_part = nullptr;
+    int n_part = 0;
+    double* hist = nullptr;
+    int64_t hist_cap = 0;
+    // probes
+    int n_probes = 0, n_freq = 0, decim = 1;
+    int32_t* d_probe_comp = nullptr;
+    int64_t* d_probe_off = nullptr;
+    void* d_ring = nullptr;
+    double* d_omega = nullptr;
+    double* d_spec = nullptr;
+    int64_t flushed = 0;
+    // source
+    int src_on = 0, src_comp = 0, src_i = 0, src_j = 0, src_k = 0;
+    double src_amp = 0, src_ws = 0, src_tp = 1, src_t0 = 0;
+    // loss box
+    int box_on = 0, box[6] = {};
+    int mur_tasks = 0, mur_a[mbf::kMaxMurTasks] = {}, mur_side[mbf::kMaxMurTasks] = {},
+        mur_c[mbf::kMaxMurTasks] = {};
+    Coef co{};
+    double Na_si = 0.0;
+    mbf_tuning tun{MBF_VARIANT_FUSED, 8, 0, 1};
+    void* prof = nullptr;     // lossy-layer profiles: [axis][integer, half][n_axis + 1]
+    int64_t prof_stride = 0;
+    bool has_layer = false;
+    int64_t gain_sites = 0;   // interior E-sites of gain cells
+    bool have_material = false, have_pump = false;
+    int64_t step = 0;
+    // graph of a chunk of steps
+    hipGraphExec_t gexec = nullptr;
+    int64_t gsteps = 0;
+    bool gdirty = true;
+};
+
+namespace {
+
+int fail(mbf_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((h), MBF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+template <typename T>
+double rnd(double v) {
+    return (double)(T)v;
+}
+
+// Coefficients of the scaled update (rounded once to the field type T).
+template <typename T>
+Coef make_coef(const mbf_config& c, double Na_si) {
+    Coef k{};
+    const double dt = c.courant * c.dx / (kC0 * std::sqrt(3.0));
+    const double S = kC0 * dt / c.dx;
+    const double wa = 2.0 * kPi * kC0 / c.lambda0;
+    const double dwa = 2.0 * kPi * kC0 * c.dlambda / (c.lambda0 * c.lambda0);
+    const double kappa = 6.0 * kPi * kEps0 * kC0 * kC0 * kC0 / (wa * wa * c.tau21);
+    const double omp2 = kappa * c.N_ref / kEps0;
+    const double D = 1.0 + 0.5 * dwa * dt;
+    const double beta = kEps0 * c.E_ref * c.E_ref / (kHbar * wa * c.N_ref);
+    const double ck = dt * dt * omp2 / D;
+    const double Na = Na_si / c.N_ref;
+    k.dt = dt;
+    k.S = rnd<T>(S);
+    k.a = rnd<T>((2.0 - wa * wa * dt * dt) / D);
+    k.b = rnd<T>(-(1.0 - 0.5 * dwa * dt) / D);
+    k.ck = rnd<T>(ck);
+    k.cF = c.noise ? rnd<T>(ck * Na * c.E_sp) : 0.0;
+    k.Na = rnd<T>(Na);
+    k.wa = wa;
+    k.dwa = dwa;
+    k.omp2 = omp2;
+    k.rates[0] = rnd<T>(dt / c.tau32);
+    k.rates[1] = rnd<T>(dt / c.tau21);
+    k.rates[2] = rnd<T>(dt / c.tau10);
+    k.rates[3] = rnd<T>(dt * c.Wp);
+    const bool frozen = (c.flags & MBF_FLAG_FROZEN_POP) != 0;
+    k.beta = frozen ? 0.0 : rnd<T>(beta);
+    k.dt32 = frozen ? 0.0 : k.rates[0];
+    k.dt21 = frozen ? 0.0 : k.rates[1];
+    k.dt10 = frozen ? 0.0 : k.rates[2];
+    k.dtWp = frozen ? 0.0 : k.rates[3];
+    return k;
+}
+
+template <typename T>
+T* A(mbf_handle* h, int q) {
+    return reinterpret_cast<T*>(h->arr[q]);
+}
+
+template <typename T>
+mbf::SimView<T> view(mbf_handle* h) {
+    mbf::SimView<T> v{};
+    for (int c = 0; c < 3; ++c) {
+        v.E[0][c] = A<T>(h, c);
+        v.E[1][c] = A<T>(h, 3 + c);
+        v.H[0][c] = A<T>(h, 6 + c);
+        v.H[1][c] = A<T>(h, 9 + c);
+        v.P[0][c] = A<T>(h, 12 + c);
+        v.P[1][c] = A<T>(h, 15 + c);
+        v.N[0][c] = A<T>(h, 18 + c);
+        v.N[1][c] = A<T>(h, 21 + c);
+        v.N[2][c] = A<T>(h, 24 + c);
+    }
+    const T* lut = reinterpret_cast<const T*>(h->lut);
+    v.mat = h->mat;
+    v.lut_inv_eps = lut;
+    v.lut_eps = lut + mbf::kMaxMat;
+    v.lut_mur = lut + 2 * mbf::kMaxMat;
+    v.lut_gain = h->lut_gain;
+    v.nx = h->cfg.nx;
+    v.ny = h->cfg.ny;
+    v.nz = h->cfg.nz;
+    v.sx = h->sx;
+    v.sxy = h->sxy;
+    const Coef& k = h->co;
+    v.S = (T)k.S; v.a = (T)k.a; v.b = (T)k.b; v.ck = (T)k.ck; v.cF = (T)k.cF;
+    v.beta = (T)k.beta; v.dt32 = (T)k.dt32; v.dt21 = (T)k.dt21; v.dt10 = (T)k.dt10;
+    v.dtWp = (T)k.dtWp; v.Na = (T)k.Na;
+    v.noise = h->cfg.noise && k.cF != 0.0;
+    v.frozen_pop = (h->cfg.flags & MBF_FLAG_FROZEN_POP) != 0;
+    v.seed_lo = (uint32_t)(h->cfg.seed & 0xFFFFFFFFull);
+    v.seed_hi = (uint32_t)(h->cfg.seed >> 32);
+    v.realization = h->cfg.realization;
+    v.src_on = h->src_on;
+    v.src_comp = h->src_comp;
+    v.src_i = h->src_i; v.src_j = h->src_j; v.src_k = h->src_k;
+    v.src_amp = h->src_amp; v.src_ws = h->src_ws; v.src_tp = h->src_tp; v.src_t0 = h->src_t0;
+    v.dt = k.dt;
+    v.box_on = h->box_on;
+    for (int q = 0; q < 6; ++q) v.box[q] = h->box[q];
+    v.n_mur = h->mur_tasks;
+    for (int q = 0; q < h->mur_tasks; ++q) {
+        v.mur_a[q] = h->mur_a[q];
+        v.mur_side[q] = h->mur_side[q];
+        v.mur_c[q] = h->mur_c[q];
+    }
+    for (int q = 0; q < 3; ++q) v.bc[q] = h->cfg.boundary[q];
+    v.has_layer = h->has_layer ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        for (int hf = 0; hf < 2; ++hf)
+            v.prof[a][hf] = reinterpret_cast<const T*>(h->prof) + (2 * a + hf) * h->prof_stride;
+    v.ctl = h->ctl;
+    v.e_part = h->e_part;
+    v.l_part = h->l_part;
+    v.n_part = h->n_part;
+    v.hist = h->hist;
+    v.hist_cap = h->hist_cap;
+    v.n_probes = h->n_probes;
+    v.n_freq = h->n_freq;
+    v.decim = h->decim;
+    v.probe_comp = h->d_probe_comp;
+    v.probe_off = h->d_probe_off;
+    v.ring = reinterpret_cast<T*>(h->d_ring);
+    v.omega = h->d_omega;
+    v.spec = h->d_spec;
+    return v;
+}
+
+dim3 grid_cells(const mbf_handle* h) {
+    return dim3((h->cfg.nx + mbf::kBlockX - 1) / mbf::kBlockX,
+                (h->cfg.ny + mbf::kBlockY - 1) / mbf::kBlockY, h->cfg.nz);
+}
+
+// Geometry of the fused kernel's work items for the handle's tuning.
+mbf::FusedGeom fused_geom(const mbf_handle* h) {
+    mbf::FusedGeom g{};
+    const int ty = h->tun.tile_y;
+    g.tiles_x = (h->cfg.nx + 63) / 64;
+    g.tiles_y = (h->cfg.ny + ty - 1) / ty;
+    int zseg = h->tun.zseg;
+    if (zseg <= 0) {
+        // enough workgroups to give every CU several, segments of >= 4 planes
+        const int cols = g.tiles_x * g.tiles_y;
+        const int segs = std::max(1, (2048 + cols - 1) / cols);
+        zseg = std::max(4, (h->cfg.nz + segs - 1) / segs);
+    }
+    zseg = std::min(zseg, h->cfg.nz);
+    g.zseg = zseg;
+    g.segs = (h->cfg.nz + zseg - 1) / zseg;
+    g.nblk = g.tiles_x * g.tiles_y * g.segs;
+    g.xcd_remap = h->tun.xcd_remap;
+    return g;
+}
+
+template <typename T>
+void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
+    const mbf::FusedGeom g = fused_geom(h);
+    v.n_part = g.nblk;
+    const dim3 grid((unsigned)g.nblk);
+    switch (h->tun.tile_y) {
+        case 2: hipLaunchKernelGGL((mbf::k_step_fused<T, 2>), grid, dim3(64, 2), 0, h->stream, v, g); break;
+        case 4: hipLaunchKernelGGL((mbf::k_step_fused<T, 4>), grid, dim3(64, 4), 0, h->stream, v, g); break;
+        case 16: hipLaunchKernelGGL((mbf::k_step_fused<T, 16>), grid, dim3(64, 16), 0, h->stream, v, g); break;
+        default: hipLaunchKernelGGL((mbf::k_step_fused<T, 8>), grid, dim3(64, 8), 0, h->stream, v, g); break;
+    }
+}
+
+// Queue one step.  When ev0/ev1 are given they bracket the step's field
+// kernels (the dominant cost) on the handle's stream.
+template <typename T>
+int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    mbf::SimView<T> v = view<T>(h);
+    if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
+    if (h->tun.variant == MBF_VARIANT_FUSED) {
+        launch_fused<T>(h, v);
+    } else {
+        const dim3 g = grid_cells(h);
+        const dim3 b(mbf::kBlockX, mbf::kBlockY, 1);
+        v.n_part = (int)(g.x * g.y * g.z);
+        hipLaunchKernelGGL(mbf::k_curl_h<T>, g, b, 0, h->stream, v);
+        hipLaunchKernelGGL(mbf::k_curl_e<T>, g, b, 0, h->stream, v);
+    }
+    if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
+    if (h->mur_tasks > 0) {
+        const int nmax = std::max({h->cfg.nx, h->cfg.ny, h->cfg.nz}) + 1;
+        const int64_t sites = (int64_t)nmax * nmax;
+        dim3 gm((unsigned)((sites + 255) / 256), (unsigned)h->mur_tasks, 1);
+        hipLaunchKernelGGL(mbf::k_mur<T>, gm, dim3(256), 0, h->stream, v);
+    }
+    hipLaunchKernelGGL(mbf::k_end_step<T>, dim3(1), dim3(256), 0, h->stream, v);
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
+}
+
+template <typename T>
+int launch_dft(mbf_handle* h, int count) {
+    if (h->n_probes == 0 || h->n_freq == 0 || count <= 0) return MBF_OK;
+    mbf::SimView<T> v = view<T>(h);
+    const int64_t tot = (int64_t)h->n_probes * h->n_freq;
+    hipLaunchKernelGGL(mbf::k_dft<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       h->stream, v, count);
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
+}
+
+int dispatch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    return h->cfg.precision == MBF_FP64 ? launch_step<double>(h, ev0, ev1)
+                                        : launch_step<float>(h, ev0, ev1);
+}
+
+int dispatch_dft(mbf_handle* h, int count) {
+    return h->cfg.precision == MBF_FP64 ? launch_dft<double>(h, count)
+                                        : launch_dft<float>(h, count);
+}
+
+void drop_graph(mbf_handle* h) {
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gsteps = 0;
+    h->gdirty = true;
+}
+
+// Capture `n` steps (plus the DFT fold when probes are set and n == decim).
+int build_graph(mbf_handle* h, int64_t n) {
+    drop_graph(h);
+    hipGraph_t g = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    int rc = MBF_OK;
+    for (int64_t s = 0; s < n && rc == MBF_OK; ++s) rc = dispatch_step(h);
+    if (rc == MBF_OK && h->n_probes > 0) rc = dispatch_dft(h, (int)n);
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != MBF_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(h, MBF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return fail(h, MBF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    h->gsteps = n;
+    h->gdirty = false;
+    return MBF_OK;
+}
+
+void free_probes(mbf_handle* h) {
+    hipFree(h->d_probe_comp); hipFree(h->d_probe_off); hipFree(h->d_ring);
+    hipFree(h->d_omega); hipFree(h->d_spec);
+    h->d_probe_comp = nullptr; h->d_probe_off = nullptr; h->d_ring = nullptr;
+    h->d_omega = nullptr; h->d_spec = nullptr;
+    h->n_probes = h->n_freq = 0;
+    h->decim = 1;
+}
+
+int field_array(mbf_handle* h, int id, int64_t step, bool write, void** out) {
+    const int par = (int)(step & 1);
+    if (id < 0 || id >= MBF_NFIELDS) return fail(h, MBF_EINVAL, "field id out of range");
+    int q;
+    if (id < 3) q = (par ? 3 : 0) + id;                       // E^n
+    else if (id < 6) q = (par ? 9 : 6) + (id - 3);           // H^{n-1/2}
+    else if (id < 9) q = (par ? 15 : 12) + (id - 6);         // P^n
+    else if (id < 12) q = (par ? 12 : 15) + (id - 9);        // P^{n-1}
+    else q = 18 + (id - 12);                                  // N1, N2, N3
+    (void)write;
+    *out = h->arr[q];
+    return MBF_OK;
+}
+
+uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t hsh = 1469598103934665603ull) {
+    for (size_t q = 0; q < n; ++q) {
+        hsh ^= p[q];
+        hsh *= 1099511628211ull;
+    }
+    return hsh;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char* mbf_version(void) { return "mbf 0.1 (gfx950)"; }
+
+const char* mbf_global_error(void) { return g_err.c_str(); }
+
+const char* mbf_last_error(const mbf_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int mbf_config_default(mbf_config* c, int nx, int ny, int nz) {
+    if (!c || nx < 2 || ny < 2 || nz < 2) return fail(nullptr, MBF_EINVAL, "bad sizes");
+    std::memset(c, 0, sizeof(*c));
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    c->boundary[0] = c->boundary[1] = c->boundary[2] = MBF_PEC;
+    c->precision = MBF_FP32;
+    c->noise = 1;
+    c->dx = 20e-9;
+    c->courant = 0.99;
+    c->lambda0 = 590e-9;
+    c->dlambda = 230e-9;
+    c->tau32 = 100e-15;
+    c->tau21 = 1e-9;
+    c->tau10 = 100e-15;
+    c->Wp = 1e12;
+    c->N_ref = 1e24;
+    c->E_ref = 1e8;
+    c->E_sp = 1e-6;
+    c->absorb_cells = 8;
+    c->absorb_order = 2;
+    c->absorb_rate = 0.25;
+    return MBF_OK;
+}
+
+int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
+    if (!cfg || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    *out = nullptr;
+    const mbf_config& c = *cfg;
+    if (c.nx < 2 || c.ny < 2 || c.nz < 2) return fail(nullptr, MBF_EINVAL, "grid sizes must be >= 2");
+    const double ext = (double)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    if (ext > 4.0e9) return fail(nullptr, MBF_EINVAL, "grid too large (cell index must fit 32 bits)");
+    if (!(std::isfinite(c.courant) && c.courant > 0.0 && c.courant <= 1.0))
+        return fail(nullptr, MBF_ECFL, "Courant number must lie in (0, 1]");
+    bool any_layer = false;
+    for (int a = 0; a < 3; ++a) {
+        if (c.boundary[a] != MBF_PEC && c.boundary[a] != MBF_MUR1 && c.boundary[a] != MBF_ABSORB)
+            return fail(nullptr, MBF_EINVAL, "boundary must be MBF_PEC, MBF_MUR1 or MBF_ABSORB");
+        any_layer = any_layer || c.boundary[a] == MBF_ABSORB;
+    }
+    if (any_layer && (c.absorb_cells < 1 || c.absorb_order < 0 || !std::isfinite(c.absorb_rate) ||
+                      c.absorb_rate < 0.0))
+        return fail(nullptr, MBF_EINVAL, "absorbing layer needs cells >= 1, order >= 0, rate >= 0");
+    if (c.precision != MBF_FP32 && c.precision != MBF_FP64)
+        return fail(nullptr, MBF_EINVAL, "precision must be MBF_FP32 or MBF_FP64");
+    if (!finite_pos(c.dx) || !finite_pos(c.lambda0) || !finite_pos(c.dlambda) ||
+        !finite_pos(c.tau21) || !finite_pos(c.N_ref) || !finite_pos(c.E_ref) ||
+        !(c.tau32 > 0.0) || !(c.tau10 > 0.0) || !(std::isfinite(c.Wp) && c.Wp >= 0.0) ||
+        !(std::isfinite(c.E_sp) && c.E_sp >= 0.0))
+        return fail(nullptr, MBF_EINVAL, "physical parameters must be finite and positive");
+    if (c.energy_history < 0) return fail(nullptr, MBF_EINVAL, "negative energy_history");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return fail(nullptr, MBF_ENODEV, "no HIP device");
+    mbf_handle* h = new mbf_handle();
+    h->cfg = c;
+    hipGetDevice(&h->dev);
+    h->esz = c.precision == MBF_FP64 ? 8 : 4;
+    h->sx = c.nx + 1;
+    h->sxy = (int64_t)(c.nx + 1) * (c.ny + 1);
+    h->nsite = h->sxy * (c.nz + 1);
+    auto bail = [&](int code, const std::string& m) {
+        g_err = m;
+        mbf_destroy(h);
+        return code;
+    };
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(MBF_EHIP, "hipStreamCreate failed");
+        h->own_stream = true;
+    }
+    const size_t bytes = (size_t)h->nsite * h->esz;
+    if (hipMalloc(&h->pool, bytes * 27) != hipSuccess) return bail(MBF_ENOMEM, "device allocation of the fields failed");
+    for (int q = 0; q < 27; ++q) h->arr[q] = (char*)h->pool + (size_t)q * bytes;
+    if (hipMalloc(&h->mat, (size_t)h->nsite) != hipSuccess ||
+        hipMalloc(&h->lut, 3 * mbf::kMaxMat * h->esz) != hipSuccess ||
+        hipMalloc(&h->lut_gain, mbf::kMaxMat) != hipSuccess ||
+        hipMalloc(&h->ctl, sizeof(mbf::Ctl)) != hipSuccess)
+        return bail(MBF_ENOMEM, "device allocation failed");
+    // enough partial-sum slots for every kernel variant (one per workgroup)
+    h->n_part = ((c.nx + 63) / 64) * c.ny * c.nz;
+    if (hipMalloc(&h->e_part, sizeof(double) * h->n_part) != hipSuccess ||
+        hipMalloc(&h->l_part, sizeof(double) * h->n_part) != hipSuccess)
+        return bail(MBF_ENOMEM, "device allocation failed");
+    h->hist_cap = c.energy_history;
+    if (h->hist_cap > 0 && hipMalloc(&h->hist, sizeof(double) * h->hist_cap) != hipSuccess)
+        return bail(MBF_ENOMEM, "energy history allocation failed");
+    if (hipMemsetAsync(h->pool, 0, bytes * 27, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->mat, 0, (size_t)h->nsite, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->lut, 0, 3 * mbf::kMaxMat * h->esz, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->lut_gain, 0, mbf::kMaxMat, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->ctl, 0, sizeof(mbf::Ctl), h->stream) != hipSuccess ||
+        hipMemsetAsync(h->l_part, 0, sizeof(double) * h->n_part, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return bail(MBF_EHIP, "device initialisation failed");
+    // Mur tasks: (axis a, side, tangential component c)
+    for (int a = 0; a < 3; ++a) {
+        if (c.boundary[a] != MBF_MUR1) continue;
+        for (int side = 0; side < 2; ++side)
+            for (int cc = 0; cc < 3; ++cc) {
+                if (cc == a) continue;
+                h->mur_a[h->mur_tasks] = a;
+                h->mur_side[h->mur_tasks] = side;
+                h->mur_c[h->mur_tasks] = cc;
+                ++h->mur_tasks;
+            }
+    }
+    // lossy-layer profiles at integer and half-integer positions of every axis
+    const int nmax = std::max({c.nx, c.ny, c.nz});
+    h->prof_stride = nmax + 1;
+    std::vector<double> prof((size_t)6 * h->prof_stride, 0.0);
+    for (int a = 0; a < 3; ++a) {
+        if (c.boundary[a] != MBF_ABSORB || c.absorb_rate == 0.0) continue;
+        const int na = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+        const double L = (double)c.absorb_cells;
+        for (int hf = 0; hf < 2; ++hf)
+            for (int q = 0; q <= na; ++q) {
+                const double x = (double)q + (hf ? 0.5 : 0.0);
+                double val = 0.0;
+                if (x < L) val += std::pow((L - x) / L, (double)c.absorb_order);
+                if (x > na - L) val += std::pow((x - (na - L)) / L, (double)c.absorb_order);
+                prof[(size_t)(2 * a + hf) * h->prof_stride + q] = c.absorb_rate * val;
+                h->has_layer = h->has_layer || val > 0.0;
+            }
+    }
+    if (hipMalloc(&h->prof, prof.size() * h->esz) != hipSuccess) return bail(MBF_ENOMEM, "profile allocation failed");
+    {
+        std::vector<uint8_t> buf(prof.size() * h->esz);
+        for (size_t q = 0; q < prof.size(); ++q) {
+            if (h->esz == 8) reinterpret_cast<double*>(buf.data())[q] = prof[q];
+            else reinterpret_cast<float*>(buf.data())[q] = (float)prof[q];
+        }
+        if (hipMemcpy(h->prof, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(MBF_EHIP, "profile upload failed");
+    }
+    h->co = c.precision == MBF_FP64 ? make_coef<double>(c, 0.0) : make_coef<float>(c, 0.0);
+    *out = h;
+    return MBF_OK;
+}
+
+void mbf_destroy(mbf_handle* h) {
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    free_probes(h);
+    hipFree(h->pool); hipFree(h->mat); hipFree(h->lut); hipFree(h->lut_gain);
+    hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int mbf_coefficients(const mbf_handle* h, double* out, int n) {
+    if (!h || !out || n < MBF_C_COUNT) return fail(nullptr, MBF_EINVAL, "bad arguments");
+    const Coef& k = h->co;
+    const double v[MBF_C_COUNT] = {k.dt, k.S, k.a, k.b, k.ck, k.cF, k.beta,
+                                   k.dt32, k.dt21, k.dt10, k.dtWp, k.Na};
+    std::memcpy(out, v, sizeof(v));
+    return MBF_OK;
+}
+
+int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int mem_kind) {
+    if (!h || !eps_r || !gain) return fail(h, MBF_EINVAL, "null argument");
+    const mbf_config& c = h->cfg;
+    const size_t ncell = (size_t)c.nx * c.ny * c.nz;
+    std::vector<float> eps(ncell);
+    std::vector<uint8_t> g(ncell);
+    if (mem_kind == MBF_MEM_DEVICE) {
+        HIPCHK(h, hipMemcpy(eps.data(), eps_r, ncell * sizeof(float), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(g.data(), gain, ncell, hipMemcpyDeviceToHost));
+    } else if (mem_kind == MBF_MEM_HOST) {
+        std::memcpy(eps.data(), eps_r, ncell * sizeof(float));
+        std::memcpy(g.data(), gain, ncell);
+    } else {
+        return fail(h, MBF_EINVAL, "mem_kind must be MBF_MEM_HOST or MBF_MEM_DEVICE");
+    }
+    std::map<std::pair<uint32_t, uint8_t>, int> ids;
+    std::vector<uint8_t> cell_id(ncell);
+    std::vector<float> lut_eps;
+    std::vector<uint8_t> lut_g;
+    for (size_t q = 0; q < ncell; ++q) {
+        const float e = eps[q];
+        if (!(std::isfinite(e) && e > 0.0f)) return fail(h, MBF_EINVAL, "eps_r must be finite and > 0");
+        uint32_t bits;
+        std::memcpy(&bits, &e, 4);
+        const auto key = std::make_pair(bits, (uint8_t)(g[q] ? 1 : 0));
+        auto it = ids.find(key);
+        int id;
+        if (it == ids.end()) {
+            id = (int)lut_eps.size();
+            if (id >= mbf::kMaxMat - 1) return fail(h, MBF_EINVAL, "more than 255 distinct (eps_r, gain) pairs");
+            ids.emplace(key, id);
+            lut_eps.push_back(e);
+            lut_g.push_back(key.second);
+        } else {
+            id = it->second;
+        }
+        cell_id[q] = (uint8_t)id;
+    }
+    // site bytes on the extended range: the cell (i, j, k) clamped to n-1
+    std::vector<uint8_t> site((size_t)h->nsite);
+    for (int k = 0; k <= c.nz; ++k)
+        for (int j = 0; j <= c.ny; ++j)
+            for (int i = 0; i <= c.nx; ++i) {
+                const int ci = std::min(i, c.nx - 1), cj = std::min(j, c.ny - 1), ck = std::min(k, c.nz - 1);
+                site[(size_t)i + h->sx * j + h->sxy * k] = cell_id[(size_t)ci + (size_t)c.nx * (cj + (size_t)c.ny * ck)];
+            }
+    int64_t gsites = 0;
+    for (int k = 0; k < c.nz; ++k)
+        for (int j = 0; j < c.ny; ++j)
+            for (int i = 0; i < c.nx; ++i) {
+                if (!lut_g[cell_id[(size_t)i + (size_t)c.nx * (j + (size_t)c.ny * k)]]) continue;
+                gsites += (j >= 1 && k >= 1) + (i >= 1 && k >= 1) + (i >= 1 && j >= 1);
+            }
+    const double Sx = kC0 * h->co.dt / c.dx;
+    std::vector<double> inv(mbf::kMaxMat, 1.0), ep(mbf::kMaxMat, 1.0), mur(mbf::kMaxMat, 0.0);
+    for (size_t q = 0; q < lut_eps.size(); ++q) {
+        const double e = (double)lut_eps[q];
+        inv[q] = 1.0 / e;
+        ep[q] = e;
+        const double sp = Sx / std::sqrt(e);
+        mur[q] = (sp - 1.0) / (sp + 1.0);
+    }
+    std::vector<uint8_t> lutbuf(3 * mbf::kMaxMat * h->esz);
+    for (int q = 0; q < mbf::kMaxMat; ++q) {
+        if (h->esz == 8) {
+            double* d = reinterpret_cast<double*>(lutbuf.data());
+            d[q] = inv[q]; d[mbf::kMaxMat + q] = ep[q]; d[2 * mbf::kMaxMat + q] = mur[q];
+        } else {
+            float* d = reinterpret_cast<float*>(lutbuf.data());
+            d[q] = (float)inv[q]; d[mbf::kMaxMat + q] = (float)ep[q]; d[2 * mbf::kMaxMat + q] = (float)mur[q];
+        }
+    }
+    std::vector<uint8_t> gl(mbf::kMaxMat, 0);
+    for (size_t q = 0; q < lut_g.size(); ++q) gl[q] = lut_g[q];
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(h->mat, site.data(), site.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->lut, lutbuf.data(), lutbuf.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->lut_gain, gl.data(), gl.size(), hipMemcpyHostToDevice));
+    h->gain_sites = gsites;
+    h->have_material = true;
+    h->have_pump = false;   // the populations depend on the gain map
+    return MBF_OK;
+}
+
+static int reset_monitors(mbf_handle* h) {
+    HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(mbf::Ctl), h->stream));
+    if (h->d_spec)
+        HIPCHK(h, hipMemsetAsync(h->d_spec, 0, sizeof(double) * 2 * h->n_probes * h->n_freq, h->stream));
+    h->flushed = 0;
+    h->step = 0;
+    return MBF_OK;
+}
+
+int mbf_set_pump(mbf_handle* h, double Na, int init) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    if (!h->have_material) return fail(h, MBF_ESTATE, "set the material first");
+    if (!(std::isfinite(Na) && Na >= 0.0)) return fail(h, MBF_EINVAL, "N_a must be finite and >= 0");
+    if (init != MBF_INIT_GROUND && init != MBF_INIT_PREPUMPED) return fail(h, MBF_EINVAL, "bad init");
+    const mbf_config& c = h->cfg;
+    h->co = c.precision == MBF_FP64 ? make_coef<double>(c, Na) : make_coef<float>(c, Na);
+    h->Na_si = Na;
+    double N1 = 0, N2 = 0, N3 = 0;
+    if (init == MBF_INIT_PREPUMPED) {
+        const double d32 = h->co.rates[0], d21 = h->co.rates[1], d10 = h->co.rates[2], dwp = h->co.rates[3];
+        const double n0 = h->co.Na / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
+        N3 = dwp * n0 / d32;
+        N2 = dwp * n0 / d21;
+        N1 = dwp * n0 / d10;
+    }
+    const size_t bytes = (size_t)h->nsite * h->esz;
+    HIPCHK(h, hipMemsetAsync(h->pool, 0, bytes * 18, h->stream));   // E, H, P (both buffers)
+    const int64_t tot = h->nsite;
+    const dim3 g((unsigned)((tot + 255) / 256));
+    if (c.precision == MBF_FP64) {
+        hipLaunchKernelGGL(mbf::k_init_pop<double>, g, dim3(256), 0, h->stream, view<double>(h), N1, N2, N3);
+    } else {
+        hipLaunchKernelGGL(mbf::k_init_pop<float>, g, dim3(256), 0, h->stream, view<float>(h),
+                           (float)N1, (float)N2, (float)N3);
+    }
+    HIPCHK(h, hipGetLastError());
+    int rc = reset_monitors(h);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->have_pump = true;
+    drop_graph(h);
+    return MBF_OK;
+}
+
+int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double amp, double lambda_s,
+                         double tau_p, double t0) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    const mbf_config& c = h->cfg;
+    if (amp == 0.0) {
+        h->src_on = 0;
+        drop_graph(h);
+        return MBF_OK;
+    }
+    if (comp < 0 || comp > 2) return fail(h, MBF_EINVAL, "component must be 0, 1 or 2");
+    const int idx[3] = {i, j, k};
+    const int nd[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = (a == comp) ? 0 : 1;
+        if (idx[a] < lo || idx[a] >= nd[a]) return fail(h, MBF_EINVAL, "source must be an interior E-site");
+    }
+    if (!std::isfinite(amp) || !finite_pos(lambda_s) || !finite_pos(tau_p) || !std::isfinite(t0))
+        return fail(h, MBF_EINVAL, "bad source parameters");
+    h->src_on = 1;
+    h->src_comp = comp; h->src_i = i; h->src_j = j; h->src_k = k;
+    h->src_amp = amp;
+    h->src_ws = 2.0 * kPi * kC0 / lambda_s;
+    h->src_tp = tau_p;
+    h->src_t0 = t0;
+    drop_graph(h);
+    return MBF_OK;
+}
+
+int mbf_set_probes(mbf_handle* h, const int32_t* sites, int n_probes, const double* omega,
+                   int n_freq, int decim) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    if (n_probes < 0 || n_freq < 0 || (n_probes > 0 && (!sites || !omega)) || decim < 1 || decim > 1024)
+        return fail(h, MBF_EINVAL, "bad probe arguments");
+    const mbf_config& c = h->cfg;
+    std::vector<int32_t> comp(n_probes);
+    std::vector<int64_t> off(n_probes);
+    for (int p = 0; p < n_probes; ++p) {
+        const int32_t* r = sites + 4 * p;
+        if (r[0] < 0 || r[0] > 2 || r[1] < 0 || r[1] > c.nx || r[2] < 0 || r[2] > c.ny || r[3] < 0 || r[3] > c.nz)
+            return fail(h, MBF_EINVAL, "probe site out of range");
+        comp[p] = r[0];
+        off[p] = (int64_t)r[1] + h->sx * r[2] + h->sxy * r[3];
+    }
+    for (int f = 0; f < n_freq; ++f)
+        if (!std::isfinite(omega[f])) return fail(h, MBF_EINVAL, "non-finite frequency");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    free_probes(h);
+    if (n_probes == 0) return MBF_OK;
+    h->n_probes = n_probes;
+    h->n_freq = n_freq;
+    h->decim = decim;
+    const size_t nspec = sizeof(double) * 2 * (size_t)n_probes * std::max(n_freq, 1);
+    if (hipMalloc(&h->d_probe_comp, sizeof(int32_t) * n_probes) != hipSuccess ||
+        hipMalloc(&h->d_probe_off, sizeof(int64_t) * n_probes) != hipSuccess ||
+        hipMalloc(&h->d_ring, h->esz * (size_t)n_probes * decim) != hipSuccess ||
+        hipMalloc(&h->d_omega, sizeof(double) * std::max(n_freq, 1)) != hipSuccess ||
+        hipMalloc(&h->d_spec, nspec) != hipSuccess) {
+        free_probes(h);
+        return fail(h, MBF_ENOMEM, "probe allocation failed");
+    }
+    HIPCHK(h, hipMemcpy(h->d_probe_comp, comp.data(), sizeof(int32_t) * n_probes, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->d_probe_off, off.data(), sizeof(int64_t) * n_probes, hipMemcpyHostToDevice));
+    if (n_freq > 0) HIPCHK(h, hipMemcpy(h->d_omega, omega, sizeof(double) * n_freq, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemset(h->d_spec, 0, nspec));
+    HIPCHK(h, hipMemset(h->d_ring, 0, h->esz * (size_t)n_probes * decim));
+    h->flushed = h->step;
+    return MBF_OK;
+}
+
+int mbf_set_loss_box(mbf_handle* h, int i0, int j0, int k0, int i1, int j1, int k1) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    const mbf_config& c = h->cfg;
+    if (i0 < 0 || j0 < 0 || k0 < 0 || i1 > c.nx || j1 > c.ny || k1 > c.nz || i0 >= i1 || j0 >= j1 || k0 >= k1)
+        return fail(h, MBF_EINVAL, "loss box must be a non-empty sub-box of the cells");
+    h->box_on = 1;
+    h->box[0] = i0; h->box[1] = j0; h->box[2] = k0;
+    h->box[3] = i1; h->box[4] = j1; h->box[5] = k1;
+    drop_graph(h);
+    return MBF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Advance n steps.  Without timing, aligned chunks run as a replayed graph;
+// with timing every step is launched directly with an event pair around its
+// field kernels.  The probe ring is folded into the spectrum every `decim`
+// samples.
+int run_steps(mbf_handle* h, int64_t nsteps, std::vector<hipEvent_t>* ev) {
+    if (nsteps < 0) return fail(h, MBF_EINVAL, "negative step count");
+    if (!h->have_material || !h->have_pump) return fail(h, MBF_ESTATE, "set material and pump before stepping");
+    if (h->step + nsteps >= (int64_t)1 << 32) return fail(h, MBF_EINVAL, "step index would exceed 2^32");
+    const int64_t chunk = h->n_probes > 0 ? h->decim : 32;
+    int64_t left = nsteps;
+    size_t e = 0;
+    while (left > 0) {
+        const int64_t pending = h->step - h->flushed;
+        if (!ev && pending == 0 && left >= chunk) {
+            if (h->gdirty || h->gsteps != chunk) {
+                int rc = build_graph(h, chunk);
+                if (rc) return rc;
+            }
+            HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+            h->step += chunk;
+            h->flushed = h->step;
+            left -= chunk;
+            continue;
+        }
+        int rc = ev ? dispatch_step(h, (*ev)[e], (*ev)[e + 1]) : dispatch_step(h);
+        if (rc) return rc;
+        e += 2;
+        h->step += 1;
+        left -= 1;
+        if (h->n_probes == 0) {
+            h->flushed = h->step;
+        } else if (h->step - h->flushed == h->decim) {
+            rc = dispatch_dft(h, h->decim);
+            if (rc) return rc;
+            h->flushed = h->step;
+        }
+    }
+    return MBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbf_step(mbf_handle* h, int64_t nsteps) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    return run_steps(h, nsteps, nullptr);
+}
+
+int mbf_step_timed(mbf_handle* h, int64_t nsteps, double* kernel_ms, int64_t* launches) {
+    if (!h || !kernel_ms || !launches) return fail(h, MBF_EINVAL, "null argument");
+    if (nsteps < 0 || nsteps > (1 << 20)) return fail(h, MBF_EINVAL, "step count out of range");
+    std::vector<hipEvent_t> ev((size_t)(2 * nsteps), nullptr);
+    for (auto& x : ev)
+        if (hipEventCreate(&x) != hipSuccess) {
+            for (auto& y : ev) if (y) hipEventDestroy(y);
+            return fail(h, MBF_EHIP, "hipEventCreate failed");
+        }
+    int rc = run_steps(h, nsteps, &ev);
+    double tot = 0.0;
+    if (rc == MBF_OK) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(h, MBF_EHIP, "synchronise failed");
+        for (int64_t q = 0; rc == MBF_OK && q < nsteps; ++q) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess)
+                rc = fail(h, MBF_EHIP, "hipEventElapsedTime failed");
+            tot += ms;
+        }
+    }
+    for (auto& x : ev) hipEventDestroy(x);
+    *kernel_ms = tot;
+    *launches = nsteps;
+    return rc;
+}
+
+int mbf_step_bytes(const mbf_handle* h, double* bytes) {
+    if (!h || !bytes) return fail(nullptr, MBF_EINVAL, "null argument");
+    const double cells = (double)h->cfg.nx * h->cfg.ny * h->cfg.nz;
+    const double v = (double)h->esz;
+    *bytes = cells * (12.0 * v + 1.0) + (double)h->gain_sites * 9.0 * v;
+    return MBF_OK;
+}
+
+int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
+    if (!h || !t) return fail(h, MBF_EINVAL, "null argument");
+    if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS)
+        return fail(h, MBF_EINVAL, "unknown variant");
+    if (t->tile_y != 2 && t->tile_y != 4 && t->tile_y != 8 && t->tile_y != 16)
+        return fail(h, MBF_EINVAL, "tile_y must be 2, 4, 8 or 16");
+    if (t->zseg < 0) return fail(h, MBF_EINVAL, "zseg must be >= 0");
+    h->tun = *t;
+    h->tun.xcd_remap = t->xcd_remap ? 1 : 0;
+    drop_graph(h);
+    return MBF_OK;
+}
+
+int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t) {
+    if (!h || !t) return fail(nullptr, MBF_EINVAL, "null argument");
+    *t = h->tun;
+    if (t->zseg == 0) t->zseg = fused_geom(h).zseg;
+    return MBF_OK;
+}
+
+int mbf_sync(mbf_handle* h) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return MBF_OK;
+}
+
+int mbf_step_index(const mbf_handle* h, int64_t* out) {
+    if (!h || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    *out = h->step;
+    return MBF_OK;
+}
+
+int mbf_read_energy(mbf_handle* h, double* W_now, double* W_int) {
+    if (!h || !W_now || !W_int) return fail(h, MBF_EINVAL, "null argument");
+    mbf::Ctl c{};
+    HIPCHK(h, hipMemcpyAsync(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *W_now = c.W_now;
+    *W_int = c.W_int;
+    if (c.nonfinite) return fail(h, MBF_ENONFINITE, "a step produced a non-finite energy");
+    return MBF_OK;
+}
+
+int mbf_read_energy_history(mbf_handle* h, double* out, int64_t cap, int64_t* count) {
+    if (!h || !count || cap < 0 || (cap > 0 && !out)) return fail(h, MBF_EINVAL, "bad arguments");
+    const int64_t n = std::min(h->step, h->hist_cap);
+    *count = n;
+    const int64_t m = std::min(n, cap);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (m > 0) HIPCHK(h, hipMemcpy(out, h->hist, sizeof(double) * m, hipMemcpyDeviceToHost));
+    return MBF_OK;
+}
+
+int mbf_read_spectrum(mbf_handle* h, double* re_im) {
+    if (!h || !re_im) return fail(h, MBF_EINVAL, "null argument");
+    if (h->n_probes == 0) return fail(h, MBF_ESTATE, "no probes set");
+    const int64_t pending = h->step - h->flushed;
+    if (pending > 0) {
+        int rc = dispatch_dft(h, (int)pending);
+        if (rc) return rc;
+        h->flushed = h->step;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(re_im, h->d_spec, sizeof(double) * 2 * h->n_probes * h->n_freq, hipMemcpyDeviceToHost));
+    return MBF_OK;
+}
+
+int mbf_read_loss(mbf_handle* h, double* out) {
+    if (!h || !out) return fail(h, MBF_EINVAL, "null argument");
+    mbf::Ctl c{};
+    HIPCHK(h, hipMemcpyAsync(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *out = c.loss;
+    return MBF_OK;
+}
+
+int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind) {
+    if (!h || !dst) return fail(h, MBF_EINVAL, "null argument");
+    void* src = nullptr;
+    int rc = field_array(h, field_id, h->step, false, &src);
+    if (rc) return rc;
+    const size_t bytes = (size_t)h->nsite * h->esz;
+    if (mem_kind == MBF_MEM_HOST) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    } else if (mem_kind == MBF_MEM_DEVICE) {
+        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        return fail(h, MBF_EINVAL, "bad mem_kind");
+    }
+    return MBF_OK;
+}
+
+int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind) {
+    if (!h || !src) return fail(h, MBF_EINVAL, "null argument");
+    void* dst = nullptr;
+    int rc = field_array(h, field_id, h->step, true, &dst);
+    if (rc) return rc;
+    // E and H are written into both buffers: sites no step ever updates (PEC
+    // walls) then keep the written value whichever buffer is current
+    void* dst2 = nullptr;
+    if (field_id < 6) field_array(h, field_id, h->step + 1, true, &dst2);
+    const size_t bytes = (size_t)h->nsite * h->esz;
+    if (mem_kind == MBF_MEM_HOST) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+        if (dst2) HIPCHK(h, hipMemcpy(dst2, src, bytes, hipMemcpyHostToDevice));
+    } else if (mem_kind == MBF_MEM_DEVICE) {
+        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+        if (dst2) HIPCHK(h, hipMemcpyAsync(dst2, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        return fail(h, MBF_EINVAL, "bad mem_kind");
+    }
+    return MBF_OK;
+}
+
+// ------------------------------------------------------------ checkpoints
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int32_t nx, ny, nz, precision;
+    int64_t step;
+    int32_t n_probes, n_freq, decim, pad;
+    int64_t flushed;
+    double Na_si;
+    mbf::Ctl ctl;
+};
+constexpr uint64_t kMagic = 0x3146424D5F54534Bull;
+}  // namespace
+
+int mbf_state_size(const mbf_handle* h, size_t* out) {
+    if (!h || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    *out = sizeof(StateHeader) + (size_t)MBF_NFIELDS * h->nsite * h->esz +
+           sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq + h->esz * (size_t)h->n_probes * h->decim +
+           sizeof(uint64_t);
+    return MBF_OK;
+}
+
+int mbf_save_state(mbf_handle* h, void* buf, size_t n) {
+    size_t need = 0;
+    if (!h || !buf) return fail(h, MBF_EINVAL, "null argument");
+    mbf_state_size(h, &need);
+    if (n < need) return fail(h, MBF_EINVAL, "state buffer too small");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    uint8_t* p = (uint8_t*)buf;
+    StateHeader hd{};
+    hd.magic = kMagic;
+    hd.nx = h->cfg.nx; hd.ny = h->cfg.ny; hd.nz = h->cfg.nz; hd.precision = h->cfg.precision;
+    hd.step = h->step;
+    hd.n_probes = h->n_probes; hd.n_freq = h->n_freq; hd.decim = h->decim;
+    hd.flushed = h->flushed;
+    hd.Na_si = h->Na_si;
+    HIPCHK(h, hipMemcpy(&hd.ctl, h->ctl, sizeof(mbf::Ctl), hipMemcpyDeviceToHost));
+    std::memcpy(p, &hd, sizeof(hd));
+    size_t off = sizeof(hd);
+    const size_t fb = (size_t)h->nsite * h->esz;
+    for (int id = 0; id < MBF_NFIELDS; ++id) {
+        void* src = nullptr;
+        field_array(h, id, h->step, false, &src);
+        HIPCHK(h, hipMemcpy(p + off, src, fb, hipMemcpyDeviceToHost));
+        off += fb;
+    }
+    if (h->n_probes > 0) {
+        const size_t sb = sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq;
+        HIPCHK(h, hipMemcpy(p + off, h->d_spec, sb, hipMemcpyDeviceToHost));
+        off += sb;
+        const size_t rb = h->esz * (size_t)h->n_probes * h->decim;
+        HIPCHK(h, hipMemcpy(p + off, h->d_ring, rb, hipMemcpyDeviceToHost));
+        off += rb;
+    }
+    const uint64_t cs = fnv1a(p, off);
+    std::memcpy(p + off, &cs, sizeof(cs));
+    return MBF_OK;
+}
+
+int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
+    size_t need = 0;
+    if (!h || !buf) return fail(h, MBF_EINVAL, "null argument");
+    mbf_state_size(h, &need);
+    if (n < need) return fail(h, MBF_EINVAL, "state buffer too small");
+    const uint8_t* p = (const uint8_t*)buf;
+    StateHeader hd;
+    std::memcpy(&hd, p, sizeof(hd));
+    if (hd.magic != kMagic || hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.nz != h->cfg.nz ||
+        hd.precision != h->cfg.precision || hd.n_probes != h->n_probes || hd.n_freq != h->n_freq ||
+        hd.decim != h->decim)
+        return fail(h, MBF_EINVAL, "state image does not match this handle");
+    const size_t body = need - sizeof(uint64_t);
+    uint64_t cs;
+    std::memcpy(&cs, p + body, sizeof(cs));
+    if (cs != fnv1a(p, body)) return fail(h, MBF_EINVAL, "state image checksum mismatch");
+    if (!h->have_material) return fail(h, MBF_ESTATE, "set the material first");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    size_t off = sizeof(hd);
+    const size_t fb = (size_t)h->nsite * h->esz;
+    for (int id = 0; id < MBF_NFIELDS; ++id) {
+        void* dst = nullptr;
+        field_array(h, id, hd.step, true, &dst);
+        HIPCHK(h, hipMemcpy(dst, p + off, fb, hipMemcpyHostToDevice));
+        if (id < 6) {
+            field_array(h, id, hd.step + 1, true, &dst);
+            HIPCHK(h, hipMemcpy(dst, p + off, fb, hipMemcpyHostToDevice));
+        }
+        off += fb;
+    }
+    if (h->n_probes > 0) {
+        const size_t sb = sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq;
+        HIPCHK(h, hipMemcpy(h->d_spec, p + off, sb, hipMemcpyHostToDevice));
+        off += sb;
+        const size_t rb = h->esz * (size_t)h->n_probes * h->decim;
+        HIPCHK(h, hipMemcpy(h->d_ring, p + off, rb, hipMemcpyHostToDevice));
+        off += rb;
+    }
+    HIPCHK(h, hipMemcpy(h->ctl, &hd.ctl, sizeof(mbf::Ctl), hipMemcpyHostToDevice));
+    h->step = hd.step;
+    h->flushed = hd.flushed;
+    h->have_pump = true;
+    h->Na_si = hd.Na_si;
+    h->co = h->cfg.precision == MBF_FP64 ? make_coef<double>(h->cfg, hd.Na_si)
+                                          : make_coef<float>(h->cfg, hd.Na_si);
+    drop_graph(h);
+    return MBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,409 @@
+"""ctypes binding of the C ABI in include/mbf.h.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library ``libmbf.so``.  Importing this module fails loudly when the library
+has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbf.so")
+
+MBF_OK, MBF_EINVAL, MBF_ECFL, MBF_ENOMEM, MBF_EHIP, MBF_ENONFINITE, MBF_ESTATE, MBF_ENODEV = \
+    0, -1, -2, -3, -4, -5, -6, -7
+MBF_PEC, MBF_MUR1, MBF_ABSORB = 0, 1, 2
+MBF_INIT_GROUND, MBF_INIT_PREPUMPED = 0, 1
+MBF_FP32, MBF_FP64 = 0, 1
+MBF_MEM_HOST, MBF_MEM_DEVICE = 0, 1
+MBF_FLAG_FROZEN_POP = 1
+MBF_EX, MBF_EY, MBF_EZ, MBF_HX, MBF_HY, MBF_HZ = range(6)
+MBF_PX, MBF_PPREVX, MBF_N1X, MBF_N2X, MBF_N3X = 6, 9, 12, 15, 18
+MBF_NFIELDS = 21
+(MBF_C_DT, MBF_C_S, MBF_C_A, MBF_C_B, MBF_C_CK, MBF_C_CF, MBF_C_BETA, MBF_C_DT32, MBF_C_DT21,
+ MBF_C_DT10, MBF_C_DTWP, MBF_C_NA, MBF_C_COUNT) = range(13)
+
+_ERRNAMES = {MBF_EINVAL: "MBF_EINVAL", MBF_ECFL: "MBF_ECFL", MBF_ENOMEM: "MBF_ENOMEM",
+             MBF_EHIP: "MBF_EHIP", MBF_ENONFINITE: "MBF_ENONFINITE", MBF_ESTATE: "MBF_ESTATE",
+             MBF_ENODEV: "MBF_ENODEV"}
+
+
+class MbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mbf_config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("boundary", C.c_int32 * 3),
+        ("precision", C.c_int32), ("noise", C.c_int32), ("flags", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("dx", C.c_double), ("courant", C.c_double),
+        ("lambda0", C.c_double), ("dlambda", C.c_double),
+        ("tau32", C.c_double), ("tau21", C.c_double), ("tau10", C.c_double),
+        ("Wp", C.c_double), ("N_ref", C.c_double), ("E_ref", C.c_double),
+        ("E_sp", C.c_double),
+        ("seed", C.c_uint64), ("realization", C.c_uint32), ("reserved1", C.c_int32),
+        ("energy_history", C.c_int64),
+        ("absorb_cells", C.c_int32), ("absorb_order", C.c_int32), ("absorb_rate", C.c_double),
+    ]
+
+
+class mbf_tuning(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("tile_y", C.c_int32), ("zseg", C.c_int32),
+                ("xcd_remap", C.c_int32)]
+
+
+MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED = 0, 1
+
+
+def _load():
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that both torch and this library bind to one runtime in the process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(the library has no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, I, I64, D, VP = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_void_p
+    dp = C.POINTER(C.c_double)
+    sigs = {
+        "mbf_version": (C.c_char_p, []),
+        "mbf_global_error": (C.c_char_p, []),
+        "mbf_last_error": (C.c_char_p, [P]),
+        "mbf_config_default": (I, [C.POINTER(mbf_config), I, I, I]),
+        "mbf_create": (I, [C.POINTER(mbf_config), VP, C.POINTER(P)]),
+        "mbf_destroy": (None, [P]),
+        "mbf_coefficients": (I, [P, dp, I]),
+        "mbf_set_material": (I, [P, VP, VP, I]),
+        "mbf_set_pump": (I, [P, D, I]),
+        "mbf_add_point_source": (I, [P, I, I, I, I, D, D, D, D]),
+        "mbf_set_probes": (I, [P, VP, I, VP, I, I]),
+        "mbf_set_loss_box": (I, [P, I, I, I, I, I, I]),
+        "mbf_step": (I, [P, I64]),
+        "mbf_sync": (I, [P]),
+        "mbf_step_index": (I, [P, C.POINTER(C.c_int64)]),
+        "mbf_read_energy": (I, [P, dp, dp]),
+        "mbf_read_energy_history": (I, [P, dp, I64, C.POINTER(C.c_int64)]),
+        "mbf_read_spectrum": (I, [P, dp]),
+        "mbf_read_loss": (I, [P, dp]),
+        "mbf_read_field": (I, [P, I, VP, I]),
+        "mbf_write_field": (I, [P, I, VP, I]),
+        "mbf_state_size": (I, [P, C.POINTER(C.c_size_t)]),
+        "mbf_save_state": (I, [P, VP, C.c_size_t]),
+        "mbf_load_state": (I, [P, VP, C.c_size_t]),
+        "mbf_set_tuning": (I, [P, C.POINTER(mbf_tuning)]),
+        "mbf_get_tuning": (I, [P, C.POINTER(mbf_tuning)]),
+        "mbf_step_timed": (I, [P, I64, dp, C.POINTER(C.c_int64)]),
+        "mbf_step_bytes": (I, [P, dp]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+lib = _load()
+EXPORTED = [
+    "mbf_version", "mbf_global_error", "mbf_last_error", "mbf_config_default", "mbf_create",
+    "mbf_destroy", "mbf_coefficients", "mbf_set_material", "mbf_set_pump",
+    "mbf_add_point_source", "mbf_set_probes", "mbf_set_loss_box", "mbf_step", "mbf_sync",
+    "mbf_step_index", "mbf_read_energy", "mbf_read_energy_history", "mbf_read_spectrum",
+    "mbf_read_loss", "mbf_read_field", "mbf_write_field", "mbf_state_size", "mbf_save_state",
+    "mbf_load_state", "mbf_set_tuning", "mbf_get_tuning", "mbf_step_timed", "mbf_step_bytes",
+]
+
+
+def _check(rc: int, h=None):
+    if rc != MBF_OK:
+        msg = (lib.mbf_last_error(h) if h else lib.mbf_global_error()) or b""
+        raise MbfError(rc, msg.decode(errors="replace"))
+
+
+# ------------------------------------------------------------ raw ABI names
+
+def mbf_version() -> str:
+    return lib.mbf_version().decode()
+
+
+def mbf_config_default(nx: int, ny: int, nz: int) -> mbf_config:
+    cfg = mbf_config()
+    _check(lib.mbf_config_default(C.byref(cfg), nx, ny, nz))
+    return cfg
+
+
+def mbf_create(cfg: mbf_config, stream: Optional[int] = None) -> int:
+    h = C.c_void_p()
+    _check(lib.mbf_create(C.byref(cfg), C.c_void_p(stream or 0), C.byref(h)))
+    return h.value
+
+
+def mbf_destroy(h: int) -> None:
+    lib.mbf_destroy(h)
+
+
+def mbf_coefficients(h: int) -> np.ndarray:
+    out = np.zeros(MBF_C_COUNT)
+    _check(lib.mbf_coefficients(h, out.ctypes.data_as(C.POINTER(C.c_double)), MBF_C_COUNT), h)
+    return out
+
+
+def _ptr_kind(a) -> Tuple[int, int, object]:
+    """(address, mem_kind, keep-alive) for a numpy array or a device tensor."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, MBF_MEM_HOST, a
+    if hasattr(a, "data_ptr") and getattr(a, "is_cuda", False):
+        return a.data_ptr(), MBF_MEM_DEVICE, a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr(), MBF_MEM_HOST, a
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+def mbf_set_material(h: int, eps_r, gain) -> None:
+    if isinstance(eps_r, np.ndarray):
+        eps_r = np.ascontiguousarray(eps_r, dtype=np.float32)
+        gain = np.ascontiguousarray(gain, dtype=np.uint8)
+    pe, ke, _a = _ptr_kind(eps_r)
+    pg, kg, _b = _ptr_kind(gain)
+    if ke != kg:
+        raise ValueError("eps_r and gain must live in the same memory")
+    _check(lib.mbf_set_material(h, pe, pg, ke), h)
+
+
+def mbf_set_pump(h: int, Na: float, init: int = MBF_INIT_PREPUMPED) -> None:
+    _check(lib.mbf_set_pump(h, float(Na), int(init)), h)
+
+
+def mbf_add_point_source(h, comp, i, j, k, amp=1.0, lambda_s=532e-9, tau_p=1e-15, t0=4e-15):
+    _check(lib.mbf_add_point_source(h, comp, i, j, k, amp, lambda_s, tau_p, t0), h)
+
+
+def mbf_set_probes(h: int, sites: np.ndarray, omega: np.ndarray, decim: int = 32) -> None:
+    sites = np.ascontiguousarray(sites, dtype=np.int32).reshape(-1, 4)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    _check(lib.mbf_set_probes(h, sites.ctypes.data, sites.shape[0], omega.ctypes.data,
+                              omega.shape[0], decim), h)
+
+
+def mbf_set_loss_box(h: int, lo: Sequence[int], hi: Sequence[int]) -> None:
+    _check(lib.mbf_set_loss_box(h, *lo, *hi), h)
+
+
+def mbf_step(h: int, n: int) -> None:
+    _check(lib.mbf_step(h, int(n)), h)
+
+
+def mbf_sync(h: int) -> None:
+    _check(lib.mbf_sync(h), h)
+
+
+def mbf_step_index(h: int) -> int:
+    v = C.c_int64()
+    _check(lib.mbf_step_index(h, C.byref(v)), h)
+    return v.value
+
+
+def mbf_read_energy(h: int) -> Tuple[float, float]:
+    a, b = C.c_double(), C.c_double()
+    _check(lib.mbf_read_energy(h, C.byref(a), C.byref(b)), h)
+    return a.value, b.value
+
+
+def mbf_read_energy_history(h: int, cap: int) -> np.ndarray:
+    out = np.zeros(max(cap, 1))
+    cnt = C.c_int64()
+    _check(lib.mbf_read_energy_history(h, out.ctypes.data_as(C.POINTER(C.c_double)), cap,
+                                       C.byref(cnt)), h)
+    return out[:min(cnt.value, cap)]
+
+
+def mbf_read_spectrum(h: int, n_probes: int, n_freq: int) -> np.ndarray:
+    out = np.zeros((n_probes, n_freq, 2))
+    _check(lib.mbf_read_spectrum(h, out.ctypes.data_as(C.POINTER(C.c_double))), h)
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def mbf_read_loss(h: int) -> float:
+    v = C.c_double()
+    _check(lib.mbf_read_loss(h, C.byref(v)), h)
+    return v.value
+
+
+def mbf_read_field(h: int, field_id: int, dst) -> None:
+    p, kind, _k = _ptr_kind(dst)
+    _check(lib.mbf_read_field(h, field_id, p, kind), h)
+
+
+def mbf_write_field(h: int, field_id: int, src) -> None:
+    p, kind, _k = _ptr_kind(src)
+    _check(lib.mbf_write_field(h, field_id, p, kind), h)
+
+
+def mbf_state_size(h: int) -> int:
+    v = C.c_size_t()
+    _check(lib.mbf_state_size(h, C.byref(v)), h)
+    return v.value
+
+
+def mbf_save_state(h: int) -> bytearray:
+    buf = bytearray(mbf_state_size(h))
+    arr = (C.c_char * len(buf)).from_buffer(buf)
+    _check(lib.mbf_save_state(h, C.addressof(arr), len(buf)), h)
+    return buf
+
+
+def mbf_load_state(h: int, buf: bytes) -> None:
+    b = bytearray(buf)
+    arr = (C.c_char * len(b)).from_buffer(b)
+    _check(lib.mbf_load_state(h, C.addressof(arr), len(b)), h)
+
+
+def mbf_set_tuning(h: int, variant: int = MBF_VARIANT_FUSED, tile_y: int = 8, zseg: int = 0,
+                   xcd_remap: int = 1) -> None:
+    t = mbf_tuning(variant, tile_y, zseg, xcd_remap)
+    _check(lib.mbf_set_tuning(h, C.byref(t)), h)
+
+
+def mbf_get_tuning(h: int) -> mbf_tuning:
+    t = mbf_tuning()
+    _check(lib.mbf_get_tuning(h, C.byref(t)), h)
+    return t
+
+
+def mbf_step_timed(h: int, n: int) -> Tuple[float, int]:
+    ms = C.c_double()
+    cnt = C.c_int64()
+    _check(lib.mbf_step_timed(h, int(n), C.byref(ms), C.byref(cnt)), h)
+    return ms.value, cnt.value
+
+
+def mbf_step_bytes(h: int) -> float:
+    b = C.c_double()
+    _check(lib.mbf_step_bytes(h, C.byref(b)), h)
+    return b.value
+
+
+# ------------------------------------------------------------ convenience
+
+class Sim:
+    """One simulation handle with numpy-friendly accessors."""
+
+    def __init__(self, n, *, boundary=("pec", "pec", "pec"), precision="fp32", noise=True,
+                 frozen_pop=False, seed=0, realization=0, energy_history=0, stream=None, **phys):
+        if isinstance(n, int):
+            n = (n, n, n)
+        if isinstance(boundary, str):
+            boundary = (boundary,) * 3
+        cfg = mbf_config_default(*n)
+        kinds = {"pec": MBF_PEC, "mur": MBF_MUR1, "absorb": MBF_ABSORB}
+        for a in range(3):
+            cfg.boundary[a] = kinds[boundary[a]]
+        cfg.precision = MBF_FP64 if precision == "fp64" else MBF_FP32
+        cfg.noise = int(bool(noise))
+        cfg.flags = MBF_FLAG_FROZEN_POP if frozen_pop else 0
+        cfg.seed = seed
+        cfg.realization = realization
+        cfg.energy_history = energy_history
+        for k, v in phys.items():
+            if not hasattr(cfg, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(cfg, k, v)
+        self.cfg = cfg
+        self.n = tuple(n)
+        self.shape = (n[2] + 1, n[1] + 1, n[0] + 1)
+        self.dtype = np.float64 if precision == "fp64" else np.float32
+        self.h = mbf_create(cfg, stream)
+        self._np = self._nf = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            mbf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def coefficients(self):
+        return mbf_coefficients(self.h)
+
+    def set_material(self, eps, gain):
+        mbf_set_material(self.h, eps, gain)
+
+    def set_pump(self, Na, init="prepumped"):
+        mbf_set_pump(self.h, Na, MBF_INIT_PREPUMPED if init == "prepumped" else MBF_INIT_GROUND)
+
+    def set_source(self, comp, i, j, k, amp=1.0, lambda_s=532e-9, tau_p=1e-15, t0=4e-15):
+        mbf_add_point_source(self.h, comp, i, j, k, amp, lambda_s, tau_p, t0)
+
+    def set_probes(self, sites, omega, decim=32):
+        sites = np.asarray(sites).reshape(-1, 4)
+        mbf_set_probes(self.h, sites, omega, decim)
+        self._np, self._nf = sites.shape[0], len(omega)
+
+    def set_loss_box(self, lo, hi):
+        mbf_set_loss_box(self.h, lo, hi)
+
+    def step(self, n):
+        mbf_step(self.h, n)
+
+    def sync(self):
+        mbf_sync(self.h)
+
+    @property
+    def step_index(self):
+        return mbf_step_index(self.h)
+
+    def field(self, fid) -> np.ndarray:
+        out = np.empty(self.shape, dtype=self.dtype)
+        mbf_read_field(self.h, fid, out)
+        return out
+
+    def set_field(self, fid, a):
+        mbf_write_field(self.h, fid, np.ascontiguousarray(a, dtype=self.dtype))
+
+    def energy(self):
+        return mbf_read_energy(self.h)
+
+    def energy_history(self):
+        return mbf_read_energy_history(self.h, self.cfg.energy_history)
+
+    def spectrum(self):
+        return mbf_read_spectrum(self.h, self._np, self._nf)
+
+    def loss(self):
+        return mbf_read_loss(self.h)
+
+    def set_tuning(self, variant="fused", tile_y=8, zseg=0, xcd_remap=1):
+        mbf_set_tuning(self.h, MBF_VARIANT_FUSED if variant == "fused" else MBF_VARIANT_TWO_PASS,
+                       tile_y, zseg, xcd_remap)
+
+    def tuning(self):
+        t = mbf_get_tuning(self.h)
+        return dict(variant="fused" if t.variant == MBF_VARIANT_FUSED else "two_pass",
+                    tile_y=t.tile_y, zseg=t.zseg, xcd_remap=t.xcd_remap)
+
+    def step_timed(self, n):
+        return mbf_step_timed(self.h, n)
+
+    def step_bytes(self):
+        return mbf_step_bytes(self.h)
+
+    def save_state(self):
+        return mbf_save_state(self.h)
+
+    def load_state(self, buf):
+        mbf_load_state(self.h, buf)

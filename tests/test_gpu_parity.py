@@ -1,0 +1,310 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+FP32 runs are compared with the oracle in parity mode (coefficients rounded to
+binary32 on both sides, FP64 arithmetic in the oracle); FP64 runs with the
+oracle's exact coefficients.  Tolerance for FP32 is the relative L2 error
+<= 1e-5 on E, H and P over the pre-lasing interval; for FP64, 1e-11.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_1547_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-11
+
+
+def _mbf():
+    from paper_0809_1547_amd import mbf
+    return mbf
+
+
+def rel(g, o):
+    no = float(np.linalg.norm(o))
+    d = float(np.linalg.norm(np.asarray(g, dtype=np.float64) - o))
+    return d / no if no > 0 else d
+
+
+def pair(n, *, bc=("pec",) * 3, init="prepumped", Na=2e24, eps=None, gain=None,
+         precision="fp32", noise=True, seed=0, realization=0, hist=0, **phys):
+    mbf = _mbf()
+    sim = mbf.Sim(n, boundary=bc, precision=precision, noise=noise, seed=seed,
+                  realization=realization, energy_history=hist, **phys)
+    kinds = {"pec": O.PEC, "mur": O.MUR1, "absorb": O.ABSORB}
+    obc = tuple(kinds[b] for b in bc)
+    ora = O.Oracle(O.default_params(n, bc=obc, round_f32=(precision == "fp32"), noise=noise,
+                                    seed=seed, realization=realization, **phys))
+    sim.set_material(eps, gain)
+    ora.set_material(eps, gain)
+    sim.set_pump(Na, init)
+    ora.set_pump(Na, O.PREPUMPED if init == "prepumped" else O.GROUND)
+    return sim, ora
+
+
+def worst(sim, ora, fids=range(9)):
+    return max(rel(sim.field(f), ora.field(f)) for f in fids)
+
+
+def c1_material():
+    pk = I.packing_for("c1", 32, 0)
+    return I.voxelize(pk)
+
+
+def test_c1_fp32_parity_500_steps():
+    eps, gain = c1_material()
+    sim, ora = pair(32, eps=eps, gain=gain, hist=500)
+    errs = []
+    for _ in range(10):
+        sim.step(50)
+        ora.step(50)
+        errs.append(worst(sim, ora))
+    print("C1 fp32 rel L2 per 50 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= TOL32
+    # populations, energy history
+    for f in range(12, 21):
+        assert rel(sim.field(f), ora.field(f)) <= TOL32
+    gh, oh = sim.energy_history(), ora.energy_history()
+    assert gh.shape == oh.shape == (500,)
+    assert gh[0] == oh[0] == 0.0
+    assert float(np.max(np.abs(gh[1:] - oh[1:]) / np.abs(oh[1:]))) <= TOL32
+    assert oh[-1] > oh[50] > 0            # noise-started field is growing
+
+
+def test_c1_fp64_parity():
+    eps, gain = c1_material()
+    sim, ora = pair(32, eps=eps, gain=gain, precision="fp64")
+    for _ in range(4):
+        sim.step(50)
+        ora.step(50)
+        assert worst(sim, ora, range(21)) <= TOL64
+
+
+def test_noise_identity_fp64_single_step():
+    # one step from a zero field: E^1 is the noise response alone, so any
+    # difference in the Philox stream or the Box-Muller mapping shows up here
+    n = (24, 20, 18)
+    eps, gain = I.homogeneous(n, 1.0, 1)
+    sim, ora = pair(n, eps=eps, gain=gain, precision="fp64", E_sp=1.0, seed=(7 << 32) + 11,
+                    realization=5)
+    sim.step(2)
+    ora.step(2)
+    for f in (6, 7, 8):
+        assert rel(sim.field(f), ora.field(f)) <= 1e-13
+    assert np.abs(ora.field(6)).max() > 0
+
+
+@pytest.mark.parametrize("n", [(48, 40, 36), (65, 9, 7)])
+def test_passive_pulse_and_spectrum_with_absorbing_layer(n):
+    # passive run: spheres without gain, single-cycle 532 nm pulse, probes
+    pk = I.rsa_pack(n, seed=2, fill=0.3)
+    eps, gain = I.voxelize(pk)
+    gain[:] = 0
+    sim, ora = pair(n, bc=("absorb",) * 3, eps=eps, gain=gain, init="ground", noise=False,
+                    absorb_cells=4)
+    src = I.nearest_void_site(np.ones_like(gain))
+    sim.set_source(*src, amp=1.0)
+    ora.set_source(*src, amp=1.0)
+    probes = I.select_probes(eps, np.ones_like(gain), 12, seed=1)
+    dt = sim.coefficients()[_mbf().MBF_C_DT]
+    om = I.dft_omegas(450e-9, 800e-9, 600, dt)
+    sim.set_probes(probes, om, decim=32)
+    ora.set_probes(probes, om)
+    errs = []
+    for _ in range(6):
+        sim.step(100)
+        ora.step(100)
+        errs.append(worst(sim, ora, range(6)))
+    print("passive rel L2 per 100 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= TOL32
+    fs, fo = sim.spectrum(), ora.spectrum()
+    assert np.linalg.norm(fs - fo) / np.linalg.norm(fo) <= TOL32
+
+
+def test_mur_source_homogeneous_walls():
+    # first-order Mur where the medium at the walls is homogeneous (vacuum)
+    n = (40, 36, 30)
+    eps, gain = I.homogeneous(n, 1.0, 0)
+    eps[8:22, 8:28, 8:32] = 8.41
+    sim, ora = pair(n, bc=("mur",) * 3, eps=eps, gain=gain, init="ground", noise=False)
+    sim.set_source(2, 4, 5, 6, amp=1.0)
+    ora.set_source(2, 4, 5, 6, amp=1.0)
+    for _ in range(4):
+        sim.step(100)
+        ora.step(100)
+        assert worst(sim, ora, range(6)) <= TOL32
+
+
+def test_lasing_absorbing_layer_ragged_grid():
+    n = (40, 36, 28)
+    pk = I.rsa_pack(n, seed=3, fill=0.4)
+    eps, gain = I.voxelize(pk)
+    sim, ora = pair(n, bc=("absorb",) * 3, eps=eps, gain=gain, seed=9, realization=3)
+    for _ in range(6):
+        sim.step(50)
+        ora.step(50)
+        assert worst(sim, ora) <= TOL32
+
+
+def test_lasing_mur_ragged_grid():
+    n = (40, 36, 28)
+    pk = I.rsa_pack(n, seed=3, fill=0.4)
+    eps, gain = I.voxelize(pk)
+    sim, ora = pair(n, bc=("mur",) * 3, eps=eps, gain=gain, seed=9, realization=3)
+    for _ in range(6):
+        sim.step(50)
+        ora.step(50)
+        assert worst(sim, ora) <= TOL32
+
+
+def test_mixed_pec_mur_walls():
+    n = (20, 24, 30)
+    pk = I.rsa_pack(n, seed=4, count=4, radius=4.0)
+    eps, gain = I.voxelize(pk)
+    for bc in [("pec", "mur", "mur"), ("mur", "pec", "mur"), ("mur", "mur", "pec"),
+               ("absorb", "mur", "pec"), ("mur", "absorb", "absorb")]:
+        sim, ora = pair(n, bc=bc, eps=eps, gain=gain, E_sp=1e-3)
+        f = I.random_fields(n, seed=5, amplitude=1e-3)
+        for c in range(3):
+            sim.set_field(c, f[c])
+            ora.set_field(c, f[c].astype(np.float64))
+        sim.step(120)
+        ora.step(120)
+        assert worst(sim, ora, range(21)) <= TOL32, bc
+
+
+def test_loss_box_and_energy_monitors():
+    n = (30, 30, 30)
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=6, count=5, radius=4.0))
+    sim, ora = pair(n, eps=eps, gain=gain, hist=200, E_sp=1e-2)
+    sim.set_loss_box((8, 9, 10), (24, 25, 26))
+    ora.set_loss_box((8, 9, 10), (24, 25, 26))
+    sim.step(200)
+    ora.step(200)
+    assert sim.loss() == pytest.approx(ora.loss(), rel=TOL32)
+    (gw, gi), (ow, oi) = sim.energy(), ora.energy()
+    assert gw == pytest.approx(ow, rel=TOL32) and gi == pytest.approx(oi, rel=TOL32)
+
+
+def test_smallest_grid():
+    n = (2, 2, 2)
+    eps, gain = I.homogeneous(n, 2.0, 1)
+    sim, ora = pair(n, bc=("mur",) * 3, eps=eps, gain=gain, E_sp=1.0)
+    sim.step(40)
+    ora.step(40)
+    assert worst(sim, ora, range(21)) <= TOL32
+
+
+# ----------------------------------------------------------- invariance
+
+@pytest.mark.parametrize("bc", ["pec", "mur", "absorb"])
+def test_kernel_variants_are_bitwise_identical(bc):
+    n = (70, 37, 29)
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=11, fill=0.35))
+    mbf = _mbf()
+    ref = None
+    for var, ty, zs, remap in [("two_pass", 8, 0, 0), ("fused", 2, 3, 1), ("fused", 4, 7, 0),
+                               ("fused", 8, 0, 1), ("fused", 16, 29, 1)]:
+        sim = mbf.Sim(n, boundary=bc, E_sp=1e-2)
+        sim.set_tuning(var, tile_y=ty, zseg=zs, xcd_remap=remap)
+        sim.set_material(eps, gain)
+        sim.set_pump(2e24)
+        src = I.nearest_void_site(gain)
+        sim.set_source(*src, amp=0.5)
+        sim.step(60)
+        st = [sim.field(f) for f in range(21)]
+        if ref is None:
+            ref = st
+        else:
+            for a, b in zip(ref, st):
+                assert np.array_equal(a, b), (var, ty, zs)
+        sim.close()
+
+
+def _state(sim):
+    return [sim.field(f).copy() for f in range(21)]
+
+
+def test_graph_replay_equals_single_steps_and_determinism():
+    eps, gain = c1_material()
+    mbf = _mbf()
+    runs = []
+    for mode in ("graph", "single", "graph"):
+        sim = mbf.Sim(32, energy_history=100)
+        sim.set_material(eps, gain)
+        sim.set_pump(2e24)
+        if mode == "graph":
+            sim.step(96)        # three 32-step graph replays
+        else:
+            for _ in range(96):
+                sim.step(1)
+        runs.append((_state(sim), sim.energy_history()))
+        sim.close()
+    for r in runs[1:]:
+        for a, b in zip(runs[0][0], r[0]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(runs[0][1], r[1])
+
+
+def test_checkpoint_resume_is_bitwise():
+    eps, gain = c1_material()
+    mbf = _mbf()
+    a = mbf.Sim(32, boundary="mur")
+    a.set_material(eps, gain)
+    a.set_pump(2e24)
+    a.step(77)
+    img = a.save_state()
+    a.step(50)
+    ref = _state(a)
+    b = mbf.Sim(32, boundary="mur")
+    b.set_material(eps, gain)
+    b.load_state(img)
+    assert b.step_index == 77
+    b.step(50)
+    for x, y in zip(ref, _state(b)):
+        assert np.array_equal(x, y)
+    bad = bytearray(img)
+    bad[200] ^= 0xFF
+    with pytest.raises(mbf.MbfError):
+        b.load_state(bytes(bad))
+
+
+def test_nonfinite_energy_is_reported():
+    mbf = _mbf()
+    eps, gain = I.homogeneous(8, 1.0, 1)
+    sim = mbf.Sim(8)
+    sim.set_material(eps, gain)
+    sim.set_pump(2e24)
+    e = np.zeros(sim.shape, dtype=np.float32)
+    e[3, 3, 3] = np.nan
+    sim.set_field(0, e)
+    sim.step(2)
+    with pytest.raises(mbf.MbfError) as err:
+        sim.energy()
+    assert err.value.code == mbf.MBF_ENONFINITE
+
+
+def test_device_memory_roundtrip_through_torch():
+    import torch
+    mbf = _mbf()
+    n = 16
+    eps, gain = I.homogeneous(n, 1.0, 1)
+    sim = mbf.Sim(n)
+    sim.set_material(torch.from_numpy(eps).cuda(), torch.from_numpy(gain).cuda())
+    sim.set_pump(2e24)
+    f = I.random_fields((n, n, n), seed=1)
+    t = torch.from_numpy(f[1]).cuda()
+    mbf.mbf_write_field(sim.h, 1, t)
+    out = torch.empty_like(t)
+    mbf.mbf_read_field(sim.h, 1, out)
+    sim.sync()
+    assert torch.equal(out, t)
+    sim.step(3)
+    host = sim.field(1)
+    mbf.mbf_read_field(sim.h, 1, out)
+    sim.sync()
+    assert np.array_equal(out.cpu().numpy(), host)

@@ -147,3 +147,91 @@ def test_loss_box_is_time_sum_of_e_squared():
             msk = I.interior_e_mask(n, c)[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
             tot += float(np.sum(e[msk] ** 2))
     assert o.loss() == pytest.approx(tot, rel=1e-13)
+
+
+# ----------------------------------------------------- graded lossy layer
+
+def test_lossy_cavity_mode_decays_by_closed_form_factor():
+    """Uniform loss a on every E- and H-site (order 0, layer deeper than the
+    box gives a = 2 a_max per axis): a cavity mode's amplitude obeys
+    z^2 - (2g - d^2 S^2 K^2) z + g^2 = 0 with g = (1-a)/(1+a), d = 1/(1+a), so
+    both roots have modulus exactly g and cos(arg z) = (2g - d^2 S^2 K^2)/(2g)."""
+    n, m = (12, 10, 8), (1, 2, 1)
+    amax = 0.01
+    o = O.Oracle(O.default_params(n, noise=False, bc=(O.ABSORB,) * 3, absorb_cells=100,
+                                  absorb_order=0, absorb_rate=amax))
+    o.set_material(*I.homogeneous(n, 1.0, 0))
+    o.set_pump(2e24, O.GROUND)
+    mode = cavity_mode(n, m)
+    for c in range(3):
+        o.set_field(c, mode[c])
+    norm2 = sum(float(np.sum(e * e)) for e in mode)
+    amps = [1.0]
+    for _ in range(400):
+        o.step(1)
+        amps.append(sum(float(np.sum(o.field(c) * mode[c])) for c in range(3)) / norm2)
+    a = np.array(amps)
+    y = a[2:]
+    X = np.stack([a[1:-1], a[:-2]], axis=1)
+    (p, q), *_ = np.linalg.lstsq(X, y, rcond=None)
+    aa = 6 * amax
+    g, d = (1 - aa) / (1 + aa), 1 / (1 + aa)
+    S = o.coefficients()[O.C_S]
+    K2 = sum(4 * math.sin(m[k] * math.pi / (2 * n[k])) ** 2 for k in range(3))
+    assert abs(-q - g * g) < 1e-12                  # product of the roots
+    assert abs(p - (2 * g - d * d * S * S * K2)) < 1e-12   # sum of the roots
+
+
+def _te10_reflection(bcz, nx=8, beta0=2 * math.pi / 12, **kw):
+    ny, nz = 2, 1200
+    n = (nx, ny, nz)
+    o = O.Oracle(O.default_params(n, noise=False, bc=(O.PEC, O.PEC, bcz), **kw))
+    o.set_material(*I.homogeneous(n, 1.0, 0))
+    o.set_pump(2e24, O.GROUND)
+    kc, sig, kp = 500, 40.0, 900
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1),
+                             indexing="ij")
+    ey = np.sin(math.pi * ii / nx) * np.exp(-0.5 * ((kk - kc) / sig) ** 2) * np.cos(beta0 * kk)
+    ey[~I.interior_e_mask(n, 1)] = 0.0
+    o.set_field(1, ey)
+    S, dt = o.coefficients()[O.C_S], o.coefficients()[O.C_DT]
+    betas = beta0 + np.linspace(-0.04, 0.04, 5)
+    th = 2 * np.arcsin(S * np.sqrt(np.sin(math.pi / (2 * nx)) ** 2 + np.sin(betas / 2) ** 2))
+    vg = S * S * math.sin(beta0) / math.sin(th[2])
+    o.set_probes(np.array([(1, nx // 2, 0, kp)]), th / dt)
+    t1 = int((kp - kc + 150) / vg)
+    t2 = int((2 * nz - kp - kc + 150) / vg)
+    o.step(t1)
+    fi = o.spectrum()[0].copy()
+    o.step(t2 - t1)
+    return np.abs((o.spectrum()[0] - fi) / fi)
+
+
+def test_lossy_layer_reflection_is_at_most_that_of_mur():
+    # a guided wave at ~37 degrees and one near normal incidence
+    for nx, beta0 in ((8, 2 * math.pi / 12), (24, 2 * math.pi / 20)):
+        r_abs = _te10_reflection(O.ABSORB, nx=nx, beta0=beta0)
+        r_mur = _te10_reflection(O.MUR1, nx=nx, beta0=beta0)
+        assert np.max(r_abs) < 0.08
+        assert np.mean(r_abs) < 1.2 * np.mean(r_mur)
+
+
+def test_lossy_layer_stable_where_mur_grows():
+    """A dielectric sphere tangent to an absorbing wall: first-order Mur turns
+    the step into a growing map (the reason the lossy layer exists), the
+    graded lossy layer keeps the field bounded."""
+    n = (16, 16, 16)
+    eps, _ = I.voxelize(I.Packing(n, np.array([[8.0, 8.0, 12.0]]), np.array([4.0])))
+    out = {}
+    for bc in (O.MUR1, O.ABSORB):
+        o = O.Oracle(O.default_params(n, noise=False, bc=(O.PEC, O.PEC, bc)))
+        o.set_material(eps, np.zeros_like(eps, dtype=np.uint8))
+        o.set_pump(2e24, O.GROUND)
+        f = I.random_fields(n, seed=5)
+        for c in range(3):
+            o.set_field(c, f[c].astype(np.float64))
+        o.step(1500)
+        out[bc] = math.sqrt(sum(float(np.sum(o.field(c) ** 2)) for c in range(3)))
+    start = math.sqrt(sum(float(np.sum(f[c].astype(np.float64) ** 2)) for c in range(3)))
+    assert out[O.MUR1] > 1e6 * start
+    assert out[O.ABSORB] < start

@@ -15,12 +15,12 @@ PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_yee.py", "tests/test_orac
 
 # (name, original text, mutated text)
 MUTATIONS = [
-    ("faraday_sign", "s->Hn[0][x] = Hx[x] - S * cx;", "s->Hn[0][x] = Hx[x] + S * cx;"),
+    ("faraday_sign", "s->Hn[c][x] = H3[c][x] - S * c3[c];", "s->Hn[c][x] = H3[c][x] + S * c3[c];"),
     ("curl_index", "double cx = (Ez[xj] - Ez[x])", "double cx = (Ez[xi] - Ez[x])"),
     ("curl_operand_order", "double cz = (Ey[xi] - Ey[x]) - (Ex[xj] - Ex[x]);",
      "double cz = (Ex[xj] - Ex[x]) - (Ey[xi] - Ey[x]);"),
     ("ampere_index", "curl = (Hz[x] - Hz[at(s, i, j - 1, k)])", "curl = (Hz[x] - Hz[at(s, i - 1, j, k)])"),
-    ("ampere_polarisation_sign", "ie * (S * curl - dP)", "ie * (S * curl + dP)"),
+    ("ampere_polarisation_sign", "s->f[c][x] = s->Eold[c][x] + ie * (S * curl - dP);", "s->f[c][x] = s->Eold[c][x] + ie * (S * curl + dP);"),
     ("ampere_missing_inv_eps", "s->Eold[c][x] + ie * (S * curl - dP)", "s->Eold[c][x] + (S * curl - dP)"),
     ("lorentz_history", "c[ORC_C_B] * Pprev", "c[ORC_C_B] * P"),
     ("lorentz_inversion_sign", "double dN = s->f[12 + c][x] - s->f[15 + c][x];",
@@ -40,6 +40,8 @@ MUTATIONS = [
     ("philox_weyl", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;"),
     ("philox_word_order", "uint32_t y1 = lo1;", "uint32_t y1 = lo0;"),
     ("rate_work_factor_only", "double W = c[ORC_C_BETA] * Ebar * dP;", "double W = 0.5 * c[ORC_C_BETA] * Ebar * dP;"),
+    ("layer_loss_sign", "s->Hn[c][x] = ((1.0 - a) / (1.0 + a)) * H3[c][x]", "s->Hn[c][x] = ((1.0 + a) / (1.0 + a)) * H3[c][x]"),
+    ("layer_e_scale", "(1.0 / (1.0 + a)) * (ie * (S * curl - dP));", "(ie * (S * curl - dP));"),
     ("prepump_fixed_point", "N[2] = rnd(s, dwp * n0 / d21);", "N[2] = rnd(s, dwp * n0 / d32);"),
 ]
 
