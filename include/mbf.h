@@ -237,19 +237,25 @@ typedef struct mbf_tuning {
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t);
 int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
 
-/* Queue nsteps steps without graph capture, bracketing the dominant kernel of
- * every step with a pair of HIP events on the handle's stream; on return
- * (synchronised) *kernel_ms holds the summed duration of those kernels and
- * *launches their count.  Used to time the kernel against its roofline. */
-int mbf_step_timed(mbf_handle* h, int64_t nsteps, double* kernel_ms, int64_t* launches);
+/* Queue nsteps steps without graph capture, bracketing the field kernels of
+ * every step with HIP events on the handle's stream.  On return
+ * (synchronised) kernel_ms[0] holds the summed duration of the first field
+ * kernel (the fused step kernel, or the Faraday pass of the two-pass variant)
+ * and kernel_ms[1] that of the second (the Ampere/Bloch pass; 0 for the
+ * fused variant); *launches is the number of steps.  Used to time the kernels
+ * against their roofline. */
+int mbf_step_timed(mbf_handle* h, int64_t nsteps, double* kernel_ms /* [2] */, int64_t* launches);
 
-/* Algorithmic HBM bytes of one step: what the step must move if every value
- * is read and written exactly once.  Per cell: E and H read and written
- * (4 x 3 values) and 1 material byte; per interior gain E-site: P^n and
+/* Algorithmic HBM bytes: what must move if every value is read and written
+ * exactly once.  bytes[0], the step: per cell E and H read and written
+ * (4 x 3 values) and 1 material byte; per interior gain E-site P^n and
  * P^{n-1} read, P^{n+1} written, N1..N3 read and written (9 values).  A value
  * is 4 B in FP32 and 8 B in FP64, so a cell whose three E-sites carry gain
- * costs 157 B in FP32.  Counted from the current material map. */
-int mbf_step_bytes(const mbf_handle* h, double* bytes);
+ * costs 157 B in FP32.  bytes[1] and bytes[2]: the same count for the first
+ * and second field kernel of the current variant (the two-pass variant reads
+ * H^{n+1/2} and the material byte in both passes).  From the current
+ * material map. */
+int mbf_step_bytes(const mbf_handle* h, double* bytes /* [3] */);
 
 /* Checkpoint: bytes needed, save into / load from a caller buffer.  The
  * image holds all 21 fields, the step index and the monitors, with a

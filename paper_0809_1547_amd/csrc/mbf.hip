@@ -41,7 +41,8 @@ struct mbf_handle {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t sx = 0, sxy = 0, nsite = 0;
+    int64_t sx = 0, sxy = 0, nsite = 0;   // device layout: x pitch padded to 128-byte lines
+    int64_t nexch = 0;                    // sites of the packed exchange layout
     size_t esz = 4;
     void* pool = nullptr;
     void* arr[27] = {};       // E_a[3] E_b[3] H_a[3] H_b[3] P_a[3] P_b[3] N1[3] N2[3] N3[3]
@@ -190,13 +191,15 @@ mbf::SimView<T> view(mbf_handle* h) {
     v.box_on = h->box_on;
     for (int q = 0; q < 6; ++q) v.box[q] = h->box[q];
     v.n_mur = h->mur_tasks;
-    for (int q = 0; q < h->mur_tasks; ++q) {
-        v.mur_a[q] = h->mur_a[q];
-        v.mur_side[q] = h->mur_side[q];
-        v.mur_c[q] = h->mur_c[q];
-    }
-    for (int q = 0; q < 3; ++q) v.bc[q] = h->cfg.boundary[q];
+    v.mur_code = 0;
+    for (int q = 0; q < h->mur_tasks; ++q)
+        v.mur_code |= (uint64_t)(h->mur_a[q] | (h->mur_side[q] << 2) | (h->mur_c[q] << 3)) << (5 * q);
+    v.mur_axes = 0;
+    for (int q = 0; q < 3; ++q)
+        if (h->cfg.boundary[q] == MBF_MUR1) v.mur_axes |= 1 << q;
     v.has_layer = h->has_layer ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        v.lay_L[a] = (h->has_layer && h->cfg.boundary[a] == MBF_ABSORB) ? h->cfg.absorb_cells : -1;
     for (int a = 0; a < 3; ++a)
         for (int hf = 0; hf < 2; ++hf)
             v.prof[a][hf] = reinterpret_cast<const T*>(h->prof) + (2 * a + hf) * h->prof_stride;
@@ -217,9 +220,14 @@ mbf::SimView<T> view(mbf_handle* h) {
     return v;
 }
 
+// Two-pass kernels: workgroups of 64 x tile_y columns, each over zchunk planes.
+int two_pass_zchunk(const mbf_handle* h) {
+    return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(8, h->cfg.nz);
+}
+
 dim3 grid_cells(const mbf_handle* h) {
-    return dim3((h->cfg.nx + mbf::kBlockX - 1) / mbf::kBlockX,
-                (h->cfg.ny + mbf::kBlockY - 1) / mbf::kBlockY, h->cfg.nz);
+    const int ty = h->tun.tile_y, zc = two_pass_zchunk(h);
+    return dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + ty - 1) / ty, (h->cfg.nz + zc - 1) / zc);
 }
 
 // Geometry of the fused kernel's work items for the handle's tuning.
@@ -259,17 +267,39 @@ void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
 // Queue one step.  When ev0/ev1 are given they bracket the step's field
 // kernels (the dominant cost) on the handle's stream.
 template <typename T>
-int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
+                hipEvent_t ev1 = nullptr) {
     mbf::SimView<T> v = view<T>(h);
     if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
     if (h->tun.variant == MBF_VARIANT_FUSED) {
         launch_fused<T>(h, v);
+        if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
     } else {
         const dim3 g = grid_cells(h);
-        const dim3 b(mbf::kBlockX, mbf::kBlockY, 1);
+        const int zc = two_pass_zchunk(h);
         v.n_part = (int)(g.x * g.y * g.z);
-        hipLaunchKernelGGL(mbf::k_curl_h<T>, g, b, 0, h->stream, v);
-        hipLaunchKernelGGL(mbf::k_curl_e<T>, g, b, 0, h->stream, v);
+        switch (h->tun.tile_y) {
+            case 2:
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 2>), g, dim3(64, 2), 0, h->stream, v, zc);
+                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 2>), g, dim3(64, 2), 0, h->stream, v, zc);
+                break;
+            case 4:
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 4>), g, dim3(64, 4), 0, h->stream, v, zc);
+                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 4>), g, dim3(64, 4), 0, h->stream, v, zc);
+                break;
+            case 16:
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 16>), g, dim3(64, 16), 0, h->stream, v, zc);
+                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 16>), g, dim3(64, 16), 0, h->stream, v, zc);
+                break;
+            default:
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 8>), g, dim3(64, 8), 0, h->stream, v, zc);
+                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 8>), g, dim3(64, 8), 0, h->stream, v, zc);
+                break;
+        }
     }
     if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
     if (h->mur_tasks > 0) {
@@ -294,14 +324,24 @@ int launch_dft(mbf_handle* h, int count) {
     return MBF_OK;
 }
 
-int dispatch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    return h->cfg.precision == MBF_FP64 ? launch_step<double>(h, ev0, ev1)
-                                        : launch_step<float>(h, ev0, ev1);
+int dispatch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
+                  hipEvent_t ev1 = nullptr) {
+    return h->cfg.precision == MBF_FP64 ? launch_step<double>(h, ev0, evm, ev1)
+                                        : launch_step<float>(h, ev0, evm, ev1);
 }
 
 int dispatch_dft(mbf_handle* h, int count) {
     return h->cfg.precision == MBF_FP64 ? launch_dft<double>(h, count)
                                         : launch_dft<float>(h, count);
+}
+
+int init_source(mbf_handle* h) {
+    if (h->cfg.precision == MBF_FP64)
+        hipLaunchKernelGGL(mbf::k_source_init<double>, dim3(1), dim3(64), 0, h->stream, view<double>(h));
+    else
+        hipLaunchKernelGGL(mbf::k_source_init<float>, dim3(1), dim3(64), 0, h->stream, view<float>(h));
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
 }
 
 void drop_graph(mbf_handle* h) {
@@ -359,6 +399,19 @@ int field_array(mbf_handle* h, int id, int64_t step, bool write, void** out) {
     return MBF_OK;
 }
 
+// Copy one site array between the padded device layout and the packed
+// exchange layout (rows of nx+1 values); kind is a hipMemcpyKind.
+hipError_t copy_sites(const mbf_handle* h, void* dst, const void* src, bool to_device, hipMemcpyKind kind,
+                      bool async) {
+    const size_t w = (size_t)(h->cfg.nx + 1) * h->esz;
+    const size_t pitch = (size_t)h->sx * h->esz;
+    const size_t rows = (size_t)(h->cfg.ny + 1) * (h->cfg.nz + 1);
+    const size_t dpitch = to_device ? pitch : w;
+    const size_t spitch = to_device ? w : pitch;
+    if (async) return hipMemcpy2DAsync(dst, dpitch, src, spitch, w, rows, kind, h->stream);
+    return hipMemcpy2D(dst, dpitch, src, spitch, w, rows, kind);
+}
+
 uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t hsh = 1469598103934665603ull) {
     for (size_t q = 0; q < n; ++q) {
         hsh ^= p[q];
@@ -409,7 +462,8 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     const mbf_config& c = *cfg;
     if (c.nx < 2 || c.ny < 2 || c.nz < 2) return fail(nullptr, MBF_EINVAL, "grid sizes must be >= 2");
     const double ext = (double)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
-    if (ext > 4.0e9) return fail(nullptr, MBF_EINVAL, "grid too large (cell index must fit 32 bits)");
+    if (ext * (c.precision == MBF_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+        return fail(nullptr, MBF_EINVAL, "grid too large (one site array must stay below 4 GiB)");
     if (!(std::isfinite(c.courant) && c.courant > 0.0 && c.courant <= 1.0))
         return fail(nullptr, MBF_ECFL, "Courant number must lie in (0, 1]");
     bool any_layer = false;
@@ -436,15 +490,19 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     mbf_handle* h = new mbf_handle();
     h->cfg = c;
     hipGetDevice(&h->dev);
-    h->esz = c.precision == MBF_FP64 ? 8 : 4;
-    h->sx = c.nx + 1;
-    h->sxy = (int64_t)(c.nx + 1) * (c.ny + 1);
-    h->nsite = h->sxy * (c.nz + 1);
     auto bail = [&](int code, const std::string& m) {
         g_err = m;
         mbf_destroy(h);
         return code;
     };
+    h->esz = c.precision == MBF_FP64 ? 8 : 4;
+    // rows start on 128-byte lines, so a 64-site tile row covers whole lines
+    const int64_t line = 128 / (int64_t)h->esz;
+    h->sx = ((int64_t)c.nx + 1 + line - 1) / line * line;
+    h->sxy = h->sx * (c.ny + 1);
+    h->nsite = h->sxy * (c.nz + 1);
+    h->nexch = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    if ((double)h->nsite * h->esz >= 4294967296.0) return bail(MBF_EINVAL, "grid too large (one site array must stay below 4 GiB)");
     if (stream) {
         h->stream = (hipStream_t)stream;
     } else {
@@ -663,6 +721,8 @@ int mbf_set_pump(mbf_handle* h, double Na, int init) {
     HIPCHK(h, hipGetLastError());
     int rc = reset_monitors(h);
     if (rc) return rc;
+    rc = init_source(h);
+    if (rc) return rc;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->have_pump = true;
     drop_graph(h);
@@ -676,7 +736,7 @@ int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double am
     if (amp == 0.0) {
         h->src_on = 0;
         drop_graph(h);
-        return MBF_OK;
+        return init_source(h);
     }
     if (comp < 0 || comp > 2) return fail(h, MBF_EINVAL, "component must be 0, 1 or 2");
     const int idx[3] = {i, j, k};
@@ -694,7 +754,7 @@ int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double am
     h->src_tp = tau_p;
     h->src_t0 = t0;
     drop_graph(h);
-    return MBF_OK;
+    return init_source(h);
 }
 
 int mbf_set_probes(mbf_handle* h, const int32_t* sites, int n_probes, const double* omega,
@@ -779,9 +839,9 @@ int run_steps(mbf_handle* h, int64_t nsteps, std::vector<hipEvent_t>* ev) {
             left -= chunk;
             continue;
         }
-        int rc = ev ? dispatch_step(h, (*ev)[e], (*ev)[e + 1]) : dispatch_step(h);
+        int rc = ev ? dispatch_step(h, (*ev)[e], (*ev)[e + 1], (*ev)[e + 2]) : dispatch_step(h);
         if (rc) return rc;
-        e += 2;
+        e += 3;
         h->step += 1;
         left -= 1;
         if (h->n_probes == 0) {
@@ -807,25 +867,28 @@ int mbf_step(mbf_handle* h, int64_t nsteps) {
 int mbf_step_timed(mbf_handle* h, int64_t nsteps, double* kernel_ms, int64_t* launches) {
     if (!h || !kernel_ms || !launches) return fail(h, MBF_EINVAL, "null argument");
     if (nsteps < 0 || nsteps > (1 << 20)) return fail(h, MBF_EINVAL, "step count out of range");
-    std::vector<hipEvent_t> ev((size_t)(2 * nsteps), nullptr);
+    std::vector<hipEvent_t> ev((size_t)(3 * nsteps), nullptr);
     for (auto& x : ev)
         if (hipEventCreate(&x) != hipSuccess) {
             for (auto& y : ev) if (y) hipEventDestroy(y);
             return fail(h, MBF_EHIP, "hipEventCreate failed");
         }
     int rc = run_steps(h, nsteps, &ev);
-    double tot = 0.0;
+    double t0 = 0.0, t1 = 0.0;
     if (rc == MBF_OK) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(h, MBF_EHIP, "synchronise failed");
         for (int64_t q = 0; rc == MBF_OK && q < nsteps; ++q) {
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess)
+            float a = 0.0f, b = 0.0f;
+            if (hipEventElapsedTime(&a, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
+                hipEventElapsedTime(&b, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess)
                 rc = fail(h, MBF_EHIP, "hipEventElapsedTime failed");
-            tot += ms;
+            t0 += a;
+            t1 += b;
         }
     }
     for (auto& x : ev) hipEventDestroy(x);
-    *kernel_ms = tot;
+    kernel_ms[0] = t0;
+    kernel_ms[1] = t1;
     *launches = nsteps;
     return rc;
 }
@@ -834,7 +897,15 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes) {
     if (!h || !bytes) return fail(nullptr, MBF_EINVAL, "null argument");
     const double cells = (double)h->cfg.nx * h->cfg.ny * h->cfg.nz;
     const double v = (double)h->esz;
-    *bytes = cells * (12.0 * v + 1.0) + (double)h->gain_sites * 9.0 * v;
+    const double gs = (double)h->gain_sites;
+    bytes[0] = cells * (12.0 * v + 1.0) + gs * 9.0 * v;      // the step
+    if (h->tun.variant == MBF_VARIANT_FUSED) {
+        bytes[1] = bytes[0];
+        bytes[2] = 0.0;
+    } else {
+        bytes[1] = cells * (9.0 * v + 1.0);                  // E read, H read + written, material
+        bytes[2] = cells * (9.0 * v + 1.0) + gs * 9.0 * v;   // H read, E read + written, material, Bloch state
+    }
     return MBF_OK;
 }
 
@@ -919,12 +990,11 @@ int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind) {
     void* src = nullptr;
     int rc = field_array(h, field_id, h->step, false, &src);
     if (rc) return rc;
-    const size_t bytes = (size_t)h->nsite * h->esz;
     if (mem_kind == MBF_MEM_HOST) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        HIPCHK(h, copy_sites(h, dst, src, false, hipMemcpyDeviceToHost, false));
     } else if (mem_kind == MBF_MEM_DEVICE) {
-        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, copy_sites(h, dst, src, false, hipMemcpyDeviceToDevice, true));
     } else {
         return fail(h, MBF_EINVAL, "bad mem_kind");
     }
@@ -940,14 +1010,13 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind) 
     // walls) then keep the written value whichever buffer is current
     void* dst2 = nullptr;
     if (field_id < 6) field_array(h, field_id, h->step + 1, true, &dst2);
-    const size_t bytes = (size_t)h->nsite * h->esz;
     if (mem_kind == MBF_MEM_HOST) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
-        if (dst2) HIPCHK(h, hipMemcpy(dst2, src, bytes, hipMemcpyHostToDevice));
+        HIPCHK(h, copy_sites(h, dst, src, true, hipMemcpyHostToDevice, false));
+        if (dst2) HIPCHK(h, copy_sites(h, dst2, src, true, hipMemcpyHostToDevice, false));
     } else if (mem_kind == MBF_MEM_DEVICE) {
-        HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream));
-        if (dst2) HIPCHK(h, hipMemcpyAsync(dst2, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, copy_sites(h, dst, src, true, hipMemcpyDeviceToDevice, true));
+        if (dst2) HIPCHK(h, copy_sites(h, dst2, src, true, hipMemcpyDeviceToDevice, true));
     } else {
         return fail(h, MBF_EINVAL, "bad mem_kind");
     }
@@ -970,7 +1039,7 @@ constexpr uint64_t kMagic = 0x3146424D5F54534Bull;
 
 int mbf_state_size(const mbf_handle* h, size_t* out) {
     if (!h || !out) return fail(nullptr, MBF_EINVAL, "null argument");
-    *out = sizeof(StateHeader) + (size_t)MBF_NFIELDS * h->nsite * h->esz +
+    *out = sizeof(StateHeader) + (size_t)MBF_NFIELDS * h->nexch * h->esz +
            sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq + h->esz * (size_t)h->n_probes * h->decim +
            sizeof(uint64_t);
     return MBF_OK;
@@ -993,11 +1062,11 @@ int mbf_save_state(mbf_handle* h, void* buf, size_t n) {
     HIPCHK(h, hipMemcpy(&hd.ctl, h->ctl, sizeof(mbf::Ctl), hipMemcpyDeviceToHost));
     std::memcpy(p, &hd, sizeof(hd));
     size_t off = sizeof(hd);
-    const size_t fb = (size_t)h->nsite * h->esz;
+    const size_t fb = (size_t)h->nexch * h->esz;
     for (int id = 0; id < MBF_NFIELDS; ++id) {
         void* src = nullptr;
         field_array(h, id, h->step, false, &src);
-        HIPCHK(h, hipMemcpy(p + off, src, fb, hipMemcpyDeviceToHost));
+        HIPCHK(h, copy_sites(h, p + off, src, false, hipMemcpyDeviceToHost, false));
         off += fb;
     }
     if (h->n_probes > 0) {
@@ -1032,14 +1101,14 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
     if (!h->have_material) return fail(h, MBF_ESTATE, "set the material first");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     size_t off = sizeof(hd);
-    const size_t fb = (size_t)h->nsite * h->esz;
+    const size_t fb = (size_t)h->nexch * h->esz;
     for (int id = 0; id < MBF_NFIELDS; ++id) {
         void* dst = nullptr;
         field_array(h, id, hd.step, true, &dst);
-        HIPCHK(h, hipMemcpy(dst, p + off, fb, hipMemcpyHostToDevice));
+        HIPCHK(h, copy_sites(h, dst, p + off, true, hipMemcpyHostToDevice, false));
         if (id < 6) {
             field_array(h, id, hd.step + 1, true, &dst);
-            HIPCHK(h, hipMemcpy(dst, p + off, fb, hipMemcpyHostToDevice));
+            HIPCHK(h, copy_sites(h, dst, p + off, true, hipMemcpyHostToDevice, false));
         }
         off += fb;
     }
@@ -1059,7 +1128,7 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
     h->co = h->cfg.precision == MBF_FP64 ? make_coef<double>(h->cfg, hd.Na_si)
                                           : make_coef<float>(h->cfg, hd.Na_si);
     drop_graph(h);
-    return MBF_OK;
+    return init_source(h);
 }
 
 }  // extern "C"

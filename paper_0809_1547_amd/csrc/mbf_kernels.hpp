@@ -20,6 +20,7 @@ constexpr int kBlockY = 4;    // four waves per workgroup
 constexpr int kThreads = kBlockX * kBlockY;
 constexpr int kMaxMat = 256;
 constexpr int kMaxMurTasks = 12;
+constexpr int kZChunk = 8;    // planes per workgroup in the two-pass kernels
 
 struct Ctl {                  // per-simulation control block (device memory)
     int64_t step;             // steps taken since the pump was set
@@ -28,6 +29,7 @@ struct Ctl {                  // per-simulation control block (device memory)
     double loss;              // loss-box integral
     int32_t nonfinite;        // set once a step produced a non-finite energy
     int32_t pad;
+    double src_val;           // soft-source value added during the current step
 };
 
 template <typename T>
@@ -52,13 +54,15 @@ struct SimView {
     double src_amp, src_ws, src_tp, src_t0, dt;
     // loss box
     int box_on, box[6];
-    // first-order Mur: one task per (axis a, side, component c)
+    // first-order Mur: task q (a, side, c) packed in bits 5q..5q+4 of mur_code
+    // as a | side << 2 | c << 3; bit a of mur_axes set when axis a is Mur
     int n_mur;
-    int mur_a[kMaxMurTasks], mur_side[kMaxMurTasks], mur_c[kMaxMurTasks];
-    int bc[3];
+    uint64_t mur_code;
+    int mur_axes;
     // graded lossy layer: loss per site = prof[x][hx][i] + prof[y][hy][j] + prof[z][hz][k]
     // (index 1 = half-integer position along that axis)
     int has_layer;
+    int lay_L[3];             // layer depth on a lossy axis, -1 on other axes
     const T* prof[3][2];
     // monitors
     Ctl* ctl;
@@ -83,10 +87,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
-        const uint32_t lo0 = 0xD2511F53u * x0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
-        const uint32_t lo1 = 0xCD9E8D57u * x2;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;   // one v_mad_u64_u32 each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         const uint32_t y0 = hi1 ^ x1 ^ k0;
         const uint32_t y2 = hi0 ^ x3 ^ k1;
         x0 = y0;
@@ -106,14 +110,14 @@ __device__ __forceinline__ void box_muller3(uint32_t w0, uint32_t w1, uint32_t w
     const float u1 = ((float)(w1 >> 8) + 0.5f) * s;
     const float u2 = ((float)(w2 >> 8) + 0.5f) * s;
     const float u3 = ((float)(w3 >> 8) + 0.5f) * s;
-    const float r0 = sqrtf(-2.0f * logf(u0));
-    const float r1 = sqrtf(-2.0f * logf(u2));
-    float s1, c1, s3, c3;
-    sincospif(2.0f * u1, &s1, &c1);
-    sincospif(2.0f * u3, &s3, &c3);
-    xi[0] = r0 * c1;
-    xi[1] = r0 * s1;
-    xi[2] = r1 * c3;
+    // hardware transcendentals: log2, square root, and sin/cos of 2*pi*u
+    // (the sin/cos units take their argument in revolutions); u lies in (0,1)
+    const float ln2x2 = 1.3862943611198906f;     // 2 ln 2
+    const float r0 = __builtin_amdgcn_sqrtf(-ln2x2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(-ln2x2 * __builtin_amdgcn_logf(u2));
+    xi[0] = r0 * __builtin_amdgcn_cosf(u1);
+    xi[1] = r0 * __builtin_amdgcn_sinf(u1);
+    xi[2] = r1 * __builtin_amdgcn_cosf(u3);
 }
 
 __device__ __forceinline__ void box_muller3(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
@@ -125,9 +129,8 @@ __device__ __forceinline__ void box_muller3(uint32_t w0, uint32_t w1, uint32_t w
     const double u3 = ((double)(w3 >> 8) + 0.5) * s;
     const double r0 = sqrt(-2.0 * log(u0));
     const double r1 = sqrt(-2.0 * log(u2));
-    double s1, c1, s3, c3;
-    sincospi(2.0 * u1, &s1, &c1);
-    sincospi(2.0 * u3, &s3, &c3);
+    const double c1 = cospi(2.0 * u1), s1 = sinpi(2.0 * u1);
+    const double c3 = cospi(2.0 * u3);
     xi[0] = r0 * c1;
     xi[1] = r0 * s1;
     xi[2] = r1 * c3;
@@ -162,6 +165,40 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
     return r;
 }
 
+// Field pointers of one step, chosen once per kernel from the step parity
+// (uniform selects; the kernel-argument arrays are only ever indexed with
+// compile-time constants, so nothing is copied to private memory).
+template <typename T>
+struct Fields {
+    const T* e[3];    // E^n
+    T* en[3];         // E^{n+1}
+    const T* h[3];    // H^{n-1/2}
+    T* hn[3];         // H^{n+1/2}
+    const T* p[3];    // P^n
+    T* q[3];          // P^{n-1} on entry, P^{n+1} on exit
+    T* n1[3];
+    T* n2[3];
+    T* n3[3];
+};
+
+template <typename T>
+__device__ __forceinline__ Fields<T> bind_fields(const SimView<T>& v, int par) {
+    Fields<T> f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        f.e[c] = par ? v.E[1][c] : v.E[0][c];
+        f.en[c] = par ? v.E[0][c] : v.E[1][c];
+        f.h[c] = par ? v.H[1][c] : v.H[0][c];
+        f.hn[c] = par ? v.H[0][c] : v.H[1][c];
+        f.p[c] = par ? v.P[1][c] : v.P[0][c];
+        f.q[c] = par ? v.P[0][c] : v.P[1][c];
+        f.n1[c] = v.N[0][c];
+        f.n2[c] = v.N[1][c];
+        f.n3[c] = v.N[2][c];
+    }
+    return f;
+}
+
 // Loss of an E-site of component c (half position along c) and of an H-site
 // of component c (half positions along the two other axes).
 template <typename T>
@@ -175,11 +212,31 @@ __device__ __forceinline__ T loss_h(const SimView<T>& v, int c, int i, int j, in
 
 // Faraday update with the semi-implicit loss of the layer
 // (H' - H = -S curl - a (H' + H)); a = 0 is the plain Yee update.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Loads and stores at a 32-bit element offset from a uniform base: the
+// address is base + zero-extended 32-bit byte offset, which maps to the
+// scalar-base form of the global memory instructions.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, uint32_t off, T val) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off * (uint32_t)sizeof(T)) = val;
+}
+
+// True when every index in [lo, hi] along an axis lies outside its lossy layer.
+__device__ __forceinline__ bool clear_of_layer(int L, int n, int lo, int hi) {
+    return L < 0 || (lo >= L && hi <= n - L - 1);
+}
+
 template <typename T>
 __device__ __forceinline__ T h_update(T h, T S, T curl, T a) {
     if (a == (T)0) return h - S * curl;
-    const T ca = ((T)1 - a) / ((T)1 + a);
-    const T cb = (T)1 / ((T)1 + a);
+    const T cb = recip((T)1 + a);
+    const T ca = ((T)1 - a) * cb;
     return ca * h - cb * (S * curl);
 }
 
@@ -194,148 +251,200 @@ __device__ __forceinline__ T source_value(const SimView<T>& v, int64_t n) {
 // H^{n+1/2} = H^{n-1/2} - S curl+ E^n on the H-sites of [0,n)^3, plus the
 // energy W^n = 1/2 [sum eps E^n^2 (interior E-sites) + sum H^{n-1/2}.H^{n+1/2}
 // (H-sites off the wall normal to their component)].
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_curl_h(SimView<T> v) {
-    __shared__ double sh[kThreads / 64];
-    const int i = blockIdx.x * kBlockX + threadIdx.x;
-    const int j = blockIdx.y * kBlockY + threadIdx.y;
-    const int k = blockIdx.z;
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, int zchunk) {
+    __shared__ double sh[TY];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
     const int par = (int)(n & 1);
-    double w = 0.0;
+    const Fields<T> f = bind_fields(v, par);
+    T wsum = (T)0;
+    const int kz0 = blockIdx.z * zchunk, kz1 = min(kz0 + zchunk, v.nz);
     if (i < v.nx && j < v.ny) {
-        const T* __restrict__ Ex = v.E[par][0];
-        const T* __restrict__ Ey = v.E[par][1];
-        const T* __restrict__ Ez = v.E[par][2];
-        const int64_t x = i + v.sx * j + v.sxy * k;
-        const T ex = Ex[x], ey = Ey[x], ez = Ez[x];
-        const T cx = (Ez[x + v.sx] - ez) - (Ey[x + v.sxy] - ey);
-        const T cy = (Ex[x + v.sxy] - ex) - (Ez[x + 1] - ez);
-        const T cz = (Ey[x + 1] - ey) - (Ex[x + v.sx] - ex);
-        const T hx = v.H[par][0][x], hy = v.H[par][1][x], hz = v.H[par][2][x];
-        T ax = (T)0, ay = (T)0, az = (T)0;
-        if (v.has_layer) {
-            ax = loss_h(v, 0, i, j, k);
-            ay = loss_h(v, 1, i, j, k);
-            az = loss_h(v, 2, i, j, k);
+        const T* __restrict__ Ex = f.e[0];
+        const T* __restrict__ Ey = f.e[1];
+        const T* __restrict__ Ez = f.e[2];
+        const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+        uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
+        // E^n at plane k is carried from the previous plane's k+1 loads
+        T ex = ldo(Ex, x), ey = ldo(Ey, x);
+        for (int k = kz0; k < kz1; ++k, x += sxy) {
+            const T ez = ldo(Ez, x);
+            const T exk = ldo(Ex, x + sxy), eyk = ldo(Ey, x + sxy);
+            const T cx = (ldo(Ez, x + sx) - ez) - (eyk - ey);
+            const T cy = (exk - ex) - (ldo(Ez, x + 1u) - ez);
+            const T cz = (ldo(Ey, x + 1u) - ey) - (ldo(Ex, x + sx) - ex);
+            const T hx = ldo(f.h[0], x), hy = ldo(f.h[1], x), hz = ldo(f.h[2], x);
+            T ax = (T)0, ay = (T)0, az = (T)0;
+            if (v.has_layer) {
+                ax = loss_h(v, 0, i, j, k);
+                ay = loss_h(v, 1, i, j, k);
+                az = loss_h(v, 2, i, j, k);
+            }
+            const T nhx = h_update(hx, v.S, cx, ax);
+            const T nhy = h_update(hy, v.S, cy, ay);
+            const T nhz = h_update(hz, v.S, cz, az);
+            sto(f.hn[0], x, nhx);
+            sto(f.hn[1], x, nhy);
+            sto(f.hn[2], x, nhz);
+            const T eps = v.lut_eps[ldo(v.mat, x)];
+            T acc = (T)0;
+            if (j >= 1 && k >= 1) acc += eps * ex * ex;
+            if (i >= 1 && k >= 1) acc += eps * ey * ey;
+            if (i >= 1 && j >= 1) acc += eps * ez * ez;
+            if (i >= 1) acc += hx * nhx;
+            if (j >= 1) acc += hy * nhy;
+            if (k >= 1) acc += hz * nhz;
+            wsum += (T)0.5 * acc;
+            ex = exk;
+            ey = eyk;
         }
-        const T nhx = h_update(hx, v.S, cx, ax);
-        const T nhy = h_update(hy, v.S, cy, ay);
-        const T nhz = h_update(hz, v.S, cz, az);
-        v.H[par ^ 1][0][x] = nhx;
-        v.H[par ^ 1][1][x] = nhy;
-        v.H[par ^ 1][2][x] = nhz;
-        const T eps = v.lut_eps[v.mat[x]];
-        T acc = (T)0;
-        if (j >= 1 && k >= 1) acc += eps * ex * ex;
-        if (i >= 1 && k >= 1) acc += eps * ey * ey;
-        if (i >= 1 && j >= 1) acc += eps * ez * ez;
-        if (i >= 1) acc += hx * nhx;
-        if (j >= 1) acc += hy * nhy;
-        if (k >= 1) acc += hz * nhz;
-        w = 0.5 * (double)acc;
     }
-    const double s = block_sum(w, sh);
+    const double s = block_sum((double)wsum, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0)
         v.e_part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
 }
 
 // ---------------------------------------------------- rows a2, a3, a4, a5
+// Per-site Bloch state of one E-site: P^n, P^{n-1} and N1..N3 (zero where
+// the site carries no gain).  Loaded ahead of the update so that the loads are
+// in flight while the field part of the step is computed.
 template <typename T>
-__device__ __forceinline__ void bloch_site(const SimView<T>& v, int c, int64_t x, T e, T curl,
-                                           T ie, bool gain, T xi, T src, T* out_e, int par,
-                                           T loss) {
-    T dP = (T)0;
-    T P = (T)0, Pn = (T)0;
-    T n1 = (T)0, n2 = (T)0, n3 = (T)0;
+struct BlochIn {
+    T P, Pp, n1, n2, n3;
+};
+
+template <typename T>
+__device__ __forceinline__ BlochIn<T> bloch_load(const Fields<T>& f, int c, uint32_t x, bool gain) {
+    BlochIn<T> b{(T)0, (T)0, (T)0, (T)0, (T)0};
     if (gain) {
-        P = v.P[par][c][x];
-        const T Pp = v.P[par ^ 1][c][x];
-        n1 = v.N[0][c][x];
-        n2 = v.N[1][c][x];
-        n3 = v.N[2][c][x];
-        Pn = v.a * P + v.b * Pp + v.ck * (n1 - n2) * e + v.cF * xi;
-        dP = Pn - P;
+        b.P = ldo(f.p[c], x);
+        b.Pp = ldo(f.q[c], x);
+        b.n1 = ldo(f.n1[c], x);
+        b.n2 = ldo(f.n2[c], x);
+        b.n3 = ldo(f.n3[c], x);
+    }
+    return b;
+}
+
+// Rows a2-a5 at one E-site from its loaded Bloch state.  `upd` marks an
+// interior site (updated by Ampere's law; other sites keep E), `gain` an
+// interior site of a gain cell.  Returns E^{n+1}.
+template <typename T>
+__device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f, int c, uint32_t x,
+                                        T e, T curl, T ie, bool upd, bool gain,
+                                        const BlochIn<T>& b, T xi, T src, T loss) {
+    T dP = (T)0;
+    T Pn = (T)0;
+    if (gain) {
+        Pn = v.a * b.P + v.b * b.Pp + v.ck * (b.n1 - b.n2) * e + v.cF * xi;
+        dP = Pn - b.P;
     }
     T en;
     if (loss == (T)0) {
         en = e + ie * (v.S * curl - dP);
     } else {
         // semi-implicit loss of the layer: (E' - E) = (1/eps)(S curl - dP) - a (E' + E)
-        const T ca = ((T)1 - loss) / ((T)1 + loss);
-        const T cb = (T)1 / ((T)1 + loss);
+        const T cb = recip((T)1 + loss);
+        const T ca = ((T)1 - loss) * cb;
         en = ca * e + cb * (ie * (v.S * curl - dP));
     }
     en += src;
+    en = upd ? en : e;
     if (gain) {
-        v.P[par ^ 1][c][x] = Pn;
+        sto(f.q[c], x, Pn);
         if (!v.frozen_pop) {
+            const T n1 = b.n1, n2 = b.n2, n3 = b.n3;
             const T W = v.beta * ((T)0.5 * (en + e)) * dP;
             const T n0 = v.Na - n1 - n2 - n3;
-            v.N[2][c][x] = n3 + (v.dtWp * n0 - v.dt32 * n3);
-            v.N[1][c][x] = n2 + (v.dt32 * n3 - v.dt21 * n2) + W;
-            v.N[0][c][x] = n1 + (v.dt21 * n2 - v.dt10 * n1) - W;
+            sto(f.n3[c], x, n3 + (v.dtWp * n0 - v.dt32 * n3));
+            sto(f.n2[c], x, n2 + (v.dt32 * n3 - v.dt21 * n2) + W);
+            sto(f.n1[c], x, n1 + (v.dt21 * n2 - v.dt10 * n1) - W);
         }
     }
-    *out_e = en;
+    return en;
 }
 
+// The soft source's value for component c at this site (zero elsewhere).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_curl_e(SimView<T> v) {
-    __shared__ double sh[kThreads / 64];
-    const int i = blockIdx.x * kBlockX + threadIdx.x;
-    const int j = blockIdx.y * kBlockY + threadIdx.y;
-    const int k = blockIdx.z;
+__device__ __forceinline__ void source3(const SimView<T>& v, int i, int j, int k, int64_t n,
+                                        T& s0, T& s1, T& s2) {
+    s0 = s1 = s2 = (T)0;
+    (void)n;
+    if (v.src_on && i == v.src_i && j == v.src_j && k == v.src_k) {
+        const T sv = (T)v.ctl->src_val;
+        s0 = v.src_comp == 0 ? sv : (T)0;
+        s1 = v.src_comp == 1 ? sv : (T)0;
+        s2 = v.src_comp == 2 ? sv : (T)0;
+    }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
+    __shared__ double sh[TY];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
     const int par = (int)(n & 1);
+    const Fields<T> f = bind_fields(v, par);
     double lsum = 0.0;
+    const int kz0 = blockIdx.z * zchunk, kz1 = min(kz0 + zchunk, v.nz);
     if (i < v.nx && j < v.ny) {
-        const int64_t x = i + v.sx * j + v.sxy * k;
-        const T* __restrict__ Hx = v.H[par ^ 1][0];
-        const T* __restrict__ Hy = v.H[par ^ 1][1];
-        const T* __restrict__ Hz = v.H[par ^ 1][2];
-        const uint8_t m = v.mat[x];
-        const T ie = v.lut_inv_eps[m];
-        const bool g = v.lut_gain[m] != 0;
-        const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-        T xi[3] = {(T)0, (T)0, (T)0};
-        if (g && v.noise && (inx || iny || inz)) {
-            const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
-            noise3(v, cell, (uint32_t)n, xi);
+        const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+        const T* __restrict__ Hx = f.hn[0];
+        const T* __restrict__ Hy = f.hn[1];
+        const T* __restrict__ Hz = f.hn[2];
+        uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
+        uint8_t m_next = ldo(v.mat, x);
+        // H^{n+1/2} at plane k-1 is carried from the previous plane
+        T hxm = kz0 >= 1 ? ldo(Hx, x - sxy) : (T)0;
+        T hym = kz0 >= 1 ? ldo(Hy, x - sxy) : (T)0;
+        for (int k = kz0; k < kz1; ++k, x += sxy) {
+            const uint8_t m = m_next;
+            if (k + 1 < kz1) m_next = ldo(v.mat, x + sxy);     // one plane ahead
+            const T ie = v.lut_inv_eps[m];
+            const bool g = v.lut_gain[m] != 0;
+            const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
+            const BlochIn<T> b0 = bloch_load(f, 0, x, g && inx);
+            const BlochIn<T> b1 = bloch_load(f, 1, x, g && iny);
+            const BlochIn<T> b2 = bloch_load(f, 2, x, g && inz);
+            const T hx = ldo(Hx, x), hy = ldo(Hy, x), hz = ldo(Hz, x);
+            T xi[3] = {(T)0, (T)0, (T)0};
+            if (g && v.noise && (inx || iny || inz)) {
+                const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
+                noise3(v, cell, (uint32_t)n, xi);
+            }
+            T s0, s1, s2;
+            source3(v, i, j, k, n, s0, s1, s2);
+            T acc = (T)0;
+            {
+                const T curl = inx ? (hz - ldo(Hz, x - sx)) - (hy - hym) : (T)0;
+                const T en = bloch_site(v, f, 0, x, ldo(f.e[0], x), curl, ie, inx, g && inx, b0, xi[0], s0,
+                                        v.has_layer ? loss_e(v, 0, i, j, k) : (T)0);
+                sto(f.en[0], x, en);
+                if (inx) acc += en * en;
+            }
+            {
+                const T curl = iny ? (hx - hxm) - (hz - ldo(Hz, x - 1u)) : (T)0;
+                const T en = bloch_site(v, f, 1, x, ldo(f.e[1], x), curl, ie, iny, g && iny, b1, xi[1], s1,
+                                        v.has_layer ? loss_e(v, 1, i, j, k) : (T)0);
+                sto(f.en[1], x, en);
+                if (iny) acc += en * en;
+            }
+            {
+                const T curl = inz ? (hy - ldo(Hy, x - 1u)) - (hx - ldo(Hx, x - sx)) : (T)0;
+                const T en = bloch_site(v, f, 2, x, ldo(f.e[2], x), curl, ie, inz, g && inz, b2, xi[2], s2,
+                                        v.has_layer ? loss_e(v, 2, i, j, k) : (T)0);
+                sto(f.en[2], x, en);
+                if (inz) acc += en * en;
+            }
+            if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
+                k >= v.box[2] && k < v.box[5])
+                lsum += (double)acc;
+            hxm = hx;
+            hym = hy;
         }
-        T srcv[3] = {(T)0, (T)0, (T)0};
-        if (v.src_on && i == v.src_i && j == v.src_j && k == v.src_k) srcv[v.src_comp] = source_value(v, n);
-        const bool inbox = v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] &&
-                           j < v.box[4] && k >= v.box[2] && k < v.box[5];
-        T acc = (T)0;
-        if (inx) {
-            const T hz = Hz[x], hy = Hy[x];
-            const T curl = (hz - Hz[x - v.sx]) - (hy - Hy[x - v.sxy]);
-            T en;
-            bloch_site(v, 0, x, v.E[par][0][x], curl, ie, g, xi[0], srcv[0], &en, par,
-                       v.has_layer ? loss_e(v, 0, i, j, k) : (T)0);
-            v.E[par ^ 1][0][x] = en;
-            acc += en * en;
-        }
-        if (iny) {
-            const T hx = Hx[x], hz = Hz[x];
-            const T curl = (hx - Hx[x - v.sxy]) - (hz - Hz[x - 1]);
-            T en;
-            bloch_site(v, 1, x, v.E[par][1][x], curl, ie, g, xi[1], srcv[1], &en, par,
-                       v.has_layer ? loss_e(v, 1, i, j, k) : (T)0);
-            v.E[par ^ 1][1][x] = en;
-            acc += en * en;
-        }
-        if (inz) {
-            const T hy = Hy[x], hx = Hx[x];
-            const T curl = (hy - Hy[x - 1]) - (hx - Hx[x - v.sx]);
-            T en;
-            bloch_site(v, 2, x, v.E[par][2][x], curl, ie, g, xi[2], srcv[2], &en, par,
-                       v.has_layer ? loss_e(v, 2, i, j, k) : (T)0);
-            v.E[par ^ 1][2][x] = en;
-            acc += en * en;
-        }
-        if (inbox) lsum = (double)acc;
     }
     if (v.box_on) {
         const double s = block_sum(lsum, sh);
@@ -370,6 +479,34 @@ __device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
     return x * q + (x < r ? x : r) + idx;
 }
 
+// Stage E^n of plane k over x0-1 .. x0+64, y0-1 .. y0+TY into LDS (zero
+// outside the stored range).  Wave w copies rows w, w+TY, ...; lane l copies
+// column l and lanes 0 and 1 also the last two columns.
+template <typename T, int TY>
+__device__ __forceinline__ void stage_plane(T (*dst)[TY + 2][66], const T* __restrict__ E0,
+                                            const T* __restrict__ E1, const T* __restrict__ E2,
+                                            int k, int x0, int y0, int nx, int ny, int nz,
+                                            uint32_t sx, uint32_t sxy, int tx, int ty) {
+    constexpr int LY = TY + 2;
+    const bool kin = k <= nz;
+    for (int r = ty; r < 3 * LY; r += TY) {
+        const int c = r >= 2 * LY ? 2 : (r >= LY ? 1 : 0);
+        const int ly = r - c * LY;
+        const T* __restrict__ src = c == 0 ? E0 : (c == 1 ? E1 : E2);
+        const int gy = y0 - 1 + ly;
+        const bool rin = kin && gy >= 0 && gy <= ny;
+        const uint32_t row = sx * (uint32_t)gy + sxy * (uint32_t)k;
+        {
+            const int gx = x0 - 1 + tx;
+            dst[c][ly][tx] = (rin && gx >= 0 && gx <= nx) ? ldo(src, row + (uint32_t)gx) : (T)0;
+        }
+        if (tx < 2) {
+            const int gx = x0 + 63 + tx;
+            dst[c][ly][64 + tx] = (rin && gx <= nx) ? ldo(src, row + (uint32_t)gx) : (T)0;
+        }
+    }
+}
+
 template <typename T, int TY>
 __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom g) {
     constexpr int TX = 64;
@@ -391,48 +528,51 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
     const bool act = i < v.nx && j < v.ny;
     const int64_t n = v.ctl->step;
     const int par = (int)(n & 1);
-    const T* __restrict__ E0 = v.E[par][0];
-    const T* __restrict__ E1 = v.E[par][1];
-    const T* __restrict__ E2 = v.E[par][2];
+    const Fields<T> f = bind_fields(v, par);
+    const int nx = v.nx, ny = v.ny, nz = v.nz;
+    const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+    // lossy-layer look-ups only where the tile can reach the layer
+    const bool lay_xy = v.has_layer && !(clear_of_layer(v.lay_L[0], nx, x0 - 1, x0 + TX) &&
+                                         clear_of_layer(v.lay_L[1], ny, y0 - 1, y0 + TY));
 
-    auto load_plane = [&](int buf, int k) {
-        const int tot = 3 * LY * LX;
-        for (int q = tid; q < tot; q += TX * TY) {
-            const int c = q / (LY * LX);
-            const int r = q % (LY * LX);
-            const int ly = r / LX, lx = r % LX;
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-            T val = (T)0;
-            if (k <= v.nz && gx >= 0 && gx <= v.nx && gy >= 0 && gy <= v.ny) {
-                const int64_t x = gx + v.sx * gy + v.sxy * k;
-                val = (c == 0 ? E0 : (c == 1 ? E1 : E2))[x];
-            }
-            se[buf][c][ly][lx] = val;
-        }
-    };
-
-    double wsum = 0.0, lsum = 0.0;
+    T wsum = (T)0;
+    double lsum = 0.0;
     T hxp = (T)0, hyp = (T)0;
     const int kstart = z0 > 0 ? z0 - 1 : z0;
     int cur = 0;
-    load_plane(cur, kstart);
+    const uint32_t xij = (uint32_t)i + sx * (uint32_t)j;
+    uint8_t m_next = act ? ldo(v.mat, xij + sxy * (uint32_t)kstart) : 0;
+    stage_plane<T, TY>(se[cur], f.e[0], f.e[1], f.e[2], kstart, x0, y0, nx, ny, nz, sx, sxy, tx, ty);
     for (int k = kstart; k < z1; ++k) {
         const int nxt = cur ^ 1;
-        load_plane(nxt, k + 1);
-        __syncthreads();
         const bool own = k >= z0;
+        // the Bloch state of this plane and the next material byte are loaded
+        // first, so they arrive while E is staged and H is formed
+        const uint8_t m = m_next;
+        if (act && k + 1 < z1) m_next = ldo(v.mat, xij + sxy * (uint32_t)(k + 1));
+        const bool gn = v.lut_gain[m] != 0;
+        const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
+        const uint32_t xo = xij + sxy * (uint32_t)k;
+        const bool ld = own && act && gn;
+        const BlochIn<T> b0 = bloch_load(f, 0, xo, ld && inx);
+        const BlochIn<T> b1 = bloch_load(f, 1, xo, ld && iny);
+        const BlochIn<T> b2 = bloch_load(f, 2, xo, ld && inz);
+        stage_plane<T, TY>(se[nxt], f.e[0], f.e[1], f.e[2], k + 1, x0, y0, nx, ny, nz, sx, sxy, tx, ty);
+        __syncthreads();
+        const bool lay = lay_xy || (v.has_layer && !clear_of_layer(v.lay_L[2], nz, k, k));
+        const uint32_t xk = sxy * (uint32_t)k;
         // ---- a1: H^{n+1/2} at plane k
         T nhx = (T)0, nhy = (T)0, nhz = (T)0;
         const int ly = ty + 1, lx = tx + 1;
         if (act) {
-            const int64_t x = i + v.sx * j + v.sxy * k;
+            const uint32_t x = (uint32_t)i + sx * (uint32_t)j + xk;
             const T ex = se[cur][0][ly][lx], ey = se[cur][1][ly][lx], ez = se[cur][2][ly][lx];
             const T cx = (se[cur][2][ly + 1][lx] - ez) - (se[nxt][1][ly][lx] - ey);
             const T cy = (se[nxt][0][ly][lx] - ex) - (se[cur][2][ly][lx + 1] - ez);
             const T cz = (se[cur][1][ly][lx + 1] - ey) - (se[cur][0][ly + 1][lx] - ex);
-            const T hx = v.H[par][0][x], hy = v.H[par][1][x], hz = v.H[par][2][x];
+            const T hx = ldo(f.h[0], x), hy = ldo(f.h[1], x), hz = ldo(f.h[2], x);
             T ax = (T)0, ay = (T)0, az = (T)0;
-            if (v.has_layer) {
+            if (lay) {
                 ax = loss_h(v, 0, i, j, k);
                 ay = loss_h(v, 1, i, j, k);
                 az = loss_h(v, 2, i, j, k);
@@ -441,10 +581,10 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
             nhy = h_update(hy, v.S, cy, ay);
             nhz = h_update(hz, v.S, cz, az);
             if (own) {
-                v.H[par ^ 1][0][x] = nhx;
-                v.H[par ^ 1][1][x] = nhy;
-                v.H[par ^ 1][2][x] = nhz;
-                const T eps = v.lut_eps[v.mat[x]];
+                sto(f.hn[0], x, nhx);
+                sto(f.hn[1], x, nhy);
+                sto(f.hn[2], x, nhz);
+                const T eps = v.lut_eps[ldo(v.mat, x)];
                 T acc = (T)0;
                 if (j >= 1 && k >= 1) acc += eps * ex * ex;
                 if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -452,76 +592,69 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
                 if (i >= 1) acc += hx * nhx;
                 if (j >= 1) acc += hy * nhy;
                 if (k >= 1) acc += hz * nhz;
-                wsum += 0.5 * (double)acc;
+                wsum += (T)0.5 * acc;
             }
         }
         sh[0][ly][lx] = nhx;
         sh[1][ly][lx] = nhy;
         sh[2][ly][lx] = nhz;
         // low-side halo row (i, y0-1): Hx and Hz
-        if (ty == 0 && y0 > 0 && i < v.nx) {
-            const int64_t x = i + v.sx * (y0 - 1) + v.sxy * k;
+        if (ty == 0 && y0 > 0 && i < nx) {
+            const uint32_t x = (uint32_t)i + sx * (uint32_t)(y0 - 1) + xk;
             const T ex = se[cur][0][0][lx], ey = se[cur][1][0][lx], ez = se[cur][2][0][lx];
             const T cx = (se[cur][2][1][lx] - ez) - (se[nxt][1][0][lx] - ey);
             const T cz = (se[cur][1][0][lx + 1] - ey) - (se[cur][0][1][lx] - ex);
-            const T ax = v.has_layer ? loss_h(v, 0, i, y0 - 1, k) : (T)0;
-            const T az = v.has_layer ? loss_h(v, 2, i, y0 - 1, k) : (T)0;
-            sh[0][0][lx] = h_update(v.H[par][0][x], v.S, cx, ax);
-            sh[2][0][lx] = h_update(v.H[par][2][x], v.S, cz, az);
+            const T ax = lay ? loss_h(v, 0, i, y0 - 1, k) : (T)0;
+            const T az = lay ? loss_h(v, 2, i, y0 - 1, k) : (T)0;
+            sh[0][0][lx] = h_update(ldo(f.h[0], x), v.S, cx, ax);
+            sh[2][0][lx] = h_update(ldo(f.h[2], x), v.S, cz, az);
         }
         // low-side halo column (x0-1, j): Hy and Hz
-        if (ty == 1 && tx < TY && x0 > 0 && y0 + tx < v.ny) {
+        if (ty == 1 && tx < TY && x0 > 0 && y0 + tx < ny) {
             const int hj = y0 + tx;
             const int hly = tx + 1;
-            const int64_t x = (x0 - 1) + v.sx * hj + v.sxy * k;
+            const uint32_t x = (uint32_t)(x0 - 1) + sx * (uint32_t)hj + xk;
             const T ex = se[cur][0][hly][0], ey = se[cur][1][hly][0], ez = se[cur][2][hly][0];
             const T cy = (se[nxt][0][hly][0] - ex) - (se[cur][2][hly][1] - ez);
             const T cz = (se[cur][1][hly][1] - ey) - (se[cur][0][hly + 1][0] - ex);
-            const T ay = v.has_layer ? loss_h(v, 1, x0 - 1, hj, k) : (T)0;
-            const T az = v.has_layer ? loss_h(v, 2, x0 - 1, hj, k) : (T)0;
-            sh[1][hly][0] = h_update(v.H[par][1][x], v.S, cy, ay);
-            sh[2][hly][0] = h_update(v.H[par][2][x], v.S, cz, az);
+            const T ay = lay ? loss_h(v, 1, x0 - 1, hj, k) : (T)0;
+            const T az = lay ? loss_h(v, 2, x0 - 1, hj, k) : (T)0;
+            sh[1][hly][0] = h_update(ldo(f.h[1], x), v.S, cy, ay);
+            sh[2][hly][0] = h_update(ldo(f.h[2], x), v.S, cz, az);
         }
         __syncthreads();
         // ---- a2..a5 at plane k
         if (own && act) {
-            const int64_t x = i + v.sx * j + v.sxy * k;
-            const uint8_t m = v.mat[x];
+            const uint32_t x = xo;
             const T ie = v.lut_inv_eps[m];
-            const bool gn = v.lut_gain[m] != 0;
-            const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
             T xi[3] = {(T)0, (T)0, (T)0};
             if (gn && v.noise && (inx || iny || inz)) {
-                const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
+                const uint32_t cell = (uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k);
                 noise3(v, cell, (uint32_t)n, xi);
             }
-            T srcv[3] = {(T)0, (T)0, (T)0};
-            if (v.src_on && i == v.src_i && j == v.src_j && k == v.src_k)
-                srcv[v.src_comp] = source_value(v, n);
+            T s0, s1, s2;
+            source3(v, i, j, k, n, s0, s1, s2);
             T acc = (T)0;
-            if (inx) {
+            {
                 const T curl = (sh[2][ly][lx] - sh[2][ly - 1][lx]) - (sh[1][ly][lx] - hyp);
-                T en;
-                bloch_site(v, 0, x, se[cur][0][ly][lx], curl, ie, gn, xi[0], srcv[0], &en, par,
-                           v.has_layer ? loss_e(v, 0, i, j, k) : (T)0);
-                v.E[par ^ 1][0][x] = en;
-                acc += en * en;
+                const T en = bloch_site(v, f, 0, x, se[cur][0][ly][lx], curl, ie, inx, gn && inx, b0,
+                                        xi[0], s0, lay ? loss_e(v, 0, i, j, k) : (T)0);
+                sto(f.en[0], x, en);
+                if (inx) acc += en * en;
             }
-            if (iny) {
+            {
                 const T curl = (sh[0][ly][lx] - hxp) - (sh[2][ly][lx] - sh[2][ly][lx - 1]);
-                T en;
-                bloch_site(v, 1, x, se[cur][1][ly][lx], curl, ie, gn, xi[1], srcv[1], &en, par,
-                           v.has_layer ? loss_e(v, 1, i, j, k) : (T)0);
-                v.E[par ^ 1][1][x] = en;
-                acc += en * en;
+                const T en = bloch_site(v, f, 1, x, se[cur][1][ly][lx], curl, ie, iny, gn && iny, b1,
+                                        xi[1], s1, lay ? loss_e(v, 1, i, j, k) : (T)0);
+                sto(f.en[1], x, en);
+                if (iny) acc += en * en;
             }
-            if (inz) {
+            {
                 const T curl = (sh[1][ly][lx] - sh[1][ly][lx - 1]) - (sh[0][ly][lx] - sh[0][ly - 1][lx]);
-                T en;
-                bloch_site(v, 2, x, se[cur][2][ly][lx], curl, ie, gn, xi[2], srcv[2], &en, par,
-                           v.has_layer ? loss_e(v, 2, i, j, k) : (T)0);
-                v.E[par ^ 1][2][x] = en;
-                acc += en * en;
+                const T en = bloch_site(v, f, 2, x, se[cur][2][ly][lx], curl, ie, inz, gn && inz, b2,
+                                        xi[2], s2, lay ? loss_e(v, 2, i, j, k) : (T)0);
+                sto(f.en[2], x, en);
+                if (inz) acc += en * en;
             }
             if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
                 k >= v.box[2] && k < v.box[5])
@@ -532,7 +665,7 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
         __syncthreads();
         cur = nxt;
     }
-    const double ws = block_sum(wsum, red);
+    const double ws = block_sum((double)wsum, red);
     __syncthreads();
     const double ls = v.box_on ? block_sum(lsum, red) : 0.0;
     if (tid == 0) {
@@ -547,33 +680,46 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
 // on the wall of the third axis t belongs to the face applied last in x, y, z
 // order; when that is face a (t < a) the neighbour it reads is itself a
 // face-t site, whose new value is formed inline.  Sites on PEC walls stay 0.
+__device__ __forceinline__ int sel3(int a, int x0, int x1, int x2) {
+    return a == 0 ? x0 : (a == 1 ? x1 : x2);
+}
+__device__ __forceinline__ int64_t sel3(int a, int64_t x0, int64_t x1, int64_t x2) {
+    return a == 0 ? x0 : (a == 1 ? x1 : x2);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_mur(SimView<T> v) {
     const int task = blockIdx.y;
-    const int a = v.mur_a[task], side = v.mur_side[task], c = v.mur_c[task];
+    const int code = (int)((v.mur_code >> (5 * task)) & 31u);
+    const int a = code & 3, side = (code >> 2) & 1, c = (code >> 3) & 3;
     const int t = 3 - a - c;
-    const int nd[3] = {v.nx, v.ny, v.nz};
-    const int nc = nd[c], nt = nd[t] + 1;
+    const int na = sel3(a, v.nx, v.ny, v.nz), nc = sel3(c, v.nx, v.ny, v.nz);
+    const int ntd = sel3(t, v.nx, v.ny, v.nz);
+    const int nt = ntd + 1;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)nc * nt) return;
     const int u = (int)(q % nc);
     const int w = (int)(q / nc);
-    const bool on_t = (w == 0 || w == nd[t]);
-    if (on_t && (v.bc[t] != 1 || t > a)) return;
-    const int64_t par = v.ctl->step & 1;   // parity of the step being finished
-    const T* __restrict__ Ec = v.E[par][c];
-    T* __restrict__ En = v.E[par ^ 1][c];
-    const int64_t st[3] = {1, v.sx, v.sxy};
-    const int wall = side ? nd[a] : 0;
-    const int inner = side ? nd[a] - 1 : 1;
-    const int64_t s = (int64_t)wall * st[a] + (int64_t)u * st[c] + (int64_t)w * st[t];
-    const int64_t s1 = s + (int64_t)(inner - wall) * st[a];
+    const bool on_t = (w == 0 || w == ntd);
+    const bool t_is_mur = ((v.mur_axes >> t) & 1) != 0;
+    if (on_t && (!t_is_mur || t > a)) return;
+    const int par = (int)(v.ctl->step & 1);   // parity of the step being finished
+    const Fields<T> f = bind_fields(v, par);
+    const T* __restrict__ Ec = c == 0 ? f.e[0] : (c == 1 ? f.e[1] : f.e[2]);
+    T* __restrict__ En = c == 0 ? f.en[0] : (c == 1 ? f.en[1] : f.en[2]);
+    const int64_t sta = sel3(a, (int64_t)1, v.sx, v.sxy);
+    const int64_t stc = sel3(c, (int64_t)1, v.sx, v.sxy);
+    const int64_t stt = sel3(t, (int64_t)1, v.sx, v.sxy);
+    const int wall = side ? na : 0;
+    const int inner = side ? na - 1 : 1;
+    const int64_t s = (int64_t)wall * sta + (int64_t)u * stc + (int64_t)w * stt;
+    const int64_t s1 = s + (int64_t)(inner - wall) * sta;
     T e1new;
     if (!on_t) {
         e1new = En[s1];
     } else {
-        const int tin = (w == 0) ? 1 : nd[t] - 1;
-        const int64_t s2 = s1 + (int64_t)(tin - w) * st[t];
+        const int tin = (w == 0) ? 1 : ntd - 1;
+        const int64_t s2 = s1 + (int64_t)(tin - w) * stt;
         const T m1 = v.lut_mur[v.mat[s1]];
         e1new = Ec[s2] + m1 * (En[s2] - Ec[s1]);
     }
@@ -604,9 +750,12 @@ __global__ void __launch_bounds__(256) k_end_step(SimView<T> v) {
         __syncthreads();
         L = sh[0] + sh[1] + sh[2] + sh[3];
     }
-    const int par1 = (int)((n + 1) & 1);
-    for (int p = t; p < v.n_probes; p += 256)
-        v.ring[(int64_t)p * v.decim + (n % v.decim)] = v.E[par1][v.probe_comp[p]][v.probe_off[p]];
+    const Fields<T> f = bind_fields(v, (int)(n & 1));
+    for (int p = t; p < v.n_probes; p += 256) {
+        const int c = v.probe_comp[p];
+        const T* e = c == 0 ? f.en[0] : (c == 1 ? f.en[1] : f.en[2]);
+        v.ring[(int64_t)p * v.decim + (n % v.decim)] = e[v.probe_off[p]];
+    }
     if (t == 0) {
         if (!(W == W) || W - W != 0.0) v.ctl->nonfinite = 1;
         if (n < v.hist_cap) v.hist[n] = W;
@@ -614,7 +763,16 @@ __global__ void __launch_bounds__(256) k_end_step(SimView<T> v) {
         v.ctl->W_int += W;
         v.ctl->loss += L;
         v.ctl->step = n + 1;
+        v.ctl->src_val = v.src_on ? (double)source_value(v, n + 1) : 0.0;
     }
+}
+
+// Source value of the current step (after the pump, a checkpoint load or a
+// change of source), so that every step reads it from the control block.
+template <typename T>
+__global__ void k_source_init(SimView<T> v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        v.ctl->src_val = v.src_on ? (double)source_value(v, v.ctl->step) : 0.0;
 }
 
 // Fold `count` buffered probe samples into the FP64 spectrum; the samples

@@ -104,8 +104,8 @@ def _load():
         "mbf_load_state": (I, [P, VP, C.c_size_t]),
         "mbf_set_tuning": (I, [P, C.POINTER(mbf_tuning)]),
         "mbf_get_tuning": (I, [P, C.POINTER(mbf_tuning)]),
-        "mbf_step_timed": (I, [P, I64, dp, C.POINTER(C.c_int64)]),
-        "mbf_step_bytes": (I, [P, dp]),
+        "mbf_step_timed": (I, [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "mbf_step_bytes": (I, [P, C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -281,17 +281,19 @@ def mbf_get_tuning(h: int) -> mbf_tuning:
     return t
 
 
-def mbf_step_timed(h: int, n: int) -> Tuple[float, int]:
-    ms = C.c_double()
+def mbf_step_timed(h: int, n: int) -> Tuple[Tuple[float, float], int]:
+    """((ms of the first field kernel, ms of the second), steps)."""
+    ms = (C.c_double * 2)()
     cnt = C.c_int64()
-    _check(lib.mbf_step_timed(h, int(n), C.byref(ms), C.byref(cnt)), h)
-    return ms.value, cnt.value
+    _check(lib.mbf_step_timed(h, int(n), ms, C.byref(cnt)), h)
+    return (ms[0], ms[1]), cnt.value
 
 
-def mbf_step_bytes(h: int) -> float:
-    b = C.c_double()
-    _check(lib.mbf_step_bytes(h, C.byref(b)), h)
-    return b.value
+def mbf_step_bytes(h: int) -> Tuple[float, float, float]:
+    """Algorithmic bytes of (the step, the first field kernel, the second)."""
+    b = (C.c_double * 3)()
+    _check(lib.mbf_step_bytes(h, b), h)
+    return b[0], b[1], b[2]
 
 
 # ------------------------------------------------------------ convenience

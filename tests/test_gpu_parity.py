@@ -46,8 +46,39 @@ def pair(n, *, bc=("pec",) * 3, init="prepumped", Na=2e24, eps=None, gain=None,
     return sim, ora
 
 
+GROUPS = [(0, 1, 2), (3, 4, 5), (6, 7, 8), (9, 10, 11), (12, 13, 14), (15, 16, 17), (18, 19, 20)]
+
+
 def worst(sim, ora, fids=range(9)):
-    return max(rel(sim.field(f), ora.field(f)) for f in fids)
+    """Largest relative L2 error over the vector fields (E, H, P, P_prev, N1,
+    N2, N3: the three components of a field form one vector) among fids."""
+    out = 0.0
+    for grp in GROUPS:
+        ids = [f for f in grp if f in fids]
+        if not ids:
+            continue
+        num = sum(float(np.sum((sim.field(f).astype(np.float64) - ora.field(f)) ** 2)) for f in ids)
+        den = sum(float(np.sum(ora.field(f) ** 2)) for f in ids)
+        out = max(out, math.sqrt(num / den) if den > 0 else math.sqrt(num))
+    return out
+
+
+class PeakNorm:
+    """Error of a run whose field decays (a pulse leaving through absorbing
+    walls): ||gpu - oracle|| over the largest oracle norm seen so far, per
+    field group, since the norm of the current field goes to zero."""
+
+    def __init__(self):
+        self.peak = {}
+
+    def __call__(self, sim, ora, groups=((0, 1, 2), (3, 4, 5))):
+        out = 0.0
+        for grp in groups:
+            num = sum(float(np.sum((sim.field(f).astype(np.float64) - ora.field(f)) ** 2)) for f in grp)
+            den = math.sqrt(sum(float(np.sum(ora.field(f) ** 2)) for f in grp))
+            self.peak[grp] = max(self.peak.get(grp, 0.0), den)
+            out = max(out, math.sqrt(num) / self.peak[grp] if self.peak[grp] > 0 else math.sqrt(num))
+        return out
 
 
 def c1_material():
@@ -66,8 +97,7 @@ def test_c1_fp32_parity_500_steps():
     print("C1 fp32 rel L2 per 50 steps:", ["%.2e" % e for e in errs])
     assert max(errs) <= TOL32
     # populations, energy history
-    for f in range(12, 21):
-        assert rel(sim.field(f), ora.field(f)) <= TOL32
+    assert worst(sim, ora, range(12, 21)) <= TOL32
     gh, oh = sim.energy_history(), ora.energy_history()
     assert gh.shape == oh.shape == (500,)
     assert gh[0] == oh[0] == 0.0
@@ -93,8 +123,7 @@ def test_noise_identity_fp64_single_step():
                     realization=5)
     sim.step(2)
     ora.step(2)
-    for f in (6, 7, 8):
-        assert rel(sim.field(f), ora.field(f)) <= 1e-13
+    assert worst(sim, ora, (6, 7, 8)) <= 1e-13
     assert np.abs(ora.field(6)).max() > 0
 
 
@@ -115,11 +144,12 @@ def test_passive_pulse_and_spectrum_with_absorbing_layer(n):
     sim.set_probes(probes, om, decim=32)
     ora.set_probes(probes, om)
     errs = []
+    err = PeakNorm()
     for _ in range(6):
         sim.step(100)
         ora.step(100)
-        errs.append(worst(sim, ora, range(6)))
-    print("passive rel L2 per 100 steps:", ["%.2e" % e for e in errs])
+        errs.append(err(sim, ora))
+    print("passive L2 error / peak norm per 100 steps:", ["%.2e" % e for e in errs])
     assert max(errs) <= TOL32
     fs, fo = sim.spectrum(), ora.spectrum()
     assert np.linalg.norm(fs - fo) / np.linalg.norm(fo) <= TOL32
@@ -133,10 +163,11 @@ def test_mur_source_homogeneous_walls():
     sim, ora = pair(n, bc=("mur",) * 3, eps=eps, gain=gain, init="ground", noise=False)
     sim.set_source(2, 4, 5, 6, amp=1.0)
     ora.set_source(2, 4, 5, 6, amp=1.0)
+    err = PeakNorm()
     for _ in range(4):
         sim.step(100)
         ora.step(100)
-        assert worst(sim, ora, range(6)) <= TOL32
+        assert err(sim, ora) <= TOL32
 
 
 def test_lasing_absorbing_layer_ragged_grid():
@@ -207,7 +238,8 @@ def test_kernel_variants_are_bitwise_identical(bc):
     eps, gain = I.voxelize(I.rsa_pack(n, seed=11, fill=0.35))
     mbf = _mbf()
     ref = None
-    for var, ty, zs, remap in [("two_pass", 8, 0, 0), ("fused", 2, 3, 1), ("fused", 4, 7, 0),
+    for var, ty, zs, remap in [("two_pass", 8, 0, 0), ("two_pass", 2, 3, 0), ("two_pass", 16, 29, 0),
+                               ("two_pass", 4, 40, 0), ("fused", 2, 3, 1), ("fused", 4, 7, 0),
                                ("fused", 8, 0, 1), ("fused", 16, 29, 1)]:
         sim = mbf.Sim(n, boundary=bc, E_sp=1e-2)
         sim.set_tuning(var, tile_y=ty, zseg=zs, xcd_remap=remap)
