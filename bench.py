@@ -9,9 +9,13 @@ N_a in {1, 2, 3.5, 5, 7} x 1e24 m^-3.  One bench step = one time step of all
 5 realizations (5 x 320^3 cell-updates).
 
 Prints ONE JSON line: cell-updates/s, the roofline of the dominant kernel
-(the fused step kernel, HBM bound: algorithmic bytes per launch / average
-launch duration from HIP events on its stream) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+(HBM bound: algorithmic bytes per launch / average launch duration from HIP
+events on its stream) and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
+
+`python bench.py --summarize-profile DIR` prints, as markdown, the kernel
+table or the per-dispatch counter means of the rocprofv3 database(s) under
+DIR (used to write the summaries kept with the sources).
 """
 import argparse
 import json
@@ -43,14 +47,56 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run one plain device copy of known size (counter calibration)")
+                    help="also run one plain elementwise kernel of known traffic (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="summarise rocprofv3 results under DIR and exit")
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel_sha):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "fused_step_c5_traffic.md")
+CALIB_BYTES = 1 << 30          # the calibration kernel reads 1 GiB and writes 1 GiB
+
+
+def summarize_profile(d):
+    """Markdown digest of rocprofv3 databases (kernel trace or counters)."""
+    import glob
+    import sqlite3
+    dbs = sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True))
+    if not dbs:
+        print(f"no rocprofv3 database under {d}", file=sys.stderr)
+        sys.exit(1)
+    for path in dbs:
+        db = sqlite3.connect(path)
+        print(f"### {os.path.relpath(path, d)}\n")
+        n_pmc = db.execute("select count(*) from counters_collection").fetchone()[0]
+        if n_pmc == 0:
+            rows = db.execute("select name, count(*), sum(duration), avg(duration), "
+                              "min(duration), max(duration) from kernels group by name "
+                              "order by sum(duration) desc").fetchall()
+            total = sum(r[2] for r in rows) or 1
+            print("| kernel | calls | total ms | average us | min us | max us | % |")
+            print("|---|---:|---:|---:|---:|---:|---:|")
+            for name, calls, tot, avg, lo, hi in rows:
+                print(f"| `{name}` | {calls} | {tot / 1e6:.3f} | {avg / 1e3:.2f} | {lo / 1e3:.2f} | "
+                      f"{hi / 1e3:.2f} | {100.0 * tot / total:.2f} |")
+        else:
+            rows = db.execute(
+                "select kernel_name, dispatch_id, counter_name, sum(value) from counters_collection "
+                "group by dispatch_id, counter_name").fetchall()
+            acc = {}
+            for name, _, cn, val in rows:
+                acc.setdefault((name, cn), []).append(val)
+            print("| kernel | counter | dispatches | mean per dispatch |")
+            print("|---|---|---:|---:|")
+            for (name, cn), vals in sorted(acc.items()):
+                print(f"| `{name}` | {cn} | {len(vals)} | {sum(vals) / len(vals):.6g} |")
+        print()
+        db.close()
+
+
+def traffic_from_profiles(kernel, kernel_sha):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_320c_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -97,6 +143,9 @@ def cpu_baseline(n, eps, gain, seconds):
 
 def main():
     args = parse()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is a design note, not built", file=sys.stderr)
@@ -133,13 +182,14 @@ def main():
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    kern_ms = 0.0
+    kern_ms = [0.0, 0.0]
     launches = 0
     torch.cuda.synchronize()
     ev0.record(stream)
     for s in sims:
         ms, cnt = s.step_timed(args.steps)
-        kern_ms += ms
+        kern_ms[0] += ms[0]
+        kern_ms[1] += ms[1]
         launches += cnt
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -149,19 +199,30 @@ def main():
     cells = n ** 3
     cu = cells * args.batch * args.steps
     value = cu / (wall_ms / 1e3)
-    alg_bytes = sims[0].step_bytes()      # same material map for every member
-    avg_kern_s = kern_ms / launches / 1e3
+    alg = sims[0].step_bytes()            # same material map for every member
+    two_pass = tuning["variant"] == "two_pass"
+    # the dominant kernel: the fused step kernel, or the longer of the two passes
+    q = 1 if two_pass and kern_ms[1] >= kern_ms[0] else 0
+    kname = ("k_curl_e" if q else "k_curl_h") if two_pass else "k_step_fused"
+    kdesc = {"k_curl_e": "k_curl_e (rows a2-a6: Ampere update, Lorentz polarisation, rate "
+                         "equations, noise, walls; one launch per realization and step)",
+             "k_curl_h": "k_curl_h (row a1: Faraday update and the energy partials)",
+             "k_step_fused": "k_step_fused (rows a1-a6 in one launch per realization and step)"}[kname]
+    alg_bytes = alg[1 + q] if two_pass else alg[0]
+    avg_kern_s = kern_ms[q] / launches / 1e3
     achieved = alg_bytes / avg_kern_s / 1e9
     sha = kernel_source_sha()
-    traffic = traffic_from_profiles(sha)
-    log(f"timed {args.steps} steps x {args.batch}: {wall_ms:.1f} ms, kernel avg "
-        f"{avg_kern_s * 1e3:.3f} ms, {alg_bytes / cells:.1f} alg. B/cell")
+    traffic = traffic_from_profiles(kname, sha)
+    log(f"timed {args.steps} steps x {args.batch}: {wall_ms:.1f} ms; per launch "
+        f"{kern_ms[0] / launches:.3f} + {kern_ms[1] / launches:.3f} ms; "
+        f"{alg[0] / cells:.1f} alg. B/cell per step; kernel source {sha}")
 
     if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.add(a, 1.0, out=b)          # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
+        del a, b
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -199,9 +260,11 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_step_fused (rows a1-a5, one launch per realization and step)",
+            "kernel": kdesc,
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": avg_kern_s * 1e3,
+            "step_alg_bytes": alg[0],
+            "step_kernels_ms": [kern_ms[0] / launches, kern_ms[1] / launches],
         },
         "cpu_baseline": cpu,
     }

@@ -146,10 +146,11 @@ const char* mbf_last_error(const mbf_handle* h);
  * Returns MBF_EINVAL for NULL or sizes < 2. */
 int mbf_config_default(mbf_config* cfg, int nx, int ny, int nz);
 
-/* Validate cfg (sizes, Courant number, finite positive parameters) before any
- * allocation, then allocate the device state on the current device and zero
- * it.  *out receives the handle.  Errors: MBF_EINVAL, MBF_ECFL, MBF_ENODEV,
- * MBF_ENOMEM, MBF_EHIP. */
+/* Validate cfg (sizes >= 2, ny and nz <= 65535, every site array below 4 GiB,
+ * Courant number, finite positive parameters) before any allocation, then
+ * allocate E and H on the current device and zero them (the Bloch state is
+ * allocated by mbf_set_material, one value per gain cell).  *out receives the
+ * handle.  Errors: MBF_EINVAL, MBF_ECFL, MBF_ENODEV, MBF_ENOMEM, MBF_EHIP. */
 int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out);
 
 /* Free everything the handle owns.  NULL is ignored. */
@@ -162,7 +163,9 @@ int mbf_coefficients(const mbf_handle* h, double* out, int n);
  * gain only in the voids).  eps_r[nx*ny*nz] relative permittivity (> 0) and
  * gain[nx*ny*nz] (0 or 1) per cell, x fastest; an E-site takes the values of
  * the cell whose edge it lies on.  At most 255 distinct (eps_r, gain) pairs.
- * Copies; the caller's buffers are not retained. */
+ * Copies; the caller's buffers are not retained.  (Re)allocates the Bloch
+ * state (15 arrays of one value per gain cell), zeroes it and requires a new
+ * mbf_set_pump before stepping. */
 int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int mem_kind);
 
 /* Pump density N_a [m^-3] (Simulations section: the pump is set through the
@@ -216,16 +219,22 @@ int mbf_read_spectrum(mbf_handle* h, double* re_im);
 /* Loss-box integral. */
 int mbf_read_loss(mbf_handle* h, double* out);
 
-/* Copy one site array out of / into the device state (see field ids).
- * Reading P gives P^n, MBF_PPREVX+c gives P^{n-1}. */
+/* Copy one site array out of / into the device state (see field ids), in the
+ * packed layout of (nx+1)*(ny+1)*(nz+1) values, x fastest; dst/src are host
+ * or device memory per mem_kind, owned by the caller.  Reading P gives P^n,
+ * MBF_PPREVX+c gives P^{n-1}.  P and N exist on gain cells only: they read as
+ * zero elsewhere and values written elsewhere are dropped.  Before
+ * mbf_set_material the Bloch fields give MBF_ESTATE. */
 int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind);
 int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 
-/* Kernel schedule.  MBF_VARIANT_FUSED runs rows a1-a5 in one z-marching
- * kernel per step (tiles of 64 x tile_y columns, z segments of zseg planes,
- * workgroups grouped per XCD when xcd_remap = 1); MBF_VARIANT_TWO_PASS runs a1
- * and a2-a5 as two kernels.  Both give bitwise identical fields.  zseg = 0
- * picks a segment length from the grid size.  tile_y must be 2, 4, 8 or 16. */
+/* Kernel schedule.  MBF_VARIANT_TWO_PASS (the default: tile_y 4, zseg 4) runs
+ * a1 and a2-a5 as two kernels, each workgroup covering 64 x tile_y columns
+ * over zseg planes.  MBF_VARIANT_FUSED runs rows a1-a5 in one z-marching
+ * kernel per step that stages H^{n+1/2} through LDS (tiles of 64 x tile_y
+ * columns, z segments of zseg planes, workgroups grouped per XCD when
+ * xcd_remap = 1).  Both give bitwise identical fields.  zseg = 0 picks a
+ * length from the grid size.  tile_y must be 2, 4, 8 or 16. */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 typedef struct mbf_tuning {

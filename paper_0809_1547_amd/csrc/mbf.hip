@@ -1,8 +1,9 @@
 // Host runtime and C ABI of the Maxwell-Bloch FDTD library (see include/mbf.h).
 //
-// A handle owns one simulation's device state: 27 site arrays (E and H
-// double-buffered, P^n/P^{n-1}, N1..N3 per component), the material bytes and
-// table, the control block and the monitor buffers.  Steps are queued on the
+// A handle owns one simulation's device state: 12 site arrays (E and H
+// double-buffered), 15 compact Bloch-state arrays (P^n/P^{n-1}, N1..N3 per
+// component, one value per gain cell, sized when the material is set), the
+// material bytes and table, the control block and the monitor buffers.  Steps are queued on the
 // handle's stream; chunks of steps are captured once into a hipGraph and
 // replayed.
 #include <hip/hip_runtime.h>
@@ -44,8 +45,13 @@ struct mbf_handle {
     int64_t sx = 0, sxy = 0, nsite = 0;   // device layout: x pitch padded to 128-byte lines
     int64_t nexch = 0;                    // sites of the packed exchange layout
     size_t esz = 4;
-    void* pool = nullptr;
-    void* arr[27] = {};       // E_a[3] E_b[3] H_a[3] H_b[3] P_a[3] P_b[3] N1[3] N2[3] N3[3]
+    void* pool = nullptr;     // E and H
+    void* gpool = nullptr;    // compact Bloch state
+    void* arr[27] = {};       // E_a[3] E_b[3] H_a[3] H_b[3] | P_a[3] P_b[3] N1[3] N2[3] N3[3] (compact)
+    int64_t ngain = 0;        // gain cells
+    int64_t glen = 0;         // allocated length of each compact array
+    uint32_t* seg_base = nullptr;   // gain cells before each 64-wide x segment of a row
+    int nbx = 0;              // segments per row
     uint8_t* mat = nullptr;
     void* lut = nullptr;      // inv_eps[256], eps[256], mur[256] in the field type
     uint8_t* lut_gain = nullptr;
@@ -72,7 +78,7 @@ struct mbf_handle {
         mur_c[mbf::kMaxMurTasks] = {};
     Coef co{};
     double Na_si = 0.0;
-    mbf_tuning tun{MBF_VARIANT_FUSED, 8, 0, 1};
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1};
     void* prof = nullptr;     // lossy-layer profiles: [axis][integer, half][n_axis + 1]
     int64_t prof_stride = 0;
     bool has_layer = false;
@@ -164,6 +170,8 @@ mbf::SimView<T> view(mbf_handle* h) {
         v.N[2][c] = A<T>(h, 24 + c);
     }
     const T* lut = reinterpret_cast<const T*>(h->lut);
+    v.seg_base = h->seg_base;
+    v.nbx = h->nbx;
     v.mat = h->mat;
     v.lut_inv_eps = lut;
     v.lut_eps = lut + mbf::kMaxMat;
@@ -222,7 +230,7 @@ mbf::SimView<T> view(mbf_handle* h) {
 
 // Two-pass kernels: workgroups of 64 x tile_y columns, each over zchunk planes.
 int two_pass_zchunk(const mbf_handle* h) {
-    return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(8, h->cfg.nz);
+    return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(4, h->cfg.nz);
 }
 
 dim3 grid_cells(const mbf_handle* h) {
@@ -308,7 +316,7 @@ int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullpt
         dim3 gm((unsigned)((sites + 255) / 256), (unsigned)h->mur_tasks, 1);
         hipLaunchKernelGGL(mbf::k_mur<T>, gm, dim3(256), 0, h->stream, v);
     }
-    hipLaunchKernelGGL(mbf::k_end_step<T>, dim3(1), dim3(256), 0, h->stream, v);
+    hipLaunchKernelGGL(mbf::k_end_step<T>, dim3(1), dim3(mbf::kEndThreads), 0, h->stream, v);
     HIPCHK(h, hipGetLastError());
     return MBF_OK;
 }
@@ -395,9 +403,46 @@ int field_array(mbf_handle* h, int id, int64_t step, bool write, void** out) {
     else if (id < 12) q = (par ? 12 : 15) + (id - 9);        // P^{n-1}
     else q = 18 + (id - 12);                                  // N1, N2, N3
     (void)write;
+    if (q >= 12 && !h->gpool) return fail(h, MBF_ESTATE, "set the material first");
     *out = h->arr[q];
     return MBF_OK;
 }
+
+// Field ids 6..20 (P, P^{n-1}, N) live in the compact gain-cell arrays.
+bool is_compact(int id) { return id >= 6; }
+
+// Compact array -> packed exchange layout in device memory (queued on the
+// handle's stream), and the reverse.
+int gather_field(mbf_handle* h, const void* csrc, void* dst) {
+    HIPCHK(h, hipMemsetAsync(dst, 0, (size_t)h->nexch * h->esz, h->stream));
+    const dim3 g((unsigned)h->nbx, (unsigned)h->cfg.ny, (unsigned)h->cfg.nz);
+    if (h->esz == 8)
+        hipLaunchKernelGGL(mbf::k_gather<double>, g, dim3(64), 0, h->stream, view<double>(h),
+                           (const double*)csrc, (double*)dst);
+    else
+        hipLaunchKernelGGL(mbf::k_gather<float>, g, dim3(64), 0, h->stream, view<float>(h),
+                           (const float*)csrc, (float*)dst);
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
+}
+
+int scatter_field(mbf_handle* h, const void* src, void* cdst) {
+    const dim3 g((unsigned)h->nbx, (unsigned)h->cfg.ny, (unsigned)h->cfg.nz);
+    if (h->esz == 8)
+        hipLaunchKernelGGL(mbf::k_scatter<double>, g, dim3(64), 0, h->stream, view<double>(h),
+                           (const double*)src, (double*)cdst);
+    else
+        hipLaunchKernelGGL(mbf::k_scatter<float>, g, dim3(64), 0, h->stream, view<float>(h),
+                           (const float*)src, (float*)cdst);
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
+}
+
+// Device staging buffer of one packed site array, freed on scope exit.
+struct Staging {
+    void* p = nullptr;
+    ~Staging() { if (p) hipFree(p); }
+};
 
 // Copy one site array between the padded device layout and the packed
 // exchange layout (rows of nx+1 values); kind is a hipMemcpyKind.
@@ -461,6 +506,7 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     *out = nullptr;
     const mbf_config& c = *cfg;
     if (c.nx < 2 || c.ny < 2 || c.nz < 2) return fail(nullptr, MBF_EINVAL, "grid sizes must be >= 2");
+    if (c.ny > 65535 || c.nz > 65535) return fail(nullptr, MBF_EINVAL, "ny and nz must be <= 65535");
     const double ext = (double)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
     if (ext * (c.precision == MBF_FP64 ? 8.0 : 4.0) >= 4294967296.0)
         return fail(nullptr, MBF_EINVAL, "grid too large (one site array must stay below 4 GiB)");
@@ -511,9 +557,11 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
         h->own_stream = true;
     }
     const size_t bytes = (size_t)h->nsite * h->esz;
-    if (hipMalloc(&h->pool, bytes * 27) != hipSuccess) return bail(MBF_ENOMEM, "device allocation of the fields failed");
-    for (int q = 0; q < 27; ++q) h->arr[q] = (char*)h->pool + (size_t)q * bytes;
-    if (hipMalloc(&h->mat, (size_t)h->nsite) != hipSuccess ||
+    if (hipMalloc(&h->pool, bytes * 12) != hipSuccess) return bail(MBF_ENOMEM, "device allocation of the fields failed");
+    for (int q = 0; q < 12; ++q) h->arr[q] = (char*)h->pool + (size_t)q * bytes;
+    h->nbx = (c.nx + 63) / 64;
+    if (hipMalloc(&h->seg_base, sizeof(uint32_t) * (size_t)h->nbx * c.ny * c.nz) != hipSuccess ||
+        hipMalloc(&h->mat, (size_t)h->nsite) != hipSuccess ||
         hipMalloc(&h->lut, 3 * mbf::kMaxMat * h->esz) != hipSuccess ||
         hipMalloc(&h->lut_gain, mbf::kMaxMat) != hipSuccess ||
         hipMalloc(&h->ctl, sizeof(mbf::Ctl)) != hipSuccess)
@@ -526,7 +574,8 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     h->hist_cap = c.energy_history;
     if (h->hist_cap > 0 && hipMalloc(&h->hist, sizeof(double) * h->hist_cap) != hipSuccess)
         return bail(MBF_ENOMEM, "energy history allocation failed");
-    if (hipMemsetAsync(h->pool, 0, bytes * 27, h->stream) != hipSuccess ||
+    if (hipMemsetAsync(h->pool, 0, bytes * 12, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->seg_base, 0, sizeof(uint32_t) * (size_t)h->nbx * c.ny * c.nz, h->stream) != hipSuccess ||
         hipMemsetAsync(h->mat, 0, (size_t)h->nsite, h->stream) != hipSuccess ||
         hipMemsetAsync(h->lut, 0, 3 * mbf::kMaxMat * h->esz, h->stream) != hipSuccess ||
         hipMemsetAsync(h->lut_gain, 0, mbf::kMaxMat, h->stream) != hipSuccess ||
@@ -584,7 +633,8 @@ void mbf_destroy(mbf_handle* h) {
     if (h->stream) hipStreamSynchronize(h->stream);
     drop_graph(h);
     free_probes(h);
-    hipFree(h->pool); hipFree(h->mat); hipFree(h->lut); hipFree(h->lut_gain);
+    hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
+    hipFree(h->mat); hipFree(h->lut); hipFree(h->lut_gain);
     hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
@@ -645,11 +695,16 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
                 const int ci = std::min(i, c.nx - 1), cj = std::min(j, c.ny - 1), ck = std::min(k, c.nz - 1);
                 site[(size_t)i + h->sx * j + h->sxy * k] = cell_id[(size_t)ci + (size_t)c.nx * (cj + (size_t)c.ny * ck)];
             }
-    int64_t gsites = 0;
+    // gain cells, numbered in (z, y, x) order; the count before every 64-wide
+    // x segment of every row is the segment's base in the compact arrays
+    int64_t gsites = 0, ngain = 0;
+    std::vector<uint32_t> seg((size_t)h->nbx * c.ny * c.nz);
     for (int k = 0; k < c.nz; ++k)
         for (int j = 0; j < c.ny; ++j)
             for (int i = 0; i < c.nx; ++i) {
+                if ((i & 63) == 0) seg[(size_t)(i >> 6) + (size_t)h->nbx * (j + (size_t)c.ny * k)] = (uint32_t)ngain;
                 if (!lut_g[cell_id[(size_t)i + (size_t)c.nx * (j + (size_t)c.ny * k)]]) continue;
+                ++ngain;
                 gsites += (j >= 1 && k >= 1) + (i >= 1 && k >= 1) + (i >= 1 && j >= 1);
             }
     const double Sx = kC0 * h->co.dt / c.dx;
@@ -674,6 +729,23 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
     std::vector<uint8_t> gl(mbf::kMaxMat, 0);
     for (size_t q = 0; q < lut_g.size(); ++q) gl[q] = lut_g[q];
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    // compact Bloch-state arrays, 15 of glen values (a multiple of 64, at least 64)
+    const int64_t glen = std::max<int64_t>(64, (ngain + 63) / 64 * 64);
+    if (glen != h->glen) {
+        hipFree(h->gpool);
+        h->gpool = nullptr;
+        h->glen = 0;
+        for (int q = 12; q < 27; ++q) h->arr[q] = nullptr;
+        h->have_material = false;
+        if (hipMalloc(&h->gpool, (size_t)glen * h->esz * 15) != hipSuccess)
+            return fail(h, MBF_ENOMEM, "device allocation of the Bloch state failed");
+        h->glen = glen;
+        for (int q = 0; q < 15; ++q) h->arr[12 + q] = (char*)h->gpool + (size_t)q * glen * h->esz;
+    }
+    HIPCHK(h, hipMemset(h->gpool, 0, (size_t)glen * h->esz * 15));
+    h->ngain = ngain;
+    HIPCHK(h, hipMemcpy(h->seg_base, seg.data(), sizeof(uint32_t) * seg.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->mat, site.data(), site.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->lut, lutbuf.data(), lutbuf.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->lut_gain, gl.data(), gl.size(), hipMemcpyHostToDevice));
@@ -709,13 +781,13 @@ int mbf_set_pump(mbf_handle* h, double Na, int init) {
         N1 = dwp * n0 / d10;
     }
     const size_t bytes = (size_t)h->nsite * h->esz;
-    HIPCHK(h, hipMemsetAsync(h->pool, 0, bytes * 18, h->stream));   // E, H, P (both buffers)
-    const int64_t tot = h->nsite;
-    const dim3 g((unsigned)((tot + 255) / 256));
+    HIPCHK(h, hipMemsetAsync(h->pool, 0, bytes * 12, h->stream));               // E, H (both buffers)
+    HIPCHK(h, hipMemsetAsync(h->gpool, 0, (size_t)h->glen * h->esz * 6, h->stream));  // P (both buffers)
+    const dim3 g((unsigned)h->nbx, (unsigned)c.ny, (unsigned)c.nz);
     if (c.precision == MBF_FP64) {
-        hipLaunchKernelGGL(mbf::k_init_pop<double>, g, dim3(256), 0, h->stream, view<double>(h), N1, N2, N3);
+        hipLaunchKernelGGL(mbf::k_init_pop<double>, g, dim3(64), 0, h->stream, view<double>(h), N1, N2, N3);
     } else {
-        hipLaunchKernelGGL(mbf::k_init_pop<float>, g, dim3(256), 0, h->stream, view<float>(h),
+        hipLaunchKernelGGL(mbf::k_init_pop<float>, g, dim3(64), 0, h->stream, view<float>(h),
                            (float)N1, (float)N2, (float)N3);
     }
     HIPCHK(h, hipGetLastError());
@@ -925,7 +997,8 @@ int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
 int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t) {
     if (!h || !t) return fail(nullptr, MBF_EINVAL, "null argument");
     *t = h->tun;
-    if (t->zseg == 0) t->zseg = fused_geom(h).zseg;
+    if (t->zseg == 0)
+        t->zseg = t->variant == MBF_VARIANT_FUSED ? fused_geom(h).zseg : two_pass_zchunk(h);
     return MBF_OK;
 }
 
@@ -988,8 +1061,19 @@ int mbf_read_loss(mbf_handle* h, double* out) {
 int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind) {
     if (!h || !dst) return fail(h, MBF_EINVAL, "null argument");
     void* src = nullptr;
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(h, MBF_EINVAL, "bad mem_kind");
     int rc = field_array(h, field_id, h->step, false, &src);
     if (rc) return rc;
+    if (is_compact(field_id)) {
+        if (mem_kind == MBF_MEM_DEVICE) return gather_field(h, src, dst);
+        Staging st;
+        HIPCHK(h, hipMalloc(&st.p, (size_t)h->nexch * h->esz));
+        rc = gather_field(h, src, st.p);
+        if (rc) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(dst, st.p, (size_t)h->nexch * h->esz, hipMemcpyDeviceToHost));
+        return MBF_OK;
+    }
     if (mem_kind == MBF_MEM_HOST) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
         HIPCHK(h, copy_sites(h, dst, src, false, hipMemcpyDeviceToHost, false));
@@ -1004,8 +1088,20 @@ int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind) {
 int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind) {
     if (!h || !src) return fail(h, MBF_EINVAL, "null argument");
     void* dst = nullptr;
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(h, MBF_EINVAL, "bad mem_kind");
     int rc = field_array(h, field_id, h->step, true, &dst);
     if (rc) return rc;
+    if (is_compact(field_id)) {
+        if (mem_kind == MBF_MEM_DEVICE) return scatter_field(h, src, dst);
+        Staging st;
+        HIPCHK(h, hipMalloc(&st.p, (size_t)h->nexch * h->esz));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(st.p, src, (size_t)h->nexch * h->esz, hipMemcpyHostToDevice));
+        rc = scatter_field(h, st.p, dst);
+        if (rc) return rc;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return MBF_OK;
+    }
     // E and H are written into both buffers: sites no step ever updates (PEC
     // walls) then keep the written value whichever buffer is current
     void* dst2 = nullptr;
@@ -1063,10 +1159,20 @@ int mbf_save_state(mbf_handle* h, void* buf, size_t n) {
     std::memcpy(p, &hd, sizeof(hd));
     size_t off = sizeof(hd);
     const size_t fb = (size_t)h->nexch * h->esz;
+    Staging st;
+    HIPCHK(h, hipMalloc(&st.p, fb));
     for (int id = 0; id < MBF_NFIELDS; ++id) {
         void* src = nullptr;
-        field_array(h, id, h->step, false, &src);
-        HIPCHK(h, copy_sites(h, p + off, src, false, hipMemcpyDeviceToHost, false));
+        int rc = field_array(h, id, h->step, false, &src);
+        if (rc) return rc;
+        if (is_compact(id)) {
+            rc = gather_field(h, src, st.p);
+            if (rc) return rc;
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            HIPCHK(h, hipMemcpy(p + off, st.p, fb, hipMemcpyDeviceToHost));
+        } else {
+            HIPCHK(h, copy_sites(h, p + off, src, false, hipMemcpyDeviceToHost, false));
+        }
         off += fb;
     }
     if (h->n_probes > 0) {
@@ -1102,9 +1208,20 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
     size_t off = sizeof(hd);
     const size_t fb = (size_t)h->nexch * h->esz;
+    Staging st;
+    HIPCHK(h, hipMalloc(&st.p, fb));
     for (int id = 0; id < MBF_NFIELDS; ++id) {
         void* dst = nullptr;
-        field_array(h, id, hd.step, true, &dst);
+        int rc = field_array(h, id, hd.step, true, &dst);
+        if (rc) return rc;
+        if (is_compact(id)) {
+            HIPCHK(h, hipMemcpy(st.p, p + off, fb, hipMemcpyHostToDevice));
+            rc = scatter_field(h, st.p, dst);
+            if (rc) return rc;
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            off += fb;
+            continue;
+        }
         HIPCHK(h, copy_sites(h, dst, p + off, true, hipMemcpyHostToDevice, false));
         if (id < 6) {
             field_array(h, id, hd.step + 1, true, &dst);

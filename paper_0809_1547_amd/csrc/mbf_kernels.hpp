@@ -1,13 +1,21 @@
 // Device code of the Maxwell-Bloch FDTD step for gfx950 (wave64).
 //
-// Layout: every field component is a structure-of-arrays array over the
-// extended Yee index range (nx+1)*(ny+1)*(nz+1), x fastest.  E and H are
-// double-buffered (the step reads buffer `par` and writes buffer `par^1`,
-// par = step & 1), so a kernel never reads a value another workgroup of the
-// same launch may already have overwritten.  P keeps P^n and P^{n-1}; P^{n+1}
-// is written over P^{n-1}.  N1..N3 are updated in place (each site only reads
-// itself).  Material is one byte per site: an index into a small table of
-// (1/eps_r, eps_r, Mur coefficient, gain flag).
+// Layout: every E and H component is a structure-of-arrays array over the
+// extended Yee index range (nx+1)*(ny+1)*(nz+1), x fastest, rows padded to
+// 128-byte lines.  E and H are double-buffered (the step reads buffer `par`
+// and writes buffer `par^1`, par = step & 1), so a kernel never reads a value
+// another workgroup of the same launch may already have overwritten.
+//
+// The Bloch state (P^n, P^{n-1}, N1..N3 per component) exists only on gain
+// cells and is stored compactly: gain cells are numbered in (z, y, x) order
+// and every component array holds one value per gain cell.  A cell's number is
+// the count of gain cells before its 64-wide x segment (a table with one entry
+// per segment, row and plane) plus the number of gain lanes below it in the
+// wave that covers the segment (a ballot and a bit count), so the P and N
+// loads and stores of a wave touch consecutive addresses and every cache line
+// carries gain sites only.  P^{n+1} is written over P^{n-1}; N1..N3 are
+// updated in place.  Material is one byte per site: an index into a small
+// table of (1/eps_r, eps_r, Mur coefficient, gain flag).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,8 +44,10 @@ template <typename T>
 struct SimView {
     T* E[2][3];
     T* H[2][3];
-    T* P[2][3];
-    T* N[3][3];               // N1, N2, N3 x component
+    T* P[2][3];               // compact, one value per gain cell
+    T* N[3][3];               // N1, N2, N3 x component, compact
+    const uint32_t* seg_base; // gain cells before segment (bx, j, k), bx + nbx (j + ny k)
+    int nbx;                  // 64-wide segments per row
     const uint8_t* mat;       // per site of the extended range
     const T* lut_inv_eps;     // per material id
     const T* lut_eps;
@@ -227,6 +237,21 @@ __device__ __forceinline__ void sto(T* base, uint32_t off, T val) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off * (uint32_t)sizeof(T)) = val;
 }
 
+// Compact index of the calling lane's cell in the Bloch-state arrays.  Must
+// be called by the whole wave that covers x segment bx of row (j, k) (lanes
+// outside the grid inactive or with g = false); j and k are wave-uniform and
+// row_ok is false for a wave past the last row (its result is then unused).
+template <typename T>
+__device__ __forceinline__ uint32_t gain_index(const SimView<T>& v, int bx, int j, int k, bool g,
+                                               bool row_ok) {
+    const uint64_t mask = __ballot(g);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const int seg = __builtin_amdgcn_readfirstlane(bx + v.nbx * (j + v.ny * k));
+    const uint32_t base = row_ok ? v.seg_base[seg] : 0u;
+    return base + below;
+}
+
 // True when every index in [lo, hi] along an axis lies outside its lossy layer.
 __device__ __forceinline__ bool clear_of_layer(int L, int n, int lo, int hi) {
     return L < 0 || (lo >= L && hi <= n - L - 1);
@@ -316,23 +341,23 @@ struct BlochIn {
 };
 
 template <typename T>
-__device__ __forceinline__ BlochIn<T> bloch_load(const Fields<T>& f, int c, uint32_t x, bool gain) {
+__device__ __forceinline__ BlochIn<T> bloch_load(const Fields<T>& f, int c, uint32_t gi, bool gain) {
     BlochIn<T> b{(T)0, (T)0, (T)0, (T)0, (T)0};
     if (gain) {
-        b.P = ldo(f.p[c], x);
-        b.Pp = ldo(f.q[c], x);
-        b.n1 = ldo(f.n1[c], x);
-        b.n2 = ldo(f.n2[c], x);
-        b.n3 = ldo(f.n3[c], x);
+        b.P = ldo(f.p[c], gi);
+        b.Pp = ldo(f.q[c], gi);
+        b.n1 = ldo(f.n1[c], gi);
+        b.n2 = ldo(f.n2[c], gi);
+        b.n3 = ldo(f.n3[c], gi);
     }
     return b;
 }
 
 // Rows a2-a5 at one E-site from its loaded Bloch state.  `upd` marks an
 // interior site (updated by Ampere's law; other sites keep E), `gain` an
-// interior site of a gain cell.  Returns E^{n+1}.
+// interior site of a gain cell, gi the cell's compact index.  Returns E^{n+1}.
 template <typename T>
-__device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f, int c, uint32_t x,
+__device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f, int c, uint32_t gi,
                                         T e, T curl, T ie, bool upd, bool gain,
                                         const BlochIn<T>& b, T xi, T src, T loss) {
     T dP = (T)0;
@@ -353,14 +378,14 @@ __device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f,
     en += src;
     en = upd ? en : e;
     if (gain) {
-        sto(f.q[c], x, Pn);
+        sto(f.q[c], gi, Pn);
         if (!v.frozen_pop) {
             const T n1 = b.n1, n2 = b.n2, n3 = b.n3;
             const T W = v.beta * ((T)0.5 * (en + e)) * dP;
             const T n0 = v.Na - n1 - n2 - n3;
-            sto(f.n3[c], x, n3 + (v.dtWp * n0 - v.dt32 * n3));
-            sto(f.n2[c], x, n2 + (v.dt32 * n3 - v.dt21 * n2) + W);
-            sto(f.n1[c], x, n1 + (v.dt21 * n2 - v.dt10 * n1) - W);
+            sto(f.n3[c], gi, n3 + (v.dtWp * n0 - v.dt32 * n3));
+            sto(f.n2[c], gi, n2 + (v.dt32 * n3 - v.dt21 * n2) + W);
+            sto(f.n1[c], gi, n1 + (v.dt21 * n2 - v.dt10 * n1) - W);
         }
     }
     return en;
@@ -406,9 +431,10 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
             const T ie = v.lut_inv_eps[m];
             const bool g = v.lut_gain[m] != 0;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-            const BlochIn<T> b0 = bloch_load(f, 0, x, g && inx);
-            const BlochIn<T> b1 = bloch_load(f, 1, x, g && iny);
-            const BlochIn<T> b2 = bloch_load(f, 2, x, g && inz);
+            const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+            const BlochIn<T> b0 = bloch_load(f, 0, gi, g && inx);
+            const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
+            const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
             const T hx = ldo(Hx, x), hy = ldo(Hy, x), hz = ldo(Hz, x);
             T xi[3] = {(T)0, (T)0, (T)0};
             if (g && v.noise && (inx || iny || inz)) {
@@ -420,21 +446,21 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
             T acc = (T)0;
             {
                 const T curl = inx ? (hz - ldo(Hz, x - sx)) - (hy - hym) : (T)0;
-                const T en = bloch_site(v, f, 0, x, ldo(f.e[0], x), curl, ie, inx, g && inx, b0, xi[0], s0,
+                const T en = bloch_site(v, f, 0, gi, ldo(f.e[0], x), curl, ie, inx, g && inx, b0, xi[0], s0,
                                         v.has_layer ? loss_e(v, 0, i, j, k) : (T)0);
                 sto(f.en[0], x, en);
                 if (inx) acc += en * en;
             }
             {
                 const T curl = iny ? (hx - hxm) - (hz - ldo(Hz, x - 1u)) : (T)0;
-                const T en = bloch_site(v, f, 1, x, ldo(f.e[1], x), curl, ie, iny, g && iny, b1, xi[1], s1,
+                const T en = bloch_site(v, f, 1, gi, ldo(f.e[1], x), curl, ie, iny, g && iny, b1, xi[1], s1,
                                         v.has_layer ? loss_e(v, 1, i, j, k) : (T)0);
                 sto(f.en[1], x, en);
                 if (iny) acc += en * en;
             }
             {
                 const T curl = inz ? (hy - ldo(Hy, x - 1u)) - (hx - ldo(Hx, x - sx)) : (T)0;
-                const T en = bloch_site(v, f, 2, x, ldo(f.e[2], x), curl, ie, inz, g && inz, b2, xi[2], s2,
+                const T en = bloch_site(v, f, 2, gi, ldo(f.e[2], x), curl, ie, inz, g && inz, b2, xi[2], s2,
                                         v.has_layer ? loss_e(v, 2, i, j, k) : (T)0);
                 sto(f.en[2], x, en);
                 if (inz) acc += en * en;
@@ -550,13 +576,14 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
         // first, so they arrive while E is staged and H is formed
         const uint8_t m = m_next;
         if (act && k + 1 < z1) m_next = ldo(v.mat, xij + sxy * (uint32_t)(k + 1));
-        const bool gn = v.lut_gain[m] != 0;
+        const bool gn = act && v.lut_gain[m] != 0;
         const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
         const uint32_t xo = xij + sxy * (uint32_t)k;
-        const bool ld = own && act && gn;
-        const BlochIn<T> b0 = bloch_load(f, 0, xo, ld && inx);
-        const BlochIn<T> b1 = bloch_load(f, 1, xo, ld && iny);
-        const BlochIn<T> b2 = bloch_load(f, 2, xo, ld && inz);
+        const bool ld = own && gn;
+        const uint32_t gi = gain_index(v, bx, j, k, gn, j < ny);
+        const BlochIn<T> b0 = bloch_load(f, 0, gi, ld && inx);
+        const BlochIn<T> b1 = bloch_load(f, 1, gi, ld && iny);
+        const BlochIn<T> b2 = bloch_load(f, 2, gi, ld && inz);
         stage_plane<T, TY>(se[nxt], f.e[0], f.e[1], f.e[2], k + 1, x0, y0, nx, ny, nz, sx, sxy, tx, ty);
         __syncthreads();
         const bool lay = lay_xy || (v.has_layer && !clear_of_layer(v.lay_L[2], nz, k, k));
@@ -637,21 +664,21 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom 
             T acc = (T)0;
             {
                 const T curl = (sh[2][ly][lx] - sh[2][ly - 1][lx]) - (sh[1][ly][lx] - hyp);
-                const T en = bloch_site(v, f, 0, x, se[cur][0][ly][lx], curl, ie, inx, gn && inx, b0,
+                const T en = bloch_site(v, f, 0, gi, se[cur][0][ly][lx], curl, ie, inx, gn && inx, b0,
                                         xi[0], s0, lay ? loss_e(v, 0, i, j, k) : (T)0);
                 sto(f.en[0], x, en);
                 if (inx) acc += en * en;
             }
             {
                 const T curl = (sh[0][ly][lx] - hxp) - (sh[2][ly][lx] - sh[2][ly][lx - 1]);
-                const T en = bloch_site(v, f, 1, x, se[cur][1][ly][lx], curl, ie, iny, gn && iny, b1,
+                const T en = bloch_site(v, f, 1, gi, se[cur][1][ly][lx], curl, ie, iny, gn && iny, b1,
                                         xi[1], s1, lay ? loss_e(v, 1, i, j, k) : (T)0);
                 sto(f.en[1], x, en);
                 if (iny) acc += en * en;
             }
             {
                 const T curl = (sh[1][ly][lx] - sh[1][ly][lx - 1]) - (sh[0][ly][lx] - sh[0][ly - 1][lx]);
-                const T en = bloch_site(v, f, 2, x, se[cur][2][ly][lx], curl, ie, inz, gn && inz, b2,
+                const T en = bloch_site(v, f, 2, gi, se[cur][2][ly][lx], curl, ie, inz, gn && inz, b2,
                                         xi[2], s2, lay ? loss_e(v, 2, i, j, k) : (T)0);
                 sto(f.en[2], x, en);
                 if (inz) acc += en * en;
@@ -728,30 +755,40 @@ __global__ void __launch_bounds__(256) k_mur(SimView<T> v) {
 }
 
 // ------------------------------------------------------ row a7, step end
+// Sum of the per-workgroup partials in a fixed order: each thread keeps eight
+// independent accumulators over a fixed stride (so its loads are in flight
+// together), then a fixed tree over the threads; every thread gets the sum.
+constexpr int kEndThreads = 1024;
+
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
+    const int t = threadIdx.x;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = t; q < n; q += 8 * kEndThreads) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int e = q + r * kEndThreads;
+            if (e < n) a[r] += p[e];
+        }
+    }
+    double x = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    x = wave_sum(x);
+    if ((t & 63) == 0) sh[t >> 6] = x;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < kEndThreads / 64; ++w) r += sh[w];
+    return r;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_end_step(SimView<T> v) {
-    __shared__ double sh[4];
+__global__ void __launch_bounds__(kEndThreads) k_end_step(SimView<T> v) {
+    __shared__ double sh[kEndThreads / 64];
     const int t = threadIdx.x;
     const int64_t n = v.ctl->step;
-    double acc = 0.0;
-    for (int q = t; q < v.n_part; q += 256) acc += v.e_part[q];
-    // fixed-order tree over the 256 strided partial sums
-    double W = wave_sum(acc);
-    if ((t & 63) == 0) sh[t >> 6] = W;
+    const double W = sum_partials(v.e_part, v.n_part, sh);
     __syncthreads();
-    W = sh[0] + sh[1] + sh[2] + sh[3];
-    __syncthreads();
-    double L = 0.0;
-    if (v.box_on) {
-        double la = 0.0;
-        for (int q = t; q < v.n_part; q += 256) la += v.l_part[q];
-        la = wave_sum(la);
-        if ((t & 63) == 0) sh[t >> 6] = la;
-        __syncthreads();
-        L = sh[0] + sh[1] + sh[2] + sh[3];
-    }
+    const double L = v.box_on ? sum_partials(v.l_part, v.n_part, sh) : 0.0;
     const Fields<T> f = bind_fields(v, (int)(n & 1));
-    for (int p = t; p < v.n_probes; p += 256) {
+    for (int p = t; p < v.n_probes; p += kEndThreads) {
         const int c = v.probe_comp[p];
         const T* e = c == 0 ? f.en[0] : (c == 1 ? f.en[1] : f.en[2]);
         v.ring[(int64_t)p * v.decim + (n % v.decim)] = e[v.probe_off[p]];
@@ -800,23 +837,47 @@ __global__ void __launch_bounds__(256) k_dft(SimView<T> v, int count) {
 
 // ------------------------------------------------------------ set-up
 // Populations of every interior gain E-site at their initial values.
+// Populations of the pump's initial state on interior gain E-sites (zero on
+// the other components of a gain cell).  Grid (nbx, ny, nz) of one wave each.
 template <typename T>
-__global__ void __launch_bounds__(256) k_init_pop(SimView<T> v, T n1, T n2, T n3) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tot = v.sxy * (int64_t)(v.nz + 1);
-    if (q >= tot) return;
-    const int k = (int)(q / v.sxy);
-    const int64_t r = q % v.sxy;
-    const int j = (int)(r / v.sx);
-    const int i = (int)(r % v.sx);
-    const bool cellok = i < v.nx && j < v.ny && k < v.nz && v.lut_gain[v.mat[q]];
-    const bool in[3] = {cellok && j >= 1 && k >= 1, cellok && i >= 1 && k >= 1,
-                        cellok && i >= 1 && j >= 1};
+__global__ void __launch_bounds__(64) k_init_pop(SimView<T> v, T n1, T n2, T n3) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const bool act = i < v.nx;
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
+    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+    if (!g) return;
+    const bool in[3] = {j >= 1 && k >= 1, i >= 1 && k >= 1, i >= 1 && j >= 1};
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        v.N[0][c][q] = in[c] ? n1 : (T)0;
-        v.N[1][c][q] = in[c] ? n2 : (T)0;
-        v.N[2][c][q] = in[c] ? n3 : (T)0;
+        v.N[0][c][gi] = in[c] ? n1 : (T)0;
+        v.N[1][c][gi] = in[c] ? n2 : (T)0;
+        v.N[2][c][gi] = in[c] ? n3 : (T)0;
     }
+}
+
+// Dense copy of one compact Bloch-state array in the packed exchange layout
+// (rows of nx+1 values, zero off the gain cells and on the upper walls, which
+// the caller clears first), and the reverse.  Grid (nbx, ny, nz).
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather(SimView<T> v, const T* __restrict__ src, T* __restrict__ dst) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const bool act = i < v.nx;
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
+    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+    if (act)
+        dst[(int64_t)i + (int64_t)(v.nx + 1) * (j + (int64_t)(v.ny + 1) * k)] = g ? src[gi] : (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_scatter(SimView<T> v, const T* __restrict__ src, T* __restrict__ dst) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const bool act = i < v.nx;
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
+    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+    if (g) dst[gi] = src[(int64_t)i + (int64_t)(v.nx + 1) * (j + (int64_t)(v.ny + 1) * k)];
 }
 
 }  // namespace mbf

@@ -269,7 +269,7 @@ def mbf_load_state(h: int, buf: bytes) -> None:
     _check(lib.mbf_load_state(h, C.addressof(arr), len(b)), h)
 
 
-def mbf_set_tuning(h: int, variant: int = MBF_VARIANT_FUSED, tile_y: int = 8, zseg: int = 0,
+def mbf_set_tuning(h: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
                    xcd_remap: int = 1) -> None:
     t = mbf_tuning(variant, tile_y, zseg, xcd_remap)
     _check(lib.mbf_set_tuning(h, C.byref(t)), h)
@@ -389,7 +389,7 @@ class Sim:
     def loss(self):
         return mbf_read_loss(self.h)
 
-    def set_tuning(self, variant="fused", tile_y=8, zseg=0, xcd_remap=1):
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1):
         mbf_set_tuning(self.h, MBF_VARIANT_FUSED if variant == "fused" else MBF_VARIANT_TWO_PASS,
                        tile_y, zseg, xcd_remap)
 

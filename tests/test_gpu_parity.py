@@ -340,3 +340,29 @@ def test_device_memory_roundtrip_through_torch():
     mbf.mbf_read_field(sim.h, 1, out)
     sim.sync()
     assert np.array_equal(out.cpu().numpy(), host)
+
+
+def test_bloch_state_lives_on_gain_cells_only():
+    # P and N are stored per gain cell: a dense write keeps the gain cells'
+    # values (host and device paths) and reads back zero everywhere else
+    import torch
+    mbf = _mbf()
+    n = (70, 13, 9)
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=6, fill=0.35))
+    sim = mbf.Sim(n)
+    sim.set_material(eps, gain)
+    sim.set_pump(2e24, "ground")
+    shape = sim.shape
+    on = np.zeros(shape, dtype=bool)
+    on[:n[2], :n[1], :n[0]] = gain.astype(bool)
+    rng = np.random.default_rng(3)
+    for fid in (mbf.MBF_PX, mbf.MBF_PPREVX + 2, mbf.MBF_N1X + 1, mbf.MBF_N3X + 2):
+        a = rng.standard_normal(shape).astype(np.float32)
+        sim.set_field(fid, a)
+        assert np.array_equal(sim.field(fid), np.where(on, a, 0.0).astype(np.float32)), fid
+        t = torch.from_numpy(np.ascontiguousarray(a[::-1].copy())).cuda()
+        mbf.mbf_write_field(sim.h, fid, t)
+        out = torch.empty_like(t)
+        mbf.mbf_read_field(sim.h, fid, out)
+        sim.sync()
+        assert np.array_equal(out.cpu().numpy(), np.where(on, a[::-1], 0.0).astype(np.float32)), fid
