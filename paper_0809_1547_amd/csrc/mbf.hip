@@ -233,14 +233,21 @@ int two_pass_zchunk(const mbf_handle* h) {
     return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(4, h->cfg.nz);
 }
 
-dim3 grid_cells(const mbf_handle* h) {
-    const int ty = h->tun.tile_y, zc = two_pass_zchunk(h);
-    return dim3((h->cfg.nx + 63) / 64, (h->cfg.ny + ty - 1) / ty, (h->cfg.nz + zc - 1) / zc);
+mbf::Geom two_pass_geom(const mbf_handle* h) {
+    mbf::Geom g{};
+    const int ty = h->tun.tile_y;
+    g.tiles_x = (h->cfg.nx + 63) / 64;
+    g.tiles_y = (h->cfg.ny + ty - 1) / ty;
+    g.zseg = two_pass_zchunk(h);
+    g.segs = (h->cfg.nz + g.zseg - 1) / g.zseg;
+    g.nblk = g.tiles_x * g.tiles_y * g.segs;
+    g.xcd_remap = h->tun.xcd_remap;
+    return g;
 }
 
 // Geometry of the fused kernel's work items for the handle's tuning.
-mbf::FusedGeom fused_geom(const mbf_handle* h) {
-    mbf::FusedGeom g{};
+mbf::Geom fused_geom(const mbf_handle* h) {
+    mbf::Geom g{};
     const int ty = h->tun.tile_y;
     g.tiles_x = (h->cfg.nx + 63) / 64;
     g.tiles_y = (h->cfg.ny + ty - 1) / ty;
@@ -261,7 +268,7 @@ mbf::FusedGeom fused_geom(const mbf_handle* h) {
 
 template <typename T>
 void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
-    const mbf::FusedGeom g = fused_geom(h);
+    const mbf::Geom g = fused_geom(h);
     v.n_part = g.nblk;
     const dim3 grid((unsigned)g.nblk);
     switch (h->tun.tile_y) {
@@ -283,29 +290,29 @@ int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullpt
         launch_fused<T>(h, v);
         if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
     } else {
-        const dim3 g = grid_cells(h);
-        const int zc = two_pass_zchunk(h);
-        v.n_part = (int)(g.x * g.y * g.z);
+        const mbf::Geom gm = two_pass_geom(h);
+        const dim3 g((unsigned)gm.nblk);
+        v.n_part = gm.nblk;
         switch (h->tun.tile_y) {
             case 2:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 2>), g, dim3(64, 2), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 2>), g, dim3(64, 2), 0, h->stream, v, gm);
                 if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 2>), g, dim3(64, 2), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 2>), g, dim3(64, 2), 0, h->stream, v, gm);
                 break;
             case 4:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 4>), g, dim3(64, 4), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 4>), g, dim3(64, 4), 0, h->stream, v, gm);
                 if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 4>), g, dim3(64, 4), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 4>), g, dim3(64, 4), 0, h->stream, v, gm);
                 break;
             case 16:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 16>), g, dim3(64, 16), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 16>), g, dim3(64, 16), 0, h->stream, v, gm);
                 if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 16>), g, dim3(64, 16), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 16>), g, dim3(64, 16), 0, h->stream, v, gm);
                 break;
             default:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 8>), g, dim3(64, 8), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_h<T, 8>), g, dim3(64, 8), 0, h->stream, v, gm);
                 if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 8>), g, dim3(64, 8), 0, h->stream, v, zc);
+                hipLaunchKernelGGL((mbf::k_curl_e<T, 8>), g, dim3(64, 8), 0, h->stream, v, gm);
                 break;
         }
     }
@@ -695,8 +702,8 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
                 const int ci = std::min(i, c.nx - 1), cj = std::min(j, c.ny - 1), ck = std::min(k, c.nz - 1);
                 site[(size_t)i + h->sx * j + h->sxy * k] = cell_id[(size_t)ci + (size_t)c.nx * (cj + (size_t)c.ny * ck)];
             }
-    // gain cells, numbered in (z, y, x) order; the count before every 64-wide
-    // x segment of every row is the segment's base in the compact arrays
+    // gain cells, numbered in memory order (z, y, x); the count before every
+    // 64-wide x segment of every row is the segment's base in the compact arrays
     int64_t gsites = 0, ngain = 0;
     std::vector<uint32_t> seg((size_t)h->nbx * c.ny * c.nz);
     for (int k = 0; k < c.nz; ++k)

@@ -7,13 +7,15 @@
 // another workgroup of the same launch may already have overwritten.
 //
 // The Bloch state (P^n, P^{n-1}, N1..N3 per component) exists only on gain
-// cells and is stored compactly: gain cells are numbered in (z, y, x) order
-// and every component array holds one value per gain cell.  A cell's number is
-// the count of gain cells before its 64-wide x segment (a table with one entry
-// per segment, row and plane) plus the number of gain lanes below it in the
-// wave that covers the segment (a ballot and a bit count), so the P and N
-// loads and stores of a wave touch consecutive addresses and every cache line
-// carries gain sites only.  P^{n+1} is written over P^{n-1}; N1..N3 are
+// cells and is stored compactly, one value per gain cell in every component
+// array.  The cells are cut into 64-wide x segments of one row and plane,
+// numbered in memory order (bx + nbx (j + ny k)), and the gain cells in that
+// order.  A cell's number is the count of gain cells before its segment (a
+// table with one entry per segment) plus the number of gain lanes below it in
+// the wave that covers the segment (a ballot and a bit count), so the Bloch
+// loads and stores of a wave touch consecutive addresses, every cache line
+// carries gain sites only, and the workgroups that run together (neighbours in
+// x and y) stream through one region of every array.  P^{n+1} is written over P^{n-1}; N1..N3 are
 // updated in place.  Material is one byte per site: an index into a small
 // table of (1/eps_r, eps_r, Mur coefficient, gain flag).
 #pragma once
@@ -272,20 +274,48 @@ __device__ __forceinline__ T source_value(const SimView<T>& v, int64_t n) {
     return (T)(v.src_amp * sin(v.src_ws * t) * exp(-q * q));
 }
 
+// Work decomposition of the step kernels: tiles of 64 x TY columns cut into
+// z segments of zseg planes, one workgroup each, on a 1-D grid of nblk.
+struct Geom {
+    int tiles_x, tiles_y, segs, zseg, nblk, xcd_remap;
+};
+
+// Workgroups are dealt to the 8 XCDs in turn (id mod 8); with remapping, XCD
+// x takes the x-th contiguous range of work items instead, so neighbouring
+// items (the next tile in x or y, whose halo rows and Bloch-array lines they
+// share) meet in the same L2.
+__device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
+    if (!remap) return b;
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = b & 7, idx = b >> 3;
+    return x * q + (x < r ? x : r) + idx;
+}
+
+// Work item -> (x tile, y tile, z segment), x tile fastest (memory order).
+__device__ __forceinline__ void decode_item(const Geom& g, int& bx, int& by, int& bz) {
+    const int w = xcd_work_item((int)blockIdx.x, g.nblk, g.xcd_remap);
+    bx = w % g.tiles_x;
+    const int r = w / g.tiles_x;
+    by = r % g.tiles_y;
+    bz = r / g.tiles_y;
+}
+
 // ---------------------------------------------------------------- row a1
 // H^{n+1/2} = H^{n-1/2} - S curl+ E^n on the H-sites of [0,n)^3, plus the
 // energy W^n = 1/2 [sum eps E^n^2 (interior E-sites) + sum H^{n-1/2}.H^{n+1/2}
 // (H-sites off the wall normal to their component)].
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, int zchunk) {
+__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
     __shared__ double sh[TY];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * TY + threadIdx.y;
+    int bx, by, bz;
+    decode_item(gm, bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
     const int par = (int)(n & 1);
     const Fields<T> f = bind_fields(v, par);
     T wsum = (T)0;
-    const int kz0 = blockIdx.z * zchunk, kz1 = min(kz0 + zchunk, v.nz);
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
     if (i < v.nx && j < v.ny) {
         const T* __restrict__ Ex = f.e[0];
         const T* __restrict__ Ey = f.e[1];
@@ -327,8 +357,7 @@ __global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, int zchunk) {
         }
     }
     const double s = block_sum((double)wsum, sh);
-    if (threadIdx.x == 0 && threadIdx.y == 0)
-        v.e_part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) v.e_part[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------- rows a2, a3, a4, a5
@@ -406,15 +435,17 @@ __device__ __forceinline__ void source3(const SimView<T>& v, int i, int j, int k
 }
 
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
+__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
     __shared__ double sh[TY];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * TY + threadIdx.y;
+    int bx, by, bz;
+    decode_item(gm, bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
     const int par = (int)(n & 1);
     const Fields<T> f = bind_fields(v, par);
     double lsum = 0.0;
-    const int kz0 = blockIdx.z * zchunk, kz1 = min(kz0 + zchunk, v.nz);
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
     if (i < v.nx && j < v.ny) {
         const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
         const T* __restrict__ Hx = f.hn[0];
@@ -431,7 +462,7 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
             const T ie = v.lut_inv_eps[m];
             const bool g = v.lut_gain[m] != 0;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-            const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+            const uint32_t gi = gain_index(v, bx, j, k, g, true);
             const BlochIn<T> b0 = bloch_load(f, 0, gi, g && inx);
             const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
             const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
@@ -474,8 +505,7 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
     }
     if (v.box_on) {
         const double s = block_sum(lsum, sh);
-        if (threadIdx.x == 0 && threadIdx.y == 0)
-            v.l_part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+        if (threadIdx.x == 0 && threadIdx.y == 0) v.l_part[blockIdx.x] = s;
     }
 }
 
@@ -494,17 +524,6 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, int zchunk) {
 // that land on one XCD (the dispatcher deals workgroups round-robin over the
 // 8 XCDs) get a contiguous run of neighbouring tiles and share halo lines in
 // that XCD's L2.
-struct FusedGeom {
-    int tiles_x, tiles_y, segs, zseg, nblk, xcd_remap;
-};
-
-__device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
-    if (!remap) return b;
-    const int q = nblk >> 3, r = nblk & 7;
-    const int x = b & 7, idx = b >> 3;
-    return x * q + (x < r ? x : r) + idx;
-}
-
 // Stage E^n of plane k over x0-1 .. x0+64, y0-1 .. y0+TY into LDS (zero
 // outside the stored range).  Wave w copies rows w, w+TY, ...; lane l copies
 // column l and lanes 0 and 1 also the last two columns.
@@ -534,19 +553,17 @@ __device__ __forceinline__ void stage_plane(T (*dst)[TY + 2][66], const T* __res
 }
 
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, FusedGeom g) {
+__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom g) {
     constexpr int TX = 64;
     constexpr int LX = TX + 2, LY = TY + 2;      // E planes: x0-1 .. x0+64, y0-1 .. y0+TY
     constexpr int HX = TX + 1, HY = TY + 1;      // new H plane: x0-1 .. x0+63, y0-1 .. y0+TY-1
     __shared__ T se[2][3][LY][LX];
     __shared__ T sh[3][HY][HX];
     __shared__ double red[(64 * TY) / 64];
-    const int w = xcd_work_item(blockIdx.x, g.nblk, g.xcd_remap);
+    int bx, by, bz;
+    decode_item(g, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + TX * ty;
-    const int bx = w % g.tiles_x;
-    const int by = (w / g.tiles_x) % g.tiles_y;
-    const int bz = w / (g.tiles_x * g.tiles_y);
     const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * g.zseg;
     const int z1 = min(z0 + g.zseg, v.nz);

@@ -13,7 +13,8 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmbf.so")
+# MBF_LIB selects another build of the same library (e.g. a debug build)
+LIB_PATH = os.environ.get("MBF_LIB") or os.path.join(HERE, "libmbf.so")
 
 MBF_OK, MBF_EINVAL, MBF_ECFL, MBF_ENOMEM, MBF_EHIP, MBF_ENONFINITE, MBF_ESTATE, MBF_ENODEV = \
     0, -1, -2, -3, -4, -5, -6, -7
