@@ -162,7 +162,8 @@ int mbf_coefficients(const mbf_handle* h, double* out, int n);
 /* Material map (Simulations section: spheres of index 2.9 in a background,
  * gain only in the voids).  eps_r[nx*ny*nz] relative permittivity (> 0) and
  * gain[nx*ny*nz] (0 or 1) per cell, x fastest; an E-site takes the values of
- * the cell whose edge it lies on.  At most 255 distinct (eps_r, gain) pairs.
+ * the cell whose edge it lies on.  At most 128 distinct eps_r values among
+ * the gain cells and 128 among the others.
  * Copies; the caller's buffers are not retained.  (Re)allocates the Bloch
  * state (15 arrays of one value per gain cell), zeroes it and requires a new
  * mbf_set_pump before stepping. */
@@ -228,13 +229,15 @@ int mbf_read_loss(mbf_handle* h, double* out);
 int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind);
 int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 
-/* Kernel schedule.  MBF_VARIANT_TWO_PASS (the default: tile_y 4, zseg 4) runs
- * a1 and a2-a5 as two kernels, each workgroup covering 64 x tile_y columns
- * over zseg planes.  MBF_VARIANT_FUSED runs rows a1-a5 in one z-marching
- * kernel per step that stages H^{n+1/2} through LDS (tiles of 64 x tile_y
- * columns, z segments of zseg planes, workgroups grouped per XCD when
- * xcd_remap = 1).  Both give bitwise identical fields.  zseg = 0 picks a
- * length from the grid size.  tile_y must be 2, 4, 8 or 16. */
+/* Kernel schedule.  Both variants give bitwise identical fields; they differ
+ * in how the step is cut into kernels.  Workgroups cover 64 x tile_y columns
+ * over zseg planes (zseg = 0: 4) and are grouped per XCD when xcd_remap = 1.
+ * tile_y must be 2, 4, 8 or 16.
+ *   MBF_VARIANT_TWO_PASS (default: tile_y 4, zseg 4): a1 in one kernel,
+ *     a2-a5 in a second.
+ *   MBF_VARIANT_FUSED: rows a1-a5 in one z-marching kernel in which every
+ *     wave owns a row and forms again the few H^{n+1/2} values of the
+ *     neighbouring row, column and plane that it needs (no LDS, no barrier). */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 typedef struct mbf_tuning {

@@ -54,7 +54,6 @@ struct mbf_handle {
     int nbx = 0;              // segments per row
     uint8_t* mat = nullptr;
     void* lut = nullptr;      // inv_eps[256], eps[256], mur[256] in the field type
-    uint8_t* lut_gain = nullptr;
     mbf::Ctl* ctl = nullptr;
     double* e_part = nullptr;
     double* l_part = nullptr;
@@ -176,7 +175,6 @@ mbf::SimView<T> view(mbf_handle* h) {
     v.lut_inv_eps = lut;
     v.lut_eps = lut + mbf::kMaxMat;
     v.lut_mur = lut + 2 * mbf::kMaxMat;
-    v.lut_gain = h->lut_gain;
     v.nx = h->cfg.nx;
     v.ny = h->cfg.ny;
     v.nz = h->cfg.nz;
@@ -228,17 +226,17 @@ mbf::SimView<T> view(mbf_handle* h) {
     return v;
 }
 
-// Two-pass kernels: workgroups of 64 x tile_y columns, each over zchunk planes.
-int two_pass_zchunk(const mbf_handle* h) {
+// Step kernels: workgroups of 64 x tile_y columns, each over zseg planes.
+int step_zseg(const mbf_handle* h) {
     return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(4, h->cfg.nz);
 }
 
-mbf::Geom two_pass_geom(const mbf_handle* h) {
+mbf::Geom step_geom(const mbf_handle* h) {
     mbf::Geom g{};
     const int ty = h->tun.tile_y;
     g.tiles_x = (h->cfg.nx + 63) / 64;
     g.tiles_y = (h->cfg.ny + ty - 1) / ty;
-    g.zseg = two_pass_zchunk(h);
+    g.zseg = step_zseg(h);
     g.segs = (h->cfg.nz + g.zseg - 1) / g.zseg;
     g.nblk = g.tiles_x * g.tiles_y * g.segs;
     g.xcd_remap = h->tun.xcd_remap;
@@ -246,29 +244,10 @@ mbf::Geom two_pass_geom(const mbf_handle* h) {
 }
 
 // Geometry of the fused kernel's work items for the handle's tuning.
-mbf::Geom fused_geom(const mbf_handle* h) {
-    mbf::Geom g{};
-    const int ty = h->tun.tile_y;
-    g.tiles_x = (h->cfg.nx + 63) / 64;
-    g.tiles_y = (h->cfg.ny + ty - 1) / ty;
-    int zseg = h->tun.zseg;
-    if (zseg <= 0) {
-        // enough workgroups to give every CU several, segments of >= 4 planes
-        const int cols = g.tiles_x * g.tiles_y;
-        const int segs = std::max(1, (2048 + cols - 1) / cols);
-        zseg = std::max(4, (h->cfg.nz + segs - 1) / segs);
-    }
-    zseg = std::min(zseg, h->cfg.nz);
-    g.zseg = zseg;
-    g.segs = (h->cfg.nz + zseg - 1) / zseg;
-    g.nblk = g.tiles_x * g.tiles_y * g.segs;
-    g.xcd_remap = h->tun.xcd_remap;
-    return g;
-}
 
 template <typename T>
 void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
-    const mbf::Geom g = fused_geom(h);
+    const mbf::Geom g = step_geom(h);
     v.n_part = g.nblk;
     const dim3 grid((unsigned)g.nblk);
     switch (h->tun.tile_y) {
@@ -290,7 +269,7 @@ int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullpt
         launch_fused<T>(h, v);
         if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
     } else {
-        const mbf::Geom gm = two_pass_geom(h);
+        const mbf::Geom gm = step_geom(h);
         const dim3 g((unsigned)gm.nblk);
         v.n_part = gm.nblk;
         switch (h->tun.tile_y) {
@@ -570,7 +549,6 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     if (hipMalloc(&h->seg_base, sizeof(uint32_t) * (size_t)h->nbx * c.ny * c.nz) != hipSuccess ||
         hipMalloc(&h->mat, (size_t)h->nsite) != hipSuccess ||
         hipMalloc(&h->lut, 3 * mbf::kMaxMat * h->esz) != hipSuccess ||
-        hipMalloc(&h->lut_gain, mbf::kMaxMat) != hipSuccess ||
         hipMalloc(&h->ctl, sizeof(mbf::Ctl)) != hipSuccess)
         return bail(MBF_ENOMEM, "device allocation failed");
     // enough partial-sum slots for every kernel variant (one per workgroup)
@@ -585,7 +563,6 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
         hipMemsetAsync(h->seg_base, 0, sizeof(uint32_t) * (size_t)h->nbx * c.ny * c.nz, h->stream) != hipSuccess ||
         hipMemsetAsync(h->mat, 0, (size_t)h->nsite, h->stream) != hipSuccess ||
         hipMemsetAsync(h->lut, 0, 3 * mbf::kMaxMat * h->esz, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->lut_gain, 0, mbf::kMaxMat, h->stream) != hipSuccess ||
         hipMemsetAsync(h->ctl, 0, sizeof(mbf::Ctl), h->stream) != hipSuccess ||
         hipMemsetAsync(h->l_part, 0, sizeof(double) * h->n_part, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
@@ -641,7 +618,7 @@ void mbf_destroy(mbf_handle* h) {
     drop_graph(h);
     free_probes(h);
     hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
-    hipFree(h->mat); hipFree(h->lut); hipFree(h->lut_gain);
+    hipFree(h->mat); hipFree(h->lut);
     hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
@@ -671,24 +648,27 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
     } else {
         return fail(h, MBF_EINVAL, "mem_kind must be MBF_MEM_HOST or MBF_MEM_DEVICE");
     }
+    // material ids: cells without gain take 0..kGainId-1, gain cells
+    // kGainId..kMaxMat-1, one id per distinct eps_r in each class
     std::map<std::pair<uint32_t, uint8_t>, int> ids;
     std::vector<uint8_t> cell_id(ncell);
-    std::vector<float> lut_eps;
-    std::vector<uint8_t> lut_g;
+    std::vector<float> lut_eps(mbf::kMaxMat, 1.0f);
+    int next_id[2] = {0, mbf::kGainId};
     for (size_t q = 0; q < ncell; ++q) {
         const float e = eps[q];
         if (!(std::isfinite(e) && e > 0.0f)) return fail(h, MBF_EINVAL, "eps_r must be finite and > 0");
         uint32_t bits;
         std::memcpy(&bits, &e, 4);
-        const auto key = std::make_pair(bits, (uint8_t)(g[q] ? 1 : 0));
+        const uint8_t gq = g[q] ? 1 : 0;
+        const auto key = std::make_pair(bits, gq);
         auto it = ids.find(key);
         int id;
         if (it == ids.end()) {
-            id = (int)lut_eps.size();
-            if (id >= mbf::kMaxMat - 1) return fail(h, MBF_EINVAL, "more than 255 distinct (eps_r, gain) pairs");
+            id = next_id[gq]++;
+            if (id >= (gq ? mbf::kMaxMat : mbf::kGainId))
+                return fail(h, MBF_EINVAL, "more than 128 distinct eps_r among gain cells or among the others");
             ids.emplace(key, id);
-            lut_eps.push_back(e);
-            lut_g.push_back(key.second);
+            lut_eps[id] = e;
         } else {
             id = it->second;
         }
@@ -710,13 +690,13 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
         for (int j = 0; j < c.ny; ++j)
             for (int i = 0; i < c.nx; ++i) {
                 if ((i & 63) == 0) seg[(size_t)(i >> 6) + (size_t)h->nbx * (j + (size_t)c.ny * k)] = (uint32_t)ngain;
-                if (!lut_g[cell_id[(size_t)i + (size_t)c.nx * (j + (size_t)c.ny * k)]]) continue;
+                if (cell_id[(size_t)i + (size_t)c.nx * (j + (size_t)c.ny * k)] < mbf::kGainId) continue;
                 ++ngain;
                 gsites += (j >= 1 && k >= 1) + (i >= 1 && k >= 1) + (i >= 1 && j >= 1);
             }
     const double Sx = kC0 * h->co.dt / c.dx;
     std::vector<double> inv(mbf::kMaxMat, 1.0), ep(mbf::kMaxMat, 1.0), mur(mbf::kMaxMat, 0.0);
-    for (size_t q = 0; q < lut_eps.size(); ++q) {
+    for (int q = 0; q < mbf::kMaxMat; ++q) {
         const double e = (double)lut_eps[q];
         inv[q] = 1.0 / e;
         ep[q] = e;
@@ -733,8 +713,6 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
             d[q] = (float)inv[q]; d[mbf::kMaxMat + q] = (float)ep[q]; d[2 * mbf::kMaxMat + q] = (float)mur[q];
         }
     }
-    std::vector<uint8_t> gl(mbf::kMaxMat, 0);
-    for (size_t q = 0; q < lut_g.size(); ++q) gl[q] = lut_g[q];
     HIPCHK(h, hipStreamSynchronize(h->stream));
     drop_graph(h);
     // compact Bloch-state arrays, 15 of glen values (a multiple of 64, at least 64)
@@ -755,7 +733,6 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
     HIPCHK(h, hipMemcpy(h->seg_base, seg.data(), sizeof(uint32_t) * seg.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->mat, site.data(), site.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->lut, lutbuf.data(), lutbuf.size(), hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(h->lut_gain, gl.data(), gl.size(), hipMemcpyHostToDevice));
     h->gain_sites = gsites;
     h->have_material = true;
     h->have_pump = false;   // the populations depend on the gain map
@@ -1005,7 +982,7 @@ int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t) {
     if (!h || !t) return fail(nullptr, MBF_EINVAL, "null argument");
     *t = h->tun;
     if (t->zseg == 0)
-        t->zseg = t->variant == MBF_VARIANT_FUSED ? fused_geom(h).zseg : two_pass_zchunk(h);
+        t->zseg = step_zseg(h);
     return MBF_OK;
 }
 

@@ -15,9 +15,10 @@
 // the wave that covers the segment (a ballot and a bit count), so the Bloch
 // loads and stores of a wave touch consecutive addresses, every cache line
 // carries gain sites only, and the workgroups that run together (neighbours in
-// x and y) stream through one region of every array.  P^{n+1} is written over P^{n-1}; N1..N3 are
-// updated in place.  Material is one byte per site: an index into a small
-// table of (1/eps_r, eps_r, Mur coefficient, gain flag).
+// x and y) stream through one region of every array.  P^{n+1} is written over
+// P^{n-1}; N1..N3 are updated in place.  Material is one byte per site: an
+// index into a small table of (1/eps_r, eps_r, Mur coefficient); ids from
+// kGainId up mark gain cells, so the gain flag needs no table look-up.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,12 +26,9 @@
 
 namespace mbf {
 
-constexpr int kBlockX = 64;   // one wave along x
-constexpr int kBlockY = 4;    // four waves per workgroup
-constexpr int kThreads = kBlockX * kBlockY;
 constexpr int kMaxMat = 256;
+constexpr int kGainId = 128;  // material ids >= kGainId are gain cells
 constexpr int kMaxMurTasks = 12;
-constexpr int kZChunk = 8;    // planes per workgroup in the two-pass kernels
 
 struct Ctl {                  // per-simulation control block (device memory)
     int64_t step;             // steps taken since the pump was set
@@ -54,7 +52,6 @@ struct SimView {
     const T* lut_inv_eps;     // per material id
     const T* lut_eps;
     const T* lut_mur;
-    const uint8_t* lut_gain;
     int nx, ny, nz;
     int64_t sx, sxy;          // strides of the extended range
     T S, a, b, ck, cF, beta, dt32, dt21, dt10, dtWp, Na;
@@ -163,7 +160,7 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Sum over a workgroup of kThreads threads in a fixed order (deterministic).
+// Sum over a workgroup in a fixed order (deterministic); thread 0 gets the sum.
 __device__ __forceinline__ double block_sum(double x, double* sh) {
     const int t = threadIdx.x + threadIdx.y * blockDim.x;
     x = wave_sum(x);
@@ -452,21 +449,24 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
         const T* __restrict__ Hy = f.hn[1];
         const T* __restrict__ Hz = f.hn[2];
         uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
+        // the material byte and the compact index of plane k are known before
+        // the iteration starts, so every load of the plane issues at once
         uint8_t m_next = ldo(v.mat, x);
+        uint32_t gi_next = gain_index(v, bx, j, kz0, m_next >= kGainId, true);
         // H^{n+1/2} at plane k-1 is carried from the previous plane
         T hxm = kz0 >= 1 ? ldo(Hx, x - sxy) : (T)0;
         T hym = kz0 >= 1 ? ldo(Hy, x - sxy) : (T)0;
         for (int k = kz0; k < kz1; ++k, x += sxy) {
             const uint8_t m = m_next;
+            const uint32_t gi = gi_next;
             if (k + 1 < kz1) m_next = ldo(v.mat, x + sxy);     // one plane ahead
-            const T ie = v.lut_inv_eps[m];
-            const bool g = v.lut_gain[m] != 0;
+            const bool g = m >= kGainId;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-            const uint32_t gi = gain_index(v, bx, j, k, g, true);
             const BlochIn<T> b0 = bloch_load(f, 0, gi, g && inx);
             const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
             const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
             const T hx = ldo(Hx, x), hy = ldo(Hy, x), hz = ldo(Hz, x);
+            const T ie = v.lut_inv_eps[m];
             T xi[3] = {(T)0, (T)0, (T)0};
             if (g && v.noise && (inx || iny || inz)) {
                 const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
@@ -501,6 +501,7 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
                 lsum += (double)acc;
             hxm = hx;
             hym = hy;
+            if (k + 1 < kz1) gi_next = gain_index(v, bx, j, k + 1, m_next >= kGainId, true);
         }
     }
     if (v.box_on) {
@@ -510,125 +511,86 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
 }
 
 // ------------------------------------------------ fused step (a1 to a5)
-// One workgroup owns a 64 x TY tile of (i, j) columns and marches along z over
-// a segment [z0, z1) of planes.  Per plane k it stages E^n(k+1) (tile plus a
-// one-site halo on every side) in LDS next to E^n(k), forms H^{n+1/2}(k) on the
-// tile and on the low-side halo row and column that the E update needs, then
-// updates E, P and the populations of the tile at plane k.  H^{n+1/2}(k-1) of
-// its own columns stays in registers from the previous plane; a segment that
-// does not start at z = 0 first recomputes plane z0-1 without storing it.
-// Every value is formed by the same expression as in the two-pass kernels
-// (k_curl_h, k_curl_e), so both paths give bitwise identical fields.
-//
-// Work items (tile x, tile y, segment) are laid out so that the workgroups
-// that land on one XCD (the dispatcher deals workgroups round-robin over the
-// 8 XCDs) get a contiguous run of neighbouring tiles and share halo lines in
-// that XCD's L2.
-// Stage E^n of plane k over x0-1 .. x0+64, y0-1 .. y0+TY into LDS (zero
-// outside the stored range).  Wave w copies rows w, w+TY, ...; lane l copies
-// column l and lanes 0 and 1 also the last two columns.
+// Each wave owns one row (64 sites along x) of a 64 x TY tile and marches
+// along z over a segment [z0, z1) of planes; the waves never wait for each
+// other (no LDS, no barrier).  Per plane k a wave forms H^{n+1/2}(k) on its own
+// row and stores it, forms again the two components of row j-1 that its E
+// update needs (Hx, Hz), takes Hy and Hz at x-1 from the next lower lane (lane
+// 0 forms them again at the tile edge), and then updates E, P and the
+// populations of its row.  H^{n+1/2}(k-1) of its own row stays in registers;
+// a segment that does not start at z = 0 first forms Hx, Hy of plane z0-1.
+// Every recomputed value is the same expression on the same inputs as where
+// it is owned (k_curl_h), so all kernel variants give bitwise identical fields.
 template <typename T, int TY>
-__device__ __forceinline__ void stage_plane(T (*dst)[TY + 2][66], const T* __restrict__ E0,
-                                            const T* __restrict__ E1, const T* __restrict__ E2,
-                                            int k, int x0, int y0, int nx, int ny, int nz,
-                                            uint32_t sx, uint32_t sxy, int tx, int ty) {
-    constexpr int LY = TY + 2;
-    const bool kin = k <= nz;
-    for (int r = ty; r < 3 * LY; r += TY) {
-        const int c = r >= 2 * LY ? 2 : (r >= LY ? 1 : 0);
-        const int ly = r - c * LY;
-        const T* __restrict__ src = c == 0 ? E0 : (c == 1 ? E1 : E2);
-        const int gy = y0 - 1 + ly;
-        const bool rin = kin && gy >= 0 && gy <= ny;
-        const uint32_t row = sx * (uint32_t)gy + sxy * (uint32_t)k;
-        {
-            const int gx = x0 - 1 + tx;
-            dst[c][ly][tx] = (rin && gx >= 0 && gx <= nx) ? ldo(src, row + (uint32_t)gx) : (T)0;
-        }
-        if (tx < 2) {
-            const int gx = x0 + 63 + tx;
-            dst[c][ly][64 + tx] = (rin && gx <= nx) ? ldo(src, row + (uint32_t)gx) : (T)0;
-        }
-    }
-}
-
-template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom g) {
-    constexpr int TX = 64;
-    constexpr int LX = TX + 2, LY = TY + 2;      // E planes: x0-1 .. x0+64, y0-1 .. y0+TY
-    constexpr int HX = TX + 1, HY = TY + 1;      // new H plane: x0-1 .. x0+63, y0-1 .. y0+TY-1
-    __shared__ T se[2][3][LY][LX];
-    __shared__ T sh[3][HY][HX];
-    __shared__ double red[(64 * TY) / 64];
+__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
+    __shared__ double sh[TY];
     int bx, by, bz;
-    decode_item(g, bx, by, bz);
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = tx + TX * ty;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int z0 = bz * g.zseg;
-    const int z1 = min(z0 + g.zseg, v.nz);
-    const int i = x0 + tx, j = y0 + ty;
-    const bool act = i < v.nx && j < v.ny;
+    decode_item(gm, bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
-    const int par = (int)(n & 1);
-    const Fields<T> f = bind_fields(v, par);
-    const int nx = v.nx, ny = v.ny, nz = v.nz;
-    const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
-    // lossy-layer look-ups only where the tile can reach the layer
-    const bool lay_xy = v.has_layer && !(clear_of_layer(v.lay_L[0], nx, x0 - 1, x0 + TX) &&
-                                         clear_of_layer(v.lay_L[1], ny, y0 - 1, y0 + TY));
-
+    const Fields<T> f = bind_fields(v, (int)(n & 1));
     T wsum = (T)0;
     double lsum = 0.0;
-    T hxp = (T)0, hyp = (T)0;
-    const int kstart = z0 > 0 ? z0 - 1 : z0;
-    int cur = 0;
-    const uint32_t xij = (uint32_t)i + sx * (uint32_t)j;
-    uint8_t m_next = act ? ldo(v.mat, xij + sxy * (uint32_t)kstart) : 0;
-    stage_plane<T, TY>(se[cur], f.e[0], f.e[1], f.e[2], kstart, x0, y0, nx, ny, nz, sx, sxy, tx, ty);
-    for (int k = kstart; k < z1; ++k) {
-        const int nxt = cur ^ 1;
-        const bool own = k >= z0;
-        // the Bloch state of this plane and the next material byte are loaded
-        // first, so they arrive while E is staged and H is formed
-        const uint8_t m = m_next;
-        if (act && k + 1 < z1) m_next = ldo(v.mat, xij + sxy * (uint32_t)(k + 1));
-        const bool gn = act && v.lut_gain[m] != 0;
-        const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-        const uint32_t xo = xij + sxy * (uint32_t)k;
-        const bool ld = own && gn;
-        const uint32_t gi = gain_index(v, bx, j, k, gn, j < ny);
-        const BlochIn<T> b0 = bloch_load(f, 0, gi, ld && inx);
-        const BlochIn<T> b1 = bloch_load(f, 1, gi, ld && iny);
-        const BlochIn<T> b2 = bloch_load(f, 2, gi, ld && inz);
-        stage_plane<T, TY>(se[nxt], f.e[0], f.e[1], f.e[2], k + 1, x0, y0, nx, ny, nz, sx, sxy, tx, ty);
-        __syncthreads();
-        const bool lay = lay_xy || (v.has_layer && !clear_of_layer(v.lay_L[2], nz, k, k));
-        const uint32_t xk = sxy * (uint32_t)k;
-        // ---- a1: H^{n+1/2} at plane k
-        T nhx = (T)0, nhy = (T)0, nhz = (T)0;
-        const int ly = ty + 1, lx = tx + 1;
-        if (act) {
-            const uint32_t x = (uint32_t)i + sx * (uint32_t)j + xk;
-            const T ex = se[cur][0][ly][lx], ey = se[cur][1][ly][lx], ez = se[cur][2][ly][lx];
-            const T cx = (se[cur][2][ly + 1][lx] - ez) - (se[nxt][1][ly][lx] - ey);
-            const T cy = (se[nxt][0][ly][lx] - ex) - (se[cur][2][ly][lx + 1] - ez);
-            const T cz = (se[cur][1][ly][lx + 1] - ey) - (se[cur][0][ly + 1][lx] - ex);
-            const T hx = ldo(f.h[0], x), hy = ldo(f.h[1], x), hz = ldo(f.h[2], x);
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    if (j < v.ny) {                                   // wave-uniform
+        const bool act = i < v.nx;
+        const int ic = act ? i : v.nx;                // lanes past the grid read a valid site
+        const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+        const T* __restrict__ Ex = f.e[0];
+        const T* __restrict__ Ey = f.e[1];
+        const T* __restrict__ Ez = f.e[2];
+        const T* __restrict__ Hx0 = f.h[0];
+        const T* __restrict__ Hy0 = f.h[1];
+        const T* __restrict__ Hz0 = f.h[2];
+        const bool lay = v.has_layer != 0;
+        const bool up = j >= 1;                       // row j-1 exists (wave-uniform)
+        const bool edge = threadIdx.x == 0 && i >= 1; // lane 0 of a tile past x = 0
+        uint32_t x = (uint32_t)ic + sx * (uint32_t)j + sxy * (uint32_t)kz0;
+        uint8_t m_next = ldo(v.mat, x);
+        uint32_t gi_next = gain_index(v, bx, j, kz0, act && m_next >= kGainId, true);
+        T ex = ldo(Ex, x), ey = ldo(Ey, x);           // E^n(k) of the row, carried along z
+        T eym = up ? ldo(Ey, x - sx) : (T)0;          // Ey^n(k) of row j-1, carried along z
+        // H^{n+1/2}(k-1) of the row: formed again at a segment start
+        T hxp = (T)0, hyp = (T)0;
+        if (kz0 >= 1) {
+            const uint32_t xp = x - sxy;
+            const T ezp = ldo(Ez, xp), eyp = ldo(Ey, xp), exp_ = ldo(Ex, xp);
+            const T cx = (ldo(Ez, xp + sx) - ezp) - (ey - eyp);
+            const T cy = (ex - exp_) - (ldo(Ez, xp + 1u) - ezp);
+            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay ? loss_h(v, 0, i, j, kz0 - 1) : (T)0);
+            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay ? loss_h(v, 1, i, j, kz0 - 1) : (T)0);
+        }
+        for (int k = kz0; k < kz1; ++k, x += sxy) {
+            const uint8_t m = m_next;
+            const uint32_t gi = gi_next;
+            if (k + 1 < kz1) m_next = ldo(v.mat, x + sxy);     // one plane ahead
+            const bool g = act && m >= kGainId;
+            const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
+            const BlochIn<T> b0 = bloch_load(f, 0, gi, g && inx);
+            const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
+            const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
+            // ---- a1 on the own row
+            const T ez = ldo(Ez, x);
+            const T exk = ldo(Ex, x + sxy), eyk = ldo(Ey, x + sxy);
+            const T hx = ldo(Hx0, x), hy = ldo(Hy0, x), hz = ldo(Hz0, x);
+            const T cx = (ldo(Ez, x + sx) - ez) - (eyk - ey);
+            const T cy = (exk - ex) - (ldo(Ez, x + 1u) - ez);
+            const T cz = (ldo(Ey, x + 1u) - ey) - (ldo(Ex, x + sx) - ex);
             T ax = (T)0, ay = (T)0, az = (T)0;
             if (lay) {
                 ax = loss_h(v, 0, i, j, k);
                 ay = loss_h(v, 1, i, j, k);
                 az = loss_h(v, 2, i, j, k);
             }
-            nhx = h_update(hx, v.S, cx, ax);
-            nhy = h_update(hy, v.S, cy, ay);
-            nhz = h_update(hz, v.S, cz, az);
-            if (own) {
+            const T nhx = h_update(hx, v.S, cx, ax);
+            const T nhy = h_update(hy, v.S, cy, ay);
+            const T nhz = h_update(hz, v.S, cz, az);
+            if (act) {
                 sto(f.hn[0], x, nhx);
                 sto(f.hn[1], x, nhy);
                 sto(f.hn[2], x, nhz);
-                const T eps = v.lut_eps[ldo(v.mat, x)];
+                const T eps = v.lut_eps[m];
                 T acc = (T)0;
                 if (j >= 1 && k >= 1) acc += eps * ex * ex;
                 if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -638,85 +600,81 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom g) {
                 if (k >= 1) acc += hz * nhz;
                 wsum += (T)0.5 * acc;
             }
-        }
-        sh[0][ly][lx] = nhx;
-        sh[1][ly][lx] = nhy;
-        sh[2][ly][lx] = nhz;
-        // low-side halo row (i, y0-1): Hx and Hz
-        if (ty == 0 && y0 > 0 && i < nx) {
-            const uint32_t x = (uint32_t)i + sx * (uint32_t)(y0 - 1) + xk;
-            const T ex = se[cur][0][0][lx], ey = se[cur][1][0][lx], ez = se[cur][2][0][lx];
-            const T cx = (se[cur][2][1][lx] - ez) - (se[nxt][1][0][lx] - ey);
-            const T cz = (se[cur][1][0][lx + 1] - ey) - (se[cur][0][1][lx] - ex);
-            const T ax = lay ? loss_h(v, 0, i, y0 - 1, k) : (T)0;
-            const T az = lay ? loss_h(v, 2, i, y0 - 1, k) : (T)0;
-            sh[0][0][lx] = h_update(ldo(f.h[0], x), v.S, cx, ax);
-            sh[2][0][lx] = h_update(ldo(f.h[2], x), v.S, cz, az);
-        }
-        // low-side halo column (x0-1, j): Hy and Hz
-        if (ty == 1 && tx < TY && x0 > 0 && y0 + tx < ny) {
-            const int hj = y0 + tx;
-            const int hly = tx + 1;
-            const uint32_t x = (uint32_t)(x0 - 1) + sx * (uint32_t)hj + xk;
-            const T ex = se[cur][0][hly][0], ey = se[cur][1][hly][0], ez = se[cur][2][hly][0];
-            const T cy = (se[nxt][0][hly][0] - ex) - (se[cur][2][hly][1] - ez);
-            const T cz = (se[cur][1][hly][1] - ey) - (se[cur][0][hly + 1][0] - ex);
-            const T ay = lay ? loss_h(v, 1, x0 - 1, hj, k) : (T)0;
-            const T az = lay ? loss_h(v, 2, x0 - 1, hj, k) : (T)0;
-            sh[1][hly][0] = h_update(ldo(f.h[1], x), v.S, cy, ay);
-            sh[2][hly][0] = h_update(ldo(f.h[2], x), v.S, cz, az);
-        }
-        __syncthreads();
-        // ---- a2..a5 at plane k
-        if (own && act) {
-            const uint32_t x = xo;
-            const T ie = v.lut_inv_eps[m];
-            T xi[3] = {(T)0, (T)0, (T)0};
-            if (gn && v.noise && (inx || iny || inz)) {
-                const uint32_t cell = (uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k);
-                noise3(v, cell, (uint32_t)n, xi);
+            // ---- Hx, Hz of row j-1 (its owner's expressions)
+            T nhx_m = (T)0, nhz_m = (T)0, eymk = (T)0;
+            if (up) {
+                const uint32_t xm = x - sx;
+                const T ezm = ldo(Ez, xm), exm = ldo(Ex, xm);
+                eymk = ldo(Ey, xm + sxy);
+                const T cxm = (ez - ezm) - (eymk - eym);
+                const T czm = (ldo(Ey, xm + 1u) - eym) - (ex - exm);
+                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay ? loss_h(v, 0, i, j - 1, k) : (T)0);
+                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay ? loss_h(v, 2, i, j - 1, k) : (T)0);
             }
-            T s0, s1, s2;
-            source3(v, i, j, k, n, s0, s1, s2);
-            T acc = (T)0;
-            {
-                const T curl = (sh[2][ly][lx] - sh[2][ly - 1][lx]) - (sh[1][ly][lx] - hyp);
-                const T en = bloch_site(v, f, 0, gi, se[cur][0][ly][lx], curl, ie, inx, gn && inx, b0,
-                                        xi[0], s0, lay ? loss_e(v, 0, i, j, k) : (T)0);
-                sto(f.en[0], x, en);
-                if (inx) acc += en * en;
+            // ---- Hy, Hz at x-1 of the own row
+            T nhy_l = __shfl_up(nhy, 1, 64);
+            T nhz_l = __shfl_up(nhz, 1, 64);
+            if (edge) {
+                const uint32_t xl = x - 1u;
+                const T exl = ldo(Ex, xl), eyl = ldo(Ey, xl), ezl = ldo(Ez, xl);
+                const T cyl = (ldo(Ex, xl + sxy) - exl) - (ez - ezl);
+                const T czl = (ey - eyl) - (ldo(Ex, xl + sx) - exl);
+                nhy_l = h_update(ldo(Hy0, xl), v.S, cyl, lay ? loss_h(v, 1, i - 1, j, k) : (T)0);
+                nhz_l = h_update(ldo(Hz0, xl), v.S, czl, lay ? loss_h(v, 2, i - 1, j, k) : (T)0);
             }
-            {
-                const T curl = (sh[0][ly][lx] - hxp) - (sh[2][ly][lx] - sh[2][ly][lx - 1]);
-                const T en = bloch_site(v, f, 1, gi, se[cur][1][ly][lx], curl, ie, iny, gn && iny, b1,
-                                        xi[1], s1, lay ? loss_e(v, 1, i, j, k) : (T)0);
-                sto(f.en[1], x, en);
-                if (iny) acc += en * en;
+            // ---- a2-a5 on the own row
+            if (act) {
+                const T ie = v.lut_inv_eps[m];
+                T xi[3] = {(T)0, (T)0, (T)0};
+                if (g && v.noise && (inx || iny || inz)) {
+                    const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
+                    noise3(v, cell, (uint32_t)n, xi);
+                }
+                T s0, s1, s2;
+                source3(v, i, j, k, n, s0, s1, s2);
+                T acc = (T)0;
+                {
+                    const T curl = inx ? (nhz - nhz_m) - (nhy - hyp) : (T)0;
+                    const T en = bloch_site(v, f, 0, gi, ex, curl, ie, inx, g && inx, b0, xi[0], s0,
+                                            lay ? loss_e(v, 0, i, j, k) : (T)0);
+                    sto(f.en[0], x, en);
+                    if (inx) acc += en * en;
+                }
+                {
+                    const T curl = iny ? (nhx - hxp) - (nhz - nhz_l) : (T)0;
+                    const T en = bloch_site(v, f, 1, gi, ey, curl, ie, iny, g && iny, b1, xi[1], s1,
+                                            lay ? loss_e(v, 1, i, j, k) : (T)0);
+                    sto(f.en[1], x, en);
+                    if (iny) acc += en * en;
+                }
+                {
+                    const T curl = inz ? (nhy - nhy_l) - (nhx - nhx_m) : (T)0;
+                    const T en = bloch_site(v, f, 2, gi, ez, curl, ie, inz, g && inz, b2, xi[2], s2,
+                                            lay ? loss_e(v, 2, i, j, k) : (T)0);
+                    sto(f.en[2], x, en);
+                    if (inz) acc += en * en;
+                }
+                if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
+                    k >= v.box[2] && k < v.box[5])
+                    lsum += (double)acc;
             }
-            {
-                const T curl = (sh[1][ly][lx] - sh[1][ly][lx - 1]) - (sh[0][ly][lx] - sh[0][ly - 1][lx]);
-                const T en = bloch_site(v, f, 2, gi, se[cur][2][ly][lx], curl, ie, inz, gn && inz, b2,
-                                        xi[2], s2, lay ? loss_e(v, 2, i, j, k) : (T)0);
-                sto(f.en[2], x, en);
-                if (inz) acc += en * en;
-            }
-            if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
-                k >= v.box[2] && k < v.box[5])
-                lsum += (double)acc;
+            hxp = nhx;
+            hyp = nhy;
+            ex = exk;
+            ey = eyk;
+            eym = eymk;
+            if (k + 1 < kz1) gi_next = gain_index(v, bx, j, k + 1, act && m_next >= kGainId, true);
         }
-        hxp = nhx;
-        hyp = nhy;
-        __syncthreads();
-        cur = nxt;
     }
-    const double ws = block_sum((double)wsum, red);
+    const double ws = block_sum((double)wsum, sh);
     __syncthreads();
-    const double ls = v.box_on ? block_sum(lsum, red) : 0.0;
-    if (tid == 0) {
+    const double ls = v.box_on ? block_sum(lsum, sh) : 0.0;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
         v.e_part[blockIdx.x] = ws;
         if (v.box_on) v.l_part[blockIdx.x] = ls;
     }
 }
+
 
 // ---------------------------------------------------------------- row a6
 // First-order Mur on the wall E-sites of Mur axes.  Task (a, side, c) covers
@@ -861,7 +819,7 @@ __global__ void __launch_bounds__(64) k_init_pop(SimView<T> v, T n1, T n2, T n3)
     const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
     const bool act = i < v.nx;
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
-    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const bool g = act && v.mat[act ? x : 0u] >= kGainId;
     const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
     if (!g) return;
     const bool in[3] = {j >= 1 && k >= 1, i >= 1 && k >= 1, i >= 1 && j >= 1};
@@ -881,7 +839,7 @@ __global__ void __launch_bounds__(64) k_gather(SimView<T> v, const T* __restrict
     const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
     const bool act = i < v.nx;
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
-    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const bool g = act && v.mat[act ? x : 0u] >= kGainId;
     const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
     if (act)
         dst[(int64_t)i + (int64_t)(v.nx + 1) * (j + (int64_t)(v.ny + 1) * k)] = g ? src[gi] : (T)0;
@@ -892,7 +850,7 @@ __global__ void __launch_bounds__(64) k_scatter(SimView<T> v, const T* __restric
     const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
     const bool act = i < v.nx;
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
-    const bool g = act && v.lut_gain[v.mat[act ? x : 0u]] != 0;
+    const bool g = act && v.mat[act ? x : 0u] >= kGainId;
     const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
     if (g) dst[gi] = src[(int64_t)i + (int64_t)(v.nx + 1) * (j + (int64_t)(v.ny + 1) * k)];
 }

@@ -63,6 +63,7 @@ class mbf_tuning(C.Structure):
 
 
 MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED = 0, 1
+_VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED}
 
 
 def _load():
@@ -391,12 +392,11 @@ class Sim:
         return mbf_read_loss(self.h)
 
     def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1):
-        mbf_set_tuning(self.h, MBF_VARIANT_FUSED if variant == "fused" else MBF_VARIANT_TWO_PASS,
-                       tile_y, zseg, xcd_remap)
+        mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap)
 
     def tuning(self):
         t = mbf_get_tuning(self.h)
-        return dict(variant="fused" if t.variant == MBF_VARIANT_FUSED else "two_pass",
+        return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant],
                     tile_y=t.tile_y, zseg=t.zseg, xcd_remap=t.xcd_remap)
 
     def step_timed(self, n):
