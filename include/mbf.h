@@ -277,6 +277,35 @@ int mbf_state_size(const mbf_handle* h, size_t* out);
 int mbf_save_state(mbf_handle* h, void* buf, size_t n);
 int mbf_load_state(mbf_handle* h, const void* buf, size_t n);
 
+/* ---------------------------------------------------------------- batches
+ * Many realizations advanced together (Simulations section: the emission is
+ * studied over several sphere packings and pump levels N_a).  A batch owns R
+ * member handles, 1 <= R <= 255, created from cfgs[0..R-1] (any sizes and
+ * walls, one precision) on one stream (`stream`, or a new one when NULL).
+ * mbf_batch_member returns a member's handle, owned by the batch and valid
+ * until mbf_batch_destroy: material, pump, sources, probes, reads and
+ * checkpoints go through it, and the member can still be stepped alone.
+ * mbf_batch_step advances every member by nsteps with one launch of each
+ * step kernel per step for all members (a work table maps workgroups to
+ * (member, tile)); chunks of steps are replayed as a hipGraph.  A member's
+ * fields, energies and spectra after mbf_batch_step are bitwise those of the
+ * same member stepped alone with the same tuning.  Every member needs its
+ * material and pump set (MBF_ESTATE otherwise).  mbf_batch_set_tuning sets
+ * the schedule of the batch and of every member.  Timing and algorithmic
+ * bytes as for a handle, summed over the members.  Errors of batch calls are
+ * read with mbf_batch_last_error. */
+int mbf_batch_create(const mbf_config* cfgs, int R, void* stream, mbf_batch** out);
+void mbf_batch_destroy(mbf_batch* b);
+const char* mbf_batch_last_error(const mbf_batch* b);
+int mbf_batch_size(const mbf_batch* b);
+int mbf_batch_member(mbf_batch* b, int r, mbf_handle** out);
+int mbf_batch_set_tuning(mbf_batch* b, const mbf_tuning* t);
+int mbf_batch_get_tuning(const mbf_batch* b, mbf_tuning* t);
+int mbf_batch_step(mbf_batch* b, int64_t nsteps);
+int mbf_batch_sync(mbf_batch* b);
+int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms /* [2] */, int64_t* launches);
+int mbf_batch_step_bytes(const mbf_batch* b, double* bytes /* [3] */);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,7 @@ struct mbf_handle {
     int64_t gain_sites = 0;   // interior E-sites of gain cells
     bool have_material = false, have_pump = false;
     int64_t step = 0;
+    uint64_t version = 0;     // bumped whenever the device view of the handle changes
     // graph of a chunk of steps
     hipGraphExec_t gexec = nullptr;
     int64_t gsteps = 0;
@@ -343,6 +344,7 @@ void drop_graph(mbf_handle* h) {
     h->gexec = nullptr;
     h->gsteps = 0;
     h->gdirty = true;
+    ++h->version;
 }
 
 // Capture `n` steps (plus the DFT fold when probes are set and n == decim).
@@ -1230,6 +1232,375 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
                                           : make_coef<float>(h->cfg, hd.Na_si);
     drop_graph(h);
     return init_source(h);
+}
+
+}  // extern "C"
+
+// ================================================================= batches
+// A batch steps R member simulations (same precision, any sizes) with one
+// launch per kernel: the step kernels run over a work table of (member, work
+// item) entries, the Mur and step-end kernels over the members.  Members are
+// ordinary handles on the batch's stream; everything else (material, pump,
+// sources, probes, reads, checkpoints) goes through them.
+struct mbf_batch {
+    std::vector<mbf_handle*> m;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int precision = MBF_FP32;
+    std::string err;
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1};
+    void* d_views = nullptr;
+    mbf::Geom* d_geoms = nullptr;
+    uint32_t* d_items = nullptr;
+    int nitems = 0;
+    int mur_tasks = 0;
+    int64_t mur_sites = 0;
+    std::vector<uint64_t> seen;   // member versions the device tables describe
+    bool tables = false;
+    hipGraphExec_t gexec = nullptr;
+    int64_t gsteps = 0;
+};
+
+namespace {
+
+int bfail(mbf_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return bfail((b), MBF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_drop_graph(mbf_batch* b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->gsteps = 0;
+}
+
+void batch_free_tables(mbf_batch* b) {
+    hipFree(b->d_views); hipFree(b->d_geoms); hipFree(b->d_items);
+    b->d_views = nullptr; b->d_geoms = nullptr; b->d_items = nullptr;
+    b->nitems = 0;
+    b->tables = false;
+}
+
+// Rebuild the device views, geometries and work table when a member changed.
+template <typename T>
+int batch_tables(mbf_batch* b) {
+    const int R = (int)b->m.size();
+    bool stale = !b->tables || (int)b->seen.size() != R;
+    for (int r = 0; !stale && r < R; ++r) stale = b->seen[r] != b->m[r]->version;
+    if (!stale) return MBF_OK;
+    batch_drop_graph(b);
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    batch_free_tables(b);
+    std::vector<mbf::SimView<T>> views(R);
+    std::vector<mbf::Geom> geoms(R);
+    std::vector<uint32_t> items;
+    b->mur_tasks = 0;
+    b->mur_sites = 0;
+    for (int r = 0; r < R; ++r) {
+        mbf_handle* h = b->m[r];
+        geoms[r] = step_geom(h);
+        views[r] = view<T>(h);
+        views[r].n_part = geoms[r].nblk;
+        if (geoms[r].nblk >= (1 << 24)) return bfail(b, MBF_EINVAL, "member grid has too many work items");
+        for (int w = 0; w < geoms[r].nblk; ++w) items.push_back(((uint32_t)r << 24) | (uint32_t)w);
+        if (h->mur_tasks > 0) {
+            const int64_t nmax = std::max({h->cfg.nx, h->cfg.ny, h->cfg.nz}) + 1;
+            b->mur_tasks = std::max(b->mur_tasks, h->mur_tasks);
+            b->mur_sites = std::max(b->mur_sites, nmax * nmax);
+        }
+    }
+    if (hipMalloc(&b->d_views, sizeof(mbf::SimView<T>) * R) != hipSuccess ||
+        hipMalloc(&b->d_geoms, sizeof(mbf::Geom) * R) != hipSuccess ||
+        hipMalloc(&b->d_items, sizeof(uint32_t) * items.size()) != hipSuccess) {
+        batch_free_tables(b);
+        return bfail(b, MBF_ENOMEM, "batch table allocation failed");
+    }
+    BHIPCHK(b, hipMemcpy(b->d_views, views.data(), sizeof(mbf::SimView<T>) * R, hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(b->d_geoms, geoms.data(), sizeof(mbf::Geom) * R, hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(b->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice));
+    b->nitems = (int)items.size();
+    b->seen.resize(R);
+    for (int r = 0; r < R; ++r) b->seen[r] = b->m[r]->version;
+    b->tables = true;
+    return MBF_OK;
+}
+
+template <typename T>
+int batch_launch_step(mbf_batch* b, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
+                      hipEvent_t ev1 = nullptr) {
+    const mbf::BatchView<T> bv{reinterpret_cast<const mbf::SimView<T>*>(b->d_views), b->d_geoms,
+                               b->d_items, b->nitems, b->tun.xcd_remap};
+    const dim3 g((unsigned)b->nitems);
+    hipStream_t st = b->stream;
+    if (ev0) BHIPCHK(b, hipEventRecord(ev0, st));
+    if (b->tun.variant == MBF_VARIANT_FUSED) {
+        switch (b->tun.tile_y) {
+            case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, bv); break;
+            case 4: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 4>), g, dim3(64, 4), 0, st, bv); break;
+            case 16: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 16>), g, dim3(64, 16), 0, st, bv); break;
+            default: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 8>), g, dim3(64, 8), 0, st, bv); break;
+        }
+        if (evm) BHIPCHK(b, hipEventRecord(evm, st));
+    } else {
+        switch (b->tun.tile_y) {
+            case 2:
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, bv);
+                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, bv);
+                break;
+            case 4:
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, bv);
+                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, bv);
+                break;
+            case 16:
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, bv);
+                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, bv);
+                break;
+            default:
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, bv);
+                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, bv);
+                break;
+        }
+    }
+    if (ev1) BHIPCHK(b, hipEventRecord(ev1, st));
+    const mbf::SimView<T>* views = reinterpret_cast<const mbf::SimView<T>*>(b->d_views);
+    if (b->mur_tasks > 0) {
+        const dim3 gm((unsigned)((b->mur_sites + 255) / 256), (unsigned)b->mur_tasks, (unsigned)b->m.size());
+        hipLaunchKernelGGL(mbf::k_mur_batch<T>, gm, dim3(256), 0, st, views);
+    }
+    hipLaunchKernelGGL(mbf::k_end_step_batch<T>, dim3((unsigned)b->m.size()), dim3(mbf::kEndThreads), 0, st, views);
+    BHIPCHK(b, hipGetLastError());
+    return MBF_OK;
+}
+
+int batch_dispatch(mbf_batch* b, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr, hipEvent_t ev1 = nullptr) {
+    return b->precision == MBF_FP64 ? batch_launch_step<double>(b, ev0, evm, ev1)
+                                    : batch_launch_step<float>(b, ev0, evm, ev1);
+}
+
+// Probe decimation shared by the members with probes (0: none has probes,
+// -1: they differ, so steps run without graphs).
+int batch_decim(const mbf_batch* b) {
+    int d = 0;
+    for (const mbf_handle* h : b->m) {
+        if (h->n_probes == 0) continue;
+        if (d == 0) d = h->decim;
+        else if (d != h->decim) return -1;
+    }
+    return d;
+}
+
+int batch_build_graph(mbf_batch* b, int64_t n) {
+    batch_drop_graph(b);
+    hipGraph_t g = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    int rc = MBF_OK;
+    for (int64_t q = 0; q < n && rc == MBF_OK; ++q) rc = batch_dispatch(b);
+    for (mbf_handle* h : b->m)
+        if (rc == MBF_OK && h->n_probes > 0) {
+            rc = dispatch_dft(h, (int)n);
+            if (rc) b->err = h->err;
+        }
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc != MBF_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(b, MBF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, MBF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    b->gsteps = n;
+    return MBF_OK;
+}
+
+int run_batch(mbf_batch* b, int64_t nsteps, std::vector<hipEvent_t>* ev) {
+    if (nsteps < 0) return bfail(b, MBF_EINVAL, "negative step count");
+    for (mbf_handle* h : b->m) {
+        if (!h->have_material || !h->have_pump) return bfail(b, MBF_ESTATE, "set material and pump of every member first");
+        if (h->step + nsteps >= (int64_t)1 << 32) return bfail(b, MBF_EINVAL, "step index would exceed 2^32");
+    }
+    int rc = b->precision == MBF_FP64 ? batch_tables<double>(b) : batch_tables<float>(b);
+    if (rc) return rc;
+    const int decim = batch_decim(b);
+    const int64_t chunk = decim > 0 ? decim : 32;
+    int64_t left = nsteps;
+    size_t e = 0;
+    while (left > 0) {
+        bool aligned = decim >= 0;
+        for (const mbf_handle* h : b->m) aligned = aligned && h->step == h->flushed;
+        if (!ev && aligned && left >= chunk) {
+            if (b->gsteps != chunk || !b->gexec) {
+                rc = batch_build_graph(b, chunk);
+                if (rc) return rc;
+            }
+            BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+            for (mbf_handle* h : b->m) {
+                h->step += chunk;
+                h->flushed = h->step;
+            }
+            left -= chunk;
+            continue;
+        }
+        rc = ev ? batch_dispatch(b, (*ev)[e], (*ev)[e + 1], (*ev)[e + 2]) : batch_dispatch(b);
+        if (rc) return rc;
+        e += 3;
+        left -= 1;
+        for (mbf_handle* h : b->m) {
+            h->step += 1;
+            if (h->n_probes == 0) {
+                h->flushed = h->step;
+            } else if (h->step - h->flushed == h->decim) {
+                rc = dispatch_dft(h, h->decim);
+                if (rc) return bfail(b, rc, h->err);
+                h->flushed = h->step;
+            }
+        }
+    }
+    return MBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbf_batch_create(const mbf_config* cfgs, int R, void* stream, mbf_batch** out) {
+    if (!cfgs || !out || R < 1 || R > 255) return bfail(nullptr, MBF_EINVAL, "need 1 to 255 member configurations");
+    *out = nullptr;
+    for (int r = 1; r < R; ++r)
+        if (cfgs[r].precision != cfgs[0].precision)
+            return bfail(nullptr, MBF_EINVAL, "all members of a batch need the same precision");
+    mbf_batch* b = new mbf_batch();
+    b->precision = cfgs[0].precision;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+            delete b;
+            return bfail(nullptr, MBF_ENODEV, "no HIP device");
+        }
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return bfail(nullptr, MBF_EHIP, "hipStreamCreate failed");
+        }
+        b->own_stream = true;
+    }
+    for (int r = 0; r < R; ++r) {
+        mbf_handle* h = nullptr;
+        const int rc = mbf_create(&cfgs[r], b->stream, &h);
+        if (rc) {
+            const std::string msg = "member " + std::to_string(r) + ": " + g_err;
+            mbf_batch_destroy(b);
+            return bfail(nullptr, rc, msg);
+        }
+        h->tun = b->tun;
+        b->m.push_back(h);
+    }
+    *out = b;
+    return MBF_OK;
+}
+
+void mbf_batch_destroy(mbf_batch* b) {
+    if (!b) return;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    batch_free_tables(b);
+    for (mbf_handle* h : b->m) mbf_destroy(h);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* mbf_batch_last_error(const mbf_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+int mbf_batch_size(const mbf_batch* b) { return b ? (int)b->m.size() : 0; }
+
+int mbf_batch_member(mbf_batch* b, int r, mbf_handle** out) {
+    if (!b || !out || r < 0 || r >= (int)b->m.size()) return bfail(b, MBF_EINVAL, "member index out of range");
+    *out = b->m[r];
+    return MBF_OK;
+}
+
+int mbf_batch_set_tuning(mbf_batch* b, const mbf_tuning* t) {
+    if (!b || !t) return bfail(b, MBF_EINVAL, "null argument");
+    for (mbf_handle* h : b->m) {
+        const int rc = mbf_set_tuning(h, t);
+        if (rc) return bfail(b, rc, h->err);
+    }
+    b->tun = b->m[0]->tun;
+    batch_drop_graph(b);
+    return MBF_OK;
+}
+
+int mbf_batch_get_tuning(const mbf_batch* b, mbf_tuning* t) {
+    if (!b || !t) return bfail(nullptr, MBF_EINVAL, "null argument");
+    return mbf_get_tuning(b->m[0], t);
+}
+
+int mbf_batch_step(mbf_batch* b, int64_t nsteps) {
+    if (!b) return bfail(nullptr, MBF_EINVAL, "null batch");
+    return run_batch(b, nsteps, nullptr);
+}
+
+int mbf_batch_sync(mbf_batch* b) {
+    if (!b) return bfail(nullptr, MBF_EINVAL, "null batch");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return MBF_OK;
+}
+
+int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms, int64_t* launches) {
+    if (!b || !kernel_ms || !launches) return bfail(b, MBF_EINVAL, "null argument");
+    if (nsteps < 0 || nsteps > (1 << 20)) return bfail(b, MBF_EINVAL, "step count out of range");
+    std::vector<hipEvent_t> ev((size_t)(3 * nsteps), nullptr);
+    for (auto& x : ev)
+        if (hipEventCreate(&x) != hipSuccess) {
+            for (auto& y : ev) if (y) hipEventDestroy(y);
+            return bfail(b, MBF_EHIP, "hipEventCreate failed");
+        }
+    int rc = run_batch(b, nsteps, &ev);
+    double t0 = 0.0, t1 = 0.0;
+    if (rc == MBF_OK) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) rc = bfail(b, MBF_EHIP, "synchronise failed");
+        for (int64_t q = 0; rc == MBF_OK && q < nsteps; ++q) {
+            float x = 0.0f, y = 0.0f;
+            if (hipEventElapsedTime(&x, ev[3 * q], ev[3 * q + 1]) != hipSuccess ||
+                hipEventElapsedTime(&y, ev[3 * q + 1], ev[3 * q + 2]) != hipSuccess)
+                rc = bfail(b, MBF_EHIP, "hipEventElapsedTime failed");
+            t0 += x;
+            t1 += y;
+        }
+    }
+    for (auto& x : ev) hipEventDestroy(x);
+    kernel_ms[0] = t0;
+    kernel_ms[1] = t1;
+    *launches = nsteps;
+    return rc;
+}
+
+int mbf_batch_step_bytes(const mbf_batch* b, double* bytes) {
+    if (!b || !bytes) return bfail(nullptr, MBF_EINVAL, "null argument");
+    bytes[0] = bytes[1] = bytes[2] = 0.0;
+    for (const mbf_handle* h : b->m) {
+        double x[3];
+        const int rc = mbf_step_bytes(h, x);
+        if (rc) return rc;
+        for (int q = 0; q < 3; ++q) bytes[q] += x[q];
+    }
+    return MBF_OK;
 }
 
 }  // extern "C"

@@ -289,12 +289,32 @@ __device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
 }
 
 // Work item -> (x tile, y tile, z segment), x tile fastest (memory order).
-__device__ __forceinline__ void decode_item(const Geom& g, int& bx, int& by, int& bz) {
-    const int w = xcd_work_item((int)blockIdx.x, g.nblk, g.xcd_remap);
+__device__ __forceinline__ void decode_item(const Geom& g, int w, int& bx, int& by, int& bz) {
     bx = w % g.tiles_x;
     const int r = w / g.tiles_x;
     by = r % g.tiles_y;
     bz = r / g.tiles_y;
+}
+
+// A batch of simulations stepped by one launch per kernel: the device array
+// of the members' views and geometries, and a work table whose entry q holds
+// (member << 24) | work item; entries run member by member, each member's
+// items in order.  Energy and loss partials are indexed by the member's own
+// work item, so a member's sums match its solo run term for term.
+template <typename T>
+struct BatchView {
+    const SimView<T>* views;
+    const Geom* geoms;
+    const uint32_t* items;
+    int nitems;
+    int xcd_remap;
+};
+
+template <typename T>
+__device__ __forceinline__ void batch_item(const BatchView<T>& b, int& r, int& w) {
+    const uint32_t e = b.items[xcd_work_item((int)blockIdx.x, b.nitems, b.xcd_remap)];
+    r = (int)(e >> 24);
+    w = (int)(e & 0xFFFFFFu);
 }
 
 // ---------------------------------------------------------------- row a1
@@ -302,10 +322,10 @@ __device__ __forceinline__ void decode_item(const Geom& g, int& bx, int& by, int
 // energy W^n = 1/2 [sum eps E^n^2 (interior E-sites) + sum H^{n-1/2}.H^{n+1/2}
 // (H-sites off the wall normal to their component)].
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
+__device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
     int bx, by, bz;
-    decode_item(gm, bx, by, bz);
+    decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
@@ -354,7 +374,19 @@ __global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
         }
     }
     const double s = block_sum((double)wsum, sh);
-    if (threadIdx.x == 0 && threadIdx.y == 0) v.e_part[blockIdx.x] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) v.e_part[w] = s;
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
+    curl_h_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_h_batch(BatchView<T> b) {
+    int r, w;
+    batch_item(b, r, w);
+    curl_h_body<T, TY>(b.views[r], b.geoms[r], w);
 }
 
 // ---------------------------------------------------- rows a2, a3, a4, a5
@@ -432,10 +464,10 @@ __device__ __forceinline__ void source3(const SimView<T>& v, int i, int j, int k
 }
 
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
+__device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
     int bx, by, bz;
-    decode_item(gm, bx, by, bz);
+    decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
@@ -506,8 +538,20 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
     }
     if (v.box_on) {
         const double s = block_sum(lsum, sh);
-        if (threadIdx.x == 0 && threadIdx.y == 0) v.l_part[blockIdx.x] = s;
+        if (threadIdx.x == 0 && threadIdx.y == 0) v.l_part[w] = s;
     }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
+    curl_e_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_curl_e_batch(BatchView<T> b) {
+    int r, w;
+    batch_item(b, r, w);
+    curl_e_body<T, TY>(b.views[r], b.geoms[r], w);
 }
 
 // ------------------------------------------------ fused step (a1 to a5)
@@ -522,10 +566,10 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
 // Every recomputed value is the same expression on the same inputs as where
 // it is owned (k_curl_h), so all kernel variants give bitwise identical fields.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
+__device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
     int bx, by, bz;
-    decode_item(gm, bx, by, bz);
+    decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
     const int64_t n = v.ctl->step;
@@ -670,9 +714,21 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
     __syncthreads();
     const double ls = v.box_on ? block_sum(lsum, sh) : 0.0;
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        v.e_part[blockIdx.x] = ws;
-        if (v.box_on) v.l_part[blockIdx.x] = ls;
+        v.e_part[w] = ws;
+        if (v.box_on) v.l_part[w] = ls;
     }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
+    step_fused_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step_fused_batch(BatchView<T> b) {
+    int r, w;
+    batch_item(b, r, w);
+    step_fused_body<T, TY>(b.views[r], b.geoms[r], w);
 }
 
 
@@ -690,8 +746,8 @@ __device__ __forceinline__ int64_t sel3(int a, int64_t x0, int64_t x1, int64_t x
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_mur(SimView<T> v) {
-    const int task = blockIdx.y;
+__device__ __forceinline__ void mur_body(const SimView<T>& v, int task) {
+    if (task >= v.n_mur) return;
     const int code = (int)((v.mur_code >> (5 * task)) & 31u);
     const int a = code & 3, side = (code >> 2) & 1, c = (code >> 3) & 3;
     const int t = 3 - a - c;
@@ -729,6 +785,17 @@ __global__ void __launch_bounds__(256) k_mur(SimView<T> v) {
     En[s] = Ec[s1] + m * (e1new - Ec[s]);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_mur(SimView<T> v) {
+    mur_body(v, (int)blockIdx.y);
+}
+
+// Batched: blockIdx.z is the member (members without Mur walls return).
+template <typename T>
+__global__ void __launch_bounds__(256) k_mur_batch(const SimView<T>* __restrict__ views) {
+    mur_body(views[blockIdx.z], (int)blockIdx.y);
+}
+
 // ------------------------------------------------------ row a7, step end
 // Sum of the per-workgroup partials in a fixed order: each thread keeps eight
 // independent accumulators over a fixed stride (so its loads are in flight
@@ -755,7 +822,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kEndThreads) k_end_step(SimView<T> v) {
+__device__ __forceinline__ void end_step_body(const SimView<T>& v) {
     __shared__ double sh[kEndThreads / 64];
     const int t = threadIdx.x;
     const int64_t n = v.ctl->step;
@@ -777,6 +844,17 @@ __global__ void __launch_bounds__(kEndThreads) k_end_step(SimView<T> v) {
         v.ctl->step = n + 1;
         v.ctl->src_val = v.src_on ? (double)source_value(v, n + 1) : 0.0;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kEndThreads) k_end_step(SimView<T> v) {
+    end_step_body(v);
+}
+
+// Batched: one workgroup per member.
+template <typename T>
+__global__ void __launch_bounds__(kEndThreads) k_end_step_batch(const SimView<T>* __restrict__ views) {
+    end_step_body(views[blockIdx.x]);
 }
 
 // Source value of the current step (after the pump, a checkpoint load or a

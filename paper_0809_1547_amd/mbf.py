@@ -108,6 +108,17 @@ def _load():
         "mbf_get_tuning": (I, [P, C.POINTER(mbf_tuning)]),
         "mbf_step_timed": (I, [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "mbf_step_bytes": (I, [P, C.POINTER(C.c_double)]),
+        "mbf_batch_create": (I, [C.POINTER(mbf_config), I, VP, C.POINTER(P)]),
+        "mbf_batch_destroy": (None, [P]),
+        "mbf_batch_last_error": (C.c_char_p, [P]),
+        "mbf_batch_size": (I, [P]),
+        "mbf_batch_member": (I, [P, I, C.POINTER(P)]),
+        "mbf_batch_set_tuning": (I, [P, C.POINTER(mbf_tuning)]),
+        "mbf_batch_get_tuning": (I, [P, C.POINTER(mbf_tuning)]),
+        "mbf_batch_step": (I, [P, I64]),
+        "mbf_batch_sync": (I, [P]),
+        "mbf_batch_step_timed": (I, [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "mbf_batch_step_bytes": (I, [P, C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -124,12 +135,21 @@ EXPORTED = [
     "mbf_step_index", "mbf_read_energy", "mbf_read_energy_history", "mbf_read_spectrum",
     "mbf_read_loss", "mbf_read_field", "mbf_write_field", "mbf_state_size", "mbf_save_state",
     "mbf_load_state", "mbf_set_tuning", "mbf_get_tuning", "mbf_step_timed", "mbf_step_bytes",
+    "mbf_batch_create", "mbf_batch_destroy", "mbf_batch_last_error", "mbf_batch_size",
+    "mbf_batch_member", "mbf_batch_set_tuning", "mbf_batch_get_tuning", "mbf_batch_step",
+    "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes",
 ]
 
 
 def _check(rc: int, h=None):
     if rc != MBF_OK:
         msg = (lib.mbf_last_error(h) if h else lib.mbf_global_error()) or b""
+        raise MbfError(rc, msg.decode(errors="replace"))
+
+
+def _bcheck(rc: int, b):
+    if rc != MBF_OK:
+        msg = lib.mbf_batch_last_error(b) or b""
         raise MbfError(rc, msg.decode(errors="replace"))
 
 
@@ -298,41 +318,103 @@ def mbf_step_bytes(h: int) -> Tuple[float, float, float]:
     return b[0], b[1], b[2]
 
 
+def mbf_batch_create(cfgs: Sequence[mbf_config], stream: Optional[int] = None) -> int:
+    arr = (mbf_config * len(cfgs))(*cfgs)
+    b = C.c_void_p()
+    _check(lib.mbf_batch_create(arr, len(cfgs), C.c_void_p(stream or 0), C.byref(b)))
+    return b.value
+
+
+def mbf_batch_destroy(b: int) -> None:
+    lib.mbf_batch_destroy(b)
+
+
+def mbf_batch_size(b: int) -> int:
+    return lib.mbf_batch_size(b)
+
+
+def mbf_batch_member(b: int, r: int) -> int:
+    h = C.c_void_p()
+    _bcheck(lib.mbf_batch_member(b, r, C.byref(h)), b)
+    return h.value
+
+
+def mbf_batch_set_tuning(b: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
+                         xcd_remap: int = 1) -> None:
+    t = mbf_tuning(variant, tile_y, zseg, xcd_remap)
+    _bcheck(lib.mbf_batch_set_tuning(b, C.byref(t)), b)
+
+
+def mbf_batch_get_tuning(b: int) -> mbf_tuning:
+    t = mbf_tuning()
+    _bcheck(lib.mbf_batch_get_tuning(b, C.byref(t)), b)
+    return t
+
+
+def mbf_batch_step(b: int, n: int) -> None:
+    _bcheck(lib.mbf_batch_step(b, int(n)), b)
+
+
+def mbf_batch_sync(b: int) -> None:
+    _bcheck(lib.mbf_batch_sync(b), b)
+
+
+def mbf_batch_step_timed(b: int, n: int) -> Tuple[Tuple[float, float], int]:
+    ms = (C.c_double * 2)()
+    cnt = C.c_int64()
+    _bcheck(lib.mbf_batch_step_timed(b, int(n), ms, C.byref(cnt)), b)
+    return (ms[0], ms[1]), cnt.value
+
+
+def mbf_batch_step_bytes(b: int) -> Tuple[float, float, float]:
+    x = (C.c_double * 3)()
+    _bcheck(lib.mbf_batch_step_bytes(b, x), b)
+    return x[0], x[1], x[2]
+
+
 # ------------------------------------------------------------ convenience
+
+def make_config(n, *, boundary=("pec", "pec", "pec"), precision="fp32", noise=True,
+                frozen_pop=False, seed=0, realization=0, energy_history=0, **phys) -> mbf_config:
+    """An mbf_config from the workload defaults and keyword overrides."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    if isinstance(boundary, str):
+        boundary = (boundary,) * 3
+    cfg = mbf_config_default(*n)
+    kinds = {"pec": MBF_PEC, "mur": MBF_MUR1, "absorb": MBF_ABSORB}
+    for a in range(3):
+        cfg.boundary[a] = kinds[boundary[a]]
+    cfg.precision = MBF_FP64 if precision == "fp64" else MBF_FP32
+    cfg.noise = int(bool(noise))
+    cfg.flags = MBF_FLAG_FROZEN_POP if frozen_pop else 0
+    cfg.seed = seed
+    cfg.realization = realization
+    cfg.energy_history = energy_history
+    for k, v in phys.items():
+        if not hasattr(cfg, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(cfg, k, v)
+    return cfg
+
 
 class Sim:
     """One simulation handle with numpy-friendly accessors."""
 
-    def __init__(self, n, *, boundary=("pec", "pec", "pec"), precision="fp32", noise=True,
-                 frozen_pop=False, seed=0, realization=0, energy_history=0, stream=None, **phys):
-        if isinstance(n, int):
-            n = (n, n, n)
-        if isinstance(boundary, str):
-            boundary = (boundary,) * 3
-        cfg = mbf_config_default(*n)
-        kinds = {"pec": MBF_PEC, "mur": MBF_MUR1, "absorb": MBF_ABSORB}
-        for a in range(3):
-            cfg.boundary[a] = kinds[boundary[a]]
-        cfg.precision = MBF_FP64 if precision == "fp64" else MBF_FP32
-        cfg.noise = int(bool(noise))
-        cfg.flags = MBF_FLAG_FROZEN_POP if frozen_pop else 0
-        cfg.seed = seed
-        cfg.realization = realization
-        cfg.energy_history = energy_history
-        for k, v in phys.items():
-            if not hasattr(cfg, k):
-                raise TypeError(f"unknown parameter {k}")
-            setattr(cfg, k, v)
+    def __init__(self, n, *, stream=None, _cfg=None, _handle=None, **kw):
+        cfg = _cfg if _cfg is not None else make_config(n, **kw)
         self.cfg = cfg
-        self.n = tuple(n)
-        self.shape = (n[2] + 1, n[1] + 1, n[0] + 1)
-        self.dtype = np.float64 if precision == "fp64" else np.float32
-        self.h = mbf_create(cfg, stream)
+        self.n = (cfg.nx, cfg.ny, cfg.nz)
+        self.shape = (cfg.nz + 1, cfg.ny + 1, cfg.nx + 1)
+        self.dtype = np.float64 if cfg.precision == MBF_FP64 else np.float32
+        self._owned = _handle is None
+        self.h = mbf_create(cfg, stream) if _handle is None else _handle
         self._np = self._nf = 0
 
     def close(self):
         if getattr(self, "h", None):
-            mbf_destroy(self.h)
+            if self._owned:
+                mbf_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -410,3 +492,52 @@ class Sim:
 
     def load_state(self, buf):
         mbf_load_state(self.h, buf)
+
+
+class Batch:
+    """A batch of simulations stepped together; `members[r]` is a Sim view of
+    member r (owned by the batch)."""
+
+    def __init__(self, configs, stream=None):
+        cfgs = [c if isinstance(c, mbf_config) else make_config(**c) for c in configs]
+        self.b = mbf_batch_create(cfgs, stream)
+        self.members = [Sim(None, _cfg=c, _handle=mbf_batch_member(self.b, r)) for r, c in enumerate(cfgs)]
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, r):
+        return self.members[r]
+
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1):
+        mbf_batch_set_tuning(self.b, _VARIANTS[variant], tile_y, zseg, xcd_remap)
+
+    def tuning(self):
+        t = mbf_batch_get_tuning(self.b)
+        return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant],
+                    tile_y=t.tile_y, zseg=t.zseg, xcd_remap=t.xcd_remap)
+
+    def step(self, n):
+        mbf_batch_step(self.b, n)
+
+    def sync(self):
+        mbf_batch_sync(self.b)
+
+    def step_timed(self, n):
+        return mbf_batch_step_timed(self.b, n)
+
+    def step_bytes(self):
+        return mbf_batch_step_bytes(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.h = None
+            mbf_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,123 @@
+"""GPU: batched stepping of realizations of different sizes (one launch per
+kernel for all members) against the same members stepped alone, and one
+member against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_1547_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [
+    dict(n=(24, 20, 18), boundary="pec", seed=1, realization=0, Na=2e24, src=True, probes=True),
+    dict(n=(33, 17, 29), boundary="absorb", seed=1, realization=1, Na=3e24, src=False, probes=True),
+    dict(n=(16, 16, 16), boundary=("mur", "pec", "mur"), seed=5, realization=2, Na=1e24, src=True, probes=False),
+    dict(n=(70, 12, 9), boundary="absorb", seed=2, realization=7, Na=5e24, src=False, probes=False),
+]
+
+
+def _mbf():
+    from paper_0809_1547_amd import mbf
+    return mbf
+
+
+def _setup(sim, spec, r):
+    mbf = _mbf()
+    eps, gain = I.voxelize(I.rsa_pack(spec["n"], seed=10 + r, fill=0.35))
+    sim.set_material(eps, gain)
+    sim.set_pump(spec["Na"])
+    if spec["src"]:
+        sim.set_source(*I.nearest_void_site(gain), amp=0.2)
+    if spec["probes"]:
+        probes = I.select_probes(eps, gain, 6, seed=r)
+        dt = sim.coefficients()[mbf.MBF_C_DT]
+        sim.set_probes(probes, I.dft_omegas(450e-9, 800e-9, 400, dt), decim=16)
+    sim.set_loss_box((1, 1, 1), (5, 6, 7))
+
+
+def _cfg(spec, hist):
+    mbf = _mbf()
+    return mbf.make_config(spec["n"], boundary=spec["boundary"], seed=spec["seed"],
+                           realization=spec["realization"], energy_history=hist, E_sp=1e-3)
+
+
+def _snapshot(sim, probes):
+    out = [sim.field(f) for f in range(21)]
+    out.append(np.array(sim.energy()))
+    out.append(sim.energy_history())
+    out.append(np.array([sim.loss()]))
+    if probes:
+        out.append(sim.spectrum())
+    return out
+
+
+@pytest.mark.parametrize("variant", ["two_pass", "fused"])
+def test_batch_members_equal_solo_runs(variant):
+    mbf = _mbf()
+    hist = 120
+    batch = mbf.Batch([_cfg(s, hist) for s in MEMBERS])
+    batch.set_tuning(variant, tile_y=4, zseg=4)
+    for r, s in enumerate(MEMBERS):
+        _setup(batch[r], s, r)
+    batch.step(3)          # unaligned start: single batched steps
+    batch.step(100)        # then graph chunks of 16 (the shared probe decimation)
+    got = [_snapshot(batch[r], s["probes"]) for r, s in enumerate(MEMBERS)]
+    assert all(batch[r].step_index == 103 for r in range(len(MEMBERS)))
+    for r, s in enumerate(MEMBERS):
+        solo = mbf.Sim(None, _cfg=_cfg(s, hist))
+        solo.set_tuning(variant, tile_y=4, zseg=4)
+        _setup(solo, s, r)
+        solo.step(103)
+        ref = _snapshot(solo, s["probes"])
+        for q, (a, b) in enumerate(zip(got[r], ref)):
+            assert np.array_equal(a, b), (r, q)
+        solo.close()
+    batch.close()
+
+
+def test_batch_member_matches_oracle():
+    mbf = _mbf()
+    spec = MEMBERS[1]
+    batch = mbf.Batch([_cfg(s, 0) for s in MEMBERS[:2]])
+    for r, s in enumerate(MEMBERS[:2]):
+        _setup(batch[r], s, r)
+    ora = O.Oracle(O.default_params(spec["n"], bc=(O.ABSORB,) * 3, round_f32=True, seed=spec["seed"],
+                                    realization=spec["realization"], E_sp=1e-3))
+    eps, gain = I.voxelize(I.rsa_pack(spec["n"], seed=11, fill=0.35))
+    ora.set_material(eps, gain)
+    ora.set_pump(spec["Na"], O.PREPUMPED)
+    for _ in range(3):
+        batch.step(40)
+        ora.step(40)
+        m = batch[1]
+        for grp in ((0, 1, 2), (3, 4, 5), (6, 7, 8)):
+            num = sum(float(np.sum((m.field(f).astype(np.float64) - ora.field(f)) ** 2)) for f in grp)
+            den = sum(float(np.sum(ora.field(f) ** 2)) for f in grp)
+            assert np.sqrt(num / den) <= 1e-5, grp
+    batch.close()
+
+
+def test_batch_with_different_probe_decimations_and_errors():
+    mbf = _mbf()
+    specs = MEMBERS[:2]
+    batch = mbf.Batch([_cfg(s, 0) for s in specs])
+    with pytest.raises(mbf.MbfError) as err:
+        batch.step(1)                       # no material yet
+    assert err.value.code == mbf.MBF_ESTATE
+    for r, s in enumerate(specs):
+        _setup(batch[r], s, r)
+    dt = batch[1].coefficients()[mbf.MBF_C_DT]
+    eps, gain = I.voxelize(I.rsa_pack(specs[1]["n"], seed=11, fill=0.35))
+    batch[1].set_probes(I.select_probes(eps, gain, 6, seed=1), I.dft_omegas(450e-9, 800e-9, 400, dt), decim=8)
+    batch.step(40)                          # decimations differ: single batched steps
+    for r, s in enumerate(specs):
+        solo = mbf.Sim(None, _cfg=_cfg(s, 0))
+        _setup(solo, s, r)
+        if r == 1:
+            solo.set_probes(I.select_probes(eps, gain, 6, seed=1), I.dft_omegas(450e-9, 800e-9, 400, dt), decim=8)
+        solo.step(40)
+        assert np.array_equal(solo.spectrum(), batch[r].spectrum())
+        assert np.array_equal(solo.field(0), batch[r].field(0))
+        solo.close()
+    batch.close()
