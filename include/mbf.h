@@ -249,6 +249,15 @@ typedef struct mbf_tuning {
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t);
 int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
 
+/* Time candidate schedules (both variants, tile_y 2/4/8, zseg 2/4/8; the
+ * default first) on the handle's own grid for about budget_ms (at least one
+ * candidate), keep the fastest and report it in *chosen (may be NULL).  The
+ * simulation state is saved to device memory before the trials and restored
+ * after them, so the run continues exactly as if autotune had not been
+ * called; this needs one extra copy of the state in device memory
+ * (MBF_ENOMEM otherwise).  Needs material and pump (MBF_ESTATE). */
+int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen);
+
 /* Queue nsteps steps without graph capture, bracketing the field kernels of
  * every step with HIP events on the handle's stream.  On return
  * (synchronised) kernel_ms[0] holds the summed duration of the first field
@@ -305,6 +314,9 @@ int mbf_batch_step(mbf_batch* b, int64_t nsteps);
 int mbf_batch_sync(mbf_batch* b);
 int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms /* [2] */, int64_t* launches);
 int mbf_batch_step_bytes(const mbf_batch* b, double* bytes /* [3] */);
+/* mbf_autotune for a whole batch (the schedule is timed on the batched
+ * launches and applied to the batch and every member). */
+int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen);
 
 #ifdef __cplusplus
 }

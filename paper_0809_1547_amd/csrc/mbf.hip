@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -443,6 +444,75 @@ hipError_t copy_sites(const mbf_handle* h, void* dst, const void* src, bool to_d
     const size_t spitch = to_device ? w : pitch;
     if (async) return hipMemcpy2DAsync(dst, dpitch, src, spitch, w, rows, kind, h->stream);
     return hipMemcpy2D(dst, dpitch, src, spitch, w, rows, kind);
+}
+
+// Device-side snapshot of the whole evolving state (E, H, Bloch state,
+// control block, energy history, spectra and probe ring) into a device buffer,
+// and back; queued on the handle's stream.  Host-side step counters travel
+// with the snapshot record.
+struct Snap {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    int64_t step = 0, flushed = 0;
+};
+
+size_t snap_bytes(const mbf_handle* h) {
+    return (size_t)h->nsite * h->esz * 12 + (size_t)h->glen * h->esz * 15 + sizeof(mbf::Ctl) +
+           sizeof(double) * (size_t)h->hist_cap + sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq +
+           h->esz * (size_t)h->n_probes * h->decim;
+}
+
+int snap_copy(mbf_handle* h, Snap& s, bool save) {
+    struct Part { void* dev; size_t n; };
+    const Part parts[] = {
+        {h->pool, (size_t)h->nsite * h->esz * 12},
+        {h->gpool, (size_t)h->glen * h->esz * 15},
+        {h->ctl, sizeof(mbf::Ctl)},
+        {h->hist, sizeof(double) * (size_t)h->hist_cap},
+        {h->d_spec, sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq},
+        {h->d_ring, h->esz * (size_t)h->n_probes * h->decim},
+    };
+    size_t off = 0;
+    for (const Part& q : parts) {
+        if (q.n == 0 || !q.dev) continue;
+        char* sp = (char*)s.buf + off;
+        HIPCHK(h, hipMemcpyAsync(save ? (void*)sp : q.dev, save ? q.dev : (const void*)sp, q.n,
+                                 hipMemcpyDeviceToDevice, h->stream));
+        off += q.n;
+    }
+    if (save) {
+        s.step = h->step;
+        s.flushed = h->flushed;
+    } else {
+        h->step = s.step;
+        h->flushed = s.flushed;
+    }
+    return MBF_OK;
+}
+
+int snap_alloc(mbf_handle* h, Snap& s) {
+    s.bytes = snap_bytes(h);
+    if (hipMalloc(&s.buf, s.bytes) != hipSuccess) {
+        s.buf = nullptr;
+        return fail(h, MBF_ENOMEM, "device snapshot allocation failed");
+    }
+    return MBF_OK;
+}
+
+void snap_free(Snap& s) {
+    if (s.buf) hipFree(s.buf);
+    s.buf = nullptr;
+}
+
+// Candidate schedules tried by the autotuner, the default first.
+std::vector<mbf_tuning> tuning_candidates() {
+    std::vector<mbf_tuning> c;
+    c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 1});
+    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED})
+        for (int ty : {2, 4, 8})
+            for (int zs : {2, 4, 8})
+                if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 1});
+    return c;
 }
 
 uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t hsh = 1469598103934665603ull) {
@@ -986,6 +1056,44 @@ int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t) {
     if (t->zseg == 0)
         t->zseg = step_zseg(h);
     return MBF_OK;
+}
+
+int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    if (budget_ms < 0) return fail(h, MBF_EINVAL, "negative budget");
+    if (!h->have_material || !h->have_pump) return fail(h, MBF_ESTATE, "set material and pump first");
+    Snap sn;
+    int rc = snap_alloc(h, sn);
+    if (rc) return rc;
+    rc = snap_copy(h, sn, true);
+    const mbf_tuning keep = h->tun;
+    mbf_tuning best = keep;
+    double best_ms = 1e300;
+    const auto t0 = std::chrono::steady_clock::now();
+    int tried = 0;
+    for (const mbf_tuning& cand : tuning_candidates()) {
+        if (rc) break;
+        const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (tried > 0 && el > budget_ms) break;
+        rc = mbf_set_tuning(h, &cand);
+        double ms[2];
+        int64_t cnt = 0;
+        if (!rc) rc = mbf_step_timed(h, 1, ms, &cnt);       // first launch of this shape
+        if (!rc) rc = mbf_step_timed(h, 3, ms, &cnt);
+        if (!rc) rc = snap_copy(h, sn, false);
+        if (rc) break;
+        ++tried;
+        if (ms[0] + ms[1] < best_ms) {
+            best_ms = ms[0] + ms[1];
+            best = cand;
+        }
+    }
+    const int rc2 = mbf_set_tuning(h, rc ? &keep : &best);
+    if (hipStreamSynchronize(h->stream) != hipSuccess && !rc) rc = fail(h, MBF_EHIP, "synchronise failed");
+    snap_free(sn);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    return chosen ? mbf_get_tuning(h, chosen) : MBF_OK;
 }
 
 int mbf_sync(mbf_handle* h) {
@@ -1589,6 +1697,51 @@ int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms, int64_
     kernel_ms[1] = t1;
     *launches = nsteps;
     return rc;
+}
+
+int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
+    if (!b) return bfail(nullptr, MBF_EINVAL, "null batch");
+    if (budget_ms < 0) return bfail(b, MBF_EINVAL, "negative budget");
+    for (mbf_handle* h : b->m)
+        if (!h->have_material || !h->have_pump) return bfail(b, MBF_ESTATE, "set material and pump of every member first");
+    std::vector<Snap> sn(b->m.size());
+    int rc = MBF_OK;
+    for (size_t r = 0; r < b->m.size() && !rc; ++r) {
+        rc = snap_alloc(b->m[r], sn[r]);
+        if (!rc) rc = snap_copy(b->m[r], sn[r], true);
+        if (rc) b->err = b->m[r]->err;
+    }
+    const mbf_tuning keep = b->tun;
+    mbf_tuning best = keep;
+    double best_ms = 1e300;
+    const auto t0 = std::chrono::steady_clock::now();
+    int tried = 0;
+    for (const mbf_tuning& cand : tuning_candidates()) {
+        if (rc) break;
+        const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (tried > 0 && el > budget_ms) break;
+        rc = mbf_batch_set_tuning(b, &cand);
+        double ms[2];
+        int64_t cnt = 0;
+        if (!rc) rc = mbf_batch_step_timed(b, 1, ms, &cnt);
+        if (!rc) rc = mbf_batch_step_timed(b, 3, ms, &cnt);
+        for (size_t r = 0; r < b->m.size() && !rc; ++r) {
+            rc = snap_copy(b->m[r], sn[r], false);
+            if (rc) b->err = b->m[r]->err;
+        }
+        if (rc) break;
+        ++tried;
+        if (ms[0] + ms[1] < best_ms) {
+            best_ms = ms[0] + ms[1];
+            best = cand;
+        }
+    }
+    const int rc2 = mbf_batch_set_tuning(b, rc ? &keep : &best);
+    if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = bfail(b, MBF_EHIP, "synchronise failed");
+    for (Snap& q : sn) snap_free(q);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    return chosen ? mbf_batch_get_tuning(b, chosen) : MBF_OK;
 }
 
 int mbf_batch_step_bytes(const mbf_batch* b, double* bytes) {

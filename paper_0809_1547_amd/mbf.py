@@ -119,6 +119,8 @@ def _load():
         "mbf_batch_sync": (I, [P]),
         "mbf_batch_step_timed": (I, [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "mbf_batch_step_bytes": (I, [P, C.POINTER(C.c_double)]),
+        "mbf_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
+        "mbf_batch_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -137,7 +139,8 @@ EXPORTED = [
     "mbf_load_state", "mbf_set_tuning", "mbf_get_tuning", "mbf_step_timed", "mbf_step_bytes",
     "mbf_batch_create", "mbf_batch_destroy", "mbf_batch_last_error", "mbf_batch_size",
     "mbf_batch_member", "mbf_batch_set_tuning", "mbf_batch_get_tuning", "mbf_batch_step",
-    "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes",
+    "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes", "mbf_autotune",
+    "mbf_batch_autotune",
 ]
 
 
@@ -318,6 +321,23 @@ def mbf_step_bytes(h: int) -> Tuple[float, float, float]:
     return b[0], b[1], b[2]
 
 
+def _tuning_dict(t: mbf_tuning) -> dict:
+    return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant], tile_y=t.tile_y,
+                zseg=t.zseg, xcd_remap=t.xcd_remap)
+
+
+def mbf_autotune(h: int, budget_ms: int = 2000) -> dict:
+    t = mbf_tuning()
+    _check(lib.mbf_autotune(h, int(budget_ms), C.byref(t)), h)
+    return _tuning_dict(t)
+
+
+def mbf_batch_autotune(b: int, budget_ms: int = 2000) -> dict:
+    t = mbf_tuning()
+    _bcheck(lib.mbf_batch_autotune(b, int(budget_ms), C.byref(t)), b)
+    return _tuning_dict(t)
+
+
 def mbf_batch_create(cfgs: Sequence[mbf_config], stream: Optional[int] = None) -> int:
     arr = (mbf_config * len(cfgs))(*cfgs)
     b = C.c_void_p()
@@ -477,9 +497,10 @@ class Sim:
         mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap)
 
     def tuning(self):
-        t = mbf_get_tuning(self.h)
-        return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant],
-                    tile_y=t.tile_y, zseg=t.zseg, xcd_remap=t.xcd_remap)
+        return _tuning_dict(mbf_get_tuning(self.h))
+
+    def autotune(self, budget_ms=2000):
+        return mbf_autotune(self.h, budget_ms)
 
     def step_timed(self, n):
         return mbf_step_timed(self.h, n)
@@ -513,9 +534,10 @@ class Batch:
         mbf_batch_set_tuning(self.b, _VARIANTS[variant], tile_y, zseg, xcd_remap)
 
     def tuning(self):
-        t = mbf_batch_get_tuning(self.b)
-        return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant],
-                    tile_y=t.tile_y, zseg=t.zseg, xcd_remap=t.xcd_remap)
+        return _tuning_dict(mbf_batch_get_tuning(self.b))
+
+    def autotune(self, budget_ms=2000):
+        return mbf_batch_autotune(self.b, budget_ms)
 
     def step(self, n):
         mbf_batch_step(self.b, n)

@@ -121,3 +121,42 @@ def test_batch_with_different_probe_decimations_and_errors():
         assert np.array_equal(solo.field(0), batch[r].field(0))
         solo.close()
     batch.close()
+
+
+def test_autotune_keeps_the_trajectory():
+    # trials run on the live state, which is restored afterwards: the run
+    # continues exactly as a run that was given the chosen schedule directly
+    mbf = _mbf()
+    spec = MEMBERS[0]
+    a = mbf.Sim(None, _cfg=_cfg(spec, 80))
+    _setup(a, spec, 0)
+    a.step(13)
+    chosen = a.autotune(budget_ms=300)
+    assert a.step_index == 13
+    a.step(60)
+    b = mbf.Sim(None, _cfg=_cfg(spec, 80))
+    _setup(b, spec, 0)
+    b.step(13)                 # energy sums follow the schedule: switch at the same step
+    b.set_tuning(**chosen)
+    b.step(60)
+    for x, y in zip(_snapshot(a, True), _snapshot(b, True)):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+    batch = mbf.Batch([_cfg(s, 40) for s in MEMBERS])
+    for r, s in enumerate(MEMBERS):
+        _setup(batch[r], s, r)
+    batch.step(5)
+    chosen = batch.autotune(budget_ms=300)
+    assert batch.tuning() == chosen
+    batch.step(35)
+    for r, s in enumerate(MEMBERS):
+        solo = mbf.Sim(None, _cfg=_cfg(s, 40))
+        _setup(solo, s, r)
+        solo.step(5)
+        solo.set_tuning(**chosen)
+        solo.step(35)
+        for x, y in zip(_snapshot(batch[r], s["probes"]), _snapshot(solo, s["probes"])):
+            assert np.array_equal(x, y), r
+        solo.close()
+    batch.close()
