@@ -1,17 +1,23 @@
 """Throughput benchmark of the Maxwell-Bloch FDTD step on one MI355X.
 
-Workload (default): the paper-scale realization -- 320^3 cells (6.4 um box,
-~8800 RSA spheres of mean diameter 300 nm, index 2.9, fill 0.4, gain in the
-voids), ground-state start, spontaneous-emission noise, 256 probe sites with
-running DFT spectra over 450-800 nm at the resolution of the full 3 ps run,
-graded absorbing walls -- advanced as a batch of 5 pump levels
-N_a in {1, 2, 3.5, 5, 7} x 1e24 m^-3.  One bench step = one time step of all
-5 realizations (5 x 320^3 cell-updates).
+Workload (default, --workload c5): the paper-scale realization -- 320^3 cells
+(6.4 um box, ~8800 RSA spheres of mean diameter 300 nm, index 2.9, fill 0.4,
+gain in the voids), ground-state start, spontaneous-emission noise, 256 probe
+sites with running DFT spectra over 450-800 nm at the resolution of the full
+3 ps run, graded absorbing walls -- advanced as a batch of 5 pump levels
+N_a in {1, 2, 3.5, 5, 7} x 1e24 m^-3, one launch of each step kernel per
+time step for all 5.  One bench step = one time step of all 5 realizations
+(5 x 320^3 cell-updates).
 
-Prints ONE JSON line: cell-updates/s, the roofline of the dominant kernel
-(HBM bound: algorithmic bytes per launch / average launch duration from HIP
-events on its stream) and the FP64 CPU oracle timed on a bounded sample of
-the same workload.
+--workload c3: 64 small realizations of uneven size (N in {48, 64, 80, 96}),
+prepumped, stepped as one autotuned batch and then one at a time through the
+plain path; both rates are printed.
+
+Prints ONE JSON line: cell-updates/s of the graph-replayed batched steps,
+the roofline of the dominant kernel (HBM bound: algorithmic bytes per launch
+/ average launch duration, from HIP events around every launch on its stream
+in a following pass of up to 64 steps) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 
 `python bench.py --summarize-profile DIR` prints, as markdown, the kernel
 table or the per-dispatch counter means of the rocprofv3 database(s) under
@@ -24,6 +30,8 @@ import os
 import re
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -44,6 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--n", type=int, default=320, help="cells per side")
     ap.add_argument("--batch", type=int, default=5)
+    ap.add_argument("--workload", choices=["c5", "c3"], default="c5",
+                    help="c5: 320^3 batch of pump levels (default); c3: 64 small realizations "
+                         "of uneven size, batched against one at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
@@ -93,16 +104,18 @@ def summarize_profile(d):
         db.close()
 
 
-def traffic_from_profiles(kernel, kernel_sha):
+def traffic_from_profiles(kernel, workload, tuning, kernel_sha):
     """Calibrated HBM bytes per launch of `kernel` from the committed counter
-    summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_320c_traffic.md")
+    summary, if it was taken on the current kernel source and schedule."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     s = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
-    if not m or not s or s.group(1) != kernel_sha:
+    t = re.search(r"tuning:\s*(\S+)", txt)
+    want = f"{tuning['variant']}/{tuning['tile_y']}/{tuning['zseg']}/{tuning['xcd_remap']}"
+    if not m or not s or s.group(1) != kernel_sha or not t or t.group(1) != want:
         return None
     return float(m.group(1))
 
@@ -141,6 +154,83 @@ def cpu_baseline(n, eps, gain, seconds):
                       f"{threads} OpenMP threads), after one untimed step"}
 
 
+def c5_batch(args, I, mbf, stream):
+    """The paper-scale workload: a batch of pump levels on one 320^3 packing."""
+    n = args.n
+    t0 = time.perf_counter()
+    pk = I.rsa_pack(n, seed=0, fill=0.4)
+    eps, gain = I.voxelize(pk)
+    log(f"packing: {pk.count} spheres, voxel fill {1 - gain.mean():.3f} ({time.perf_counter() - t0:.1f} s)")
+    probes = I.select_probes(eps, gain, 256, seed=0)
+    cfgs = [mbf.make_config(n, boundary="absorb", seed=0, realization=r) for r in range(args.batch)]
+    batch = mbf.Batch(cfgs, stream=stream.cuda_stream)
+    om = None
+    for r, s in enumerate(batch.members):
+        s.set_material(eps, gain)
+        s.set_pump(NA_LEVELS[r % len(NA_LEVELS)], "ground")
+        dt = s.coefficients()[mbf.MBF_C_DT]
+        om = I.dft_omegas(450e-9, 800e-9, RUN_STEPS_3PS, dt)
+        s.set_probes(probes, om, decim=32)
+    log(f"set-up of {args.batch} x {n}^3 done ({time.perf_counter() - t0:.1f} s), {len(om)} DFT bins")
+    config = {
+        "workload": f"paper-scale realization {n}^3 x batch of {args.batch} pump levels "
+                    f"(RSA spheres d=300nm n=2.9 fill 0.4, gain in voids, ground start, "
+                    f"noise, 256 probes x {len(om)} DFT bins, absorbing walls)",
+        "cells_per_realization": n ** 3,
+        "batch": args.batch,
+        "pump_levels_m3": [NA_LEVELS[r % len(NA_LEVELS)] for r in range(args.batch)],
+    }
+    return batch, n ** 3 * args.batch, config, (eps, gain)
+
+
+def c3_batch(args, I, mbf, stream):
+    """Many small realizations of uneven size: 64 packings with N drawn from
+    {48, 64, 80, 96}, prepumped, with noise, at eight pump levels."""
+    R = 64
+    rng = np.random.default_rng(0)
+    sizes = [int(x) for x in rng.choice([48, 64, 80, 96], size=R)]
+    cfgs = [mbf.make_config(N, boundary="pec", seed=0, realization=r) for r, N in enumerate(sizes)]
+    batch = mbf.Batch(cfgs, stream=stream.cuda_stream)
+    levels = [0.5 * 8 ** (p / 7) * 2e24 for p in range(8)]
+    mats = []
+    for r, N in enumerate(sizes):
+        eps, gain = I.voxelize(I.rsa_pack(N, seed=r, fill=0.4))
+        mats.append((eps, gain))
+        batch[r].set_material(eps, gain)
+        batch[r].set_pump(levels[r % 8], "prepumped")
+    cells = sum(N ** 3 for N in sizes)
+    config = {
+        "workload": f"{R} realizations of uneven size (N in {{48,64,80,96}}, {cells} cells in all), "
+                    "RSA spheres d=300nm n=2.9 fill 0.4, prepumped, noise, 8 pump levels, PEC walls",
+        "sizes": sizes,
+    }
+    return batch, cells, config, (sizes, mats, levels)
+
+
+def one_at_a_time(mbf, sizes, mats, levels, steps, tuning):
+    """The same realizations stepped one after another through the plain path
+    (each with its own graph): cell-updates/s."""
+    import torch
+    sims = []
+    for r, N in enumerate(sizes):
+        s = mbf.Sim(N, boundary="pec", seed=0, realization=r)
+        s.set_tuning(**tuning)
+        s.set_material(*mats[r])
+        s.set_pump(levels[r % 8], "prepumped")
+        s.step(32)
+        sims.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    for s in sims:
+        s.sync()
+    dt = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    return sum(N ** 3 for N in sizes) * steps / dt
+
+
 def main():
     args = parse()
     if args.summarize_profile:
@@ -150,70 +240,55 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is a design note, not built", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_0809_1547_amd import inputs as I
     from paper_0809_1547_amd import mbf
 
-    n = args.n
-    t0 = time.perf_counter()
-    pk = I.rsa_pack(n, seed=0, fill=0.4)
-    eps, gain = I.voxelize(pk)
-    log(f"packing: {pk.count} spheres, voxel fill {1 - gain.mean():.3f} ({time.perf_counter() - t0:.1f} s)")
-    probes = I.select_probes(eps, gain, 256, seed=0)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    sims = []
-    for r in range(args.batch):
-        s = mbf.Sim(n, boundary="absorb", seed=0, realization=r, stream=stream.cuda_stream)
-        s.set_material(eps, gain)
-        s.set_pump(NA_LEVELS[r % len(NA_LEVELS)], "ground")
-        dt = s.coefficients()[mbf.MBF_C_DT]
-        om = I.dft_omegas(450e-9, 800e-9, RUN_STEPS_3PS, dt)
-        s.set_probes(probes, om, decim=32)
-        sims.append(s)
-    log(f"set-up of {args.batch} x {n}^3 done ({time.perf_counter() - t0:.1f} s), "
-        f"{len(om)} DFT bins, tuning {sims[0].tuning()}")
-    tuning = sims[0].tuning()
-    for s in sims:
-        s.step(args.warmup)
-    torch.cuda.synchronize()
+    if args.workload == "c3":
+        batch, cells, config, extra = c3_batch(args, I, mbf, stream)
+        tuning = batch.autotune(budget_ms=3000)
+        log(f"autotuned: {tuning}")
+    else:
+        batch, cells, config, extra = c5_batch(args, I, mbf, stream)
+        tuning = batch.tuning()
+    config["tuning"] = tuning
+    batch.step(args.warmup)
+    batch.sync()
     log("warm-up done")
 
+    # throughput: the production path (graph-replayed chunks of batched steps)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    kern_ms = [0.0, 0.0]
-    launches = 0
     torch.cuda.synchronize()
     ev0.record(stream)
-    for s in sims:
-        ms, cnt = s.step_timed(args.steps)
-        kern_ms[0] += ms[0]
-        kern_ms[1] += ms[1]
-        launches += cnt
+    batch.step(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall_ms = ev0.elapsed_time(ev1)
-    for s in sims:
-        W, _ = s.energy()                 # raises on a non-finite energy
-    cells = n ** 3
-    cu = cells * args.batch * args.steps
-    value = cu / (wall_ms / 1e3)
-    alg = sims[0].step_bytes()            # same material map for every member
+    for s in batch.members:
+        s.energy()                        # raises on a non-finite energy
+    value = cells * args.steps / (wall_ms / 1e3)
+    # kernel roofline: the same kernels launched step by step with HIP events
+    # around them on the batch's stream
+    kern_ms, launches = batch.step_timed(min(args.steps, 64))
+    alg = batch.step_bytes()
     two_pass = tuning["variant"] == "two_pass"
     # the dominant kernel: the fused step kernel, or the longer of the two passes
     q = 1 if two_pass and kern_ms[1] >= kern_ms[0] else 0
-    kname = ("k_curl_e" if q else "k_curl_h") if two_pass else "k_step_fused"
-    kdesc = {"k_curl_e": "k_curl_e (rows a2-a6: Ampere update, Lorentz polarisation, rate "
-                         "equations, noise, walls; one launch per realization and step)",
-             "k_curl_h": "k_curl_h (row a1: Faraday update and the energy partials)",
-             "k_step_fused": "k_step_fused (rows a1-a6 in one launch per realization and step)"}[kname]
+    kname = ("k_curl_e_batch" if q else "k_curl_h_batch") if two_pass else "k_step_fused_batch"
+    kdesc = {"k_curl_e_batch": "k_curl_e_batch (rows a2-a6: Ampere update, Lorentz polarisation, "
+                               "rate equations, noise, walls; one launch per step for all realizations)",
+             "k_curl_h_batch": "k_curl_h_batch (row a1: Faraday update and the energy partials)",
+             "k_step_fused_batch": "k_step_fused_batch (rows a1-a6 in one launch per step for all "
+                                   "realizations)"}[kname]
     alg_bytes = alg[1 + q] if two_pass else alg[0]
     avg_kern_s = kern_ms[q] / launches / 1e3
     achieved = alg_bytes / avg_kern_s / 1e9
     sha = kernel_source_sha()
-    traffic = traffic_from_profiles(kname, sha)
-    log(f"timed {args.steps} steps x {args.batch}: {wall_ms:.1f} ms; per launch "
+    traffic = traffic_from_profiles(kname, args.workload, tuning, sha)
+    log(f"timed {args.steps} batched steps: {wall_ms:.1f} ms; kernel pass per launch "
         f"{kern_ms[0] / launches:.3f} + {kern_ms[1] / launches:.3f} ms; "
         f"{alg[0] / cells:.1f} alg. B/cell per step; kernel source {sha}")
 
@@ -225,10 +300,18 @@ def main():
         del a, b
 
     cpu = None
-    if not args.no_cpu_baseline:
-        for s in sims:
-            s.close()
-        cpu = cpu_baseline(n, eps, gain, args.cpu_seconds)
+    extra_out = {}
+    if args.workload == "c3":
+        batch.close()
+        sizes, mats, levels = extra
+        solo = one_at_a_time(mbf, sizes, mats, levels, args.steps, tuning)
+        extra_out["one_at_a_time"] = {"value": solo, "unit": "cell-updates/s",
+                                      "ratio_batched_over_solo": value / solo}
+        log(f"one at a time: {solo:.3e} cu/s; batched / one at a time = {value / solo:.2f}")
+    elif not args.no_cpu_baseline:
+        batch.close()
+        eps, gain = extra
+        cpu = cpu_baseline(args.n, eps, gain, args.cpu_seconds)
         log(f"cpu baseline: {cpu}")
 
     out = {
@@ -244,15 +327,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": f"paper-scale realization {n}^3 x batch of {args.batch} pump levels "
-                        f"(RSA spheres d=300nm n=2.9 fill 0.4, gain in voids, ground start, "
-                        f"noise, 256 probes x {len(om)} DFT bins, absorbing walls)",
-            "cells_per_realization": cells,
-            "batch": args.batch,
-            "pump_levels_m3": [NA_LEVELS[r % len(NA_LEVELS)] for r in range(args.batch)],
-            "tuning": tuning,
-        },
+        "config": config,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -268,6 +343,7 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    out.update(extra_out)
     print(json.dumps(out), flush=True)
 
 

@@ -237,7 +237,12 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  *     a2-a5 in a second.
  *   MBF_VARIANT_FUSED: rows a1-a5 in one z-marching kernel in which every
  *     wave owns a row and forms again the few H^{n+1/2} values of the
- *     neighbouring row, column and plane that it needs (no LDS, no barrier). */
+ *     neighbouring row, column and plane that it needs (no LDS, no barrier).
+ * group_mb (batches only; >= 0): consecutive members whose device state adds
+ * up to at most group_mb MiB form a group, and a graph-replayed chunk of
+ * steps runs group by group, so that a group's state can stay in the
+ * device's last-level cache over the chunk; 0 puts all members in one group.
+ * Results do not depend on it. */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 typedef struct mbf_tuning {
@@ -245,6 +250,7 @@ typedef struct mbf_tuning {
     int32_t tile_y;
     int32_t zseg;
     int32_t xcd_remap;
+    int32_t group_mb;
 } mbf_tuning;
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t);
 int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
@@ -314,8 +320,9 @@ int mbf_batch_step(mbf_batch* b, int64_t nsteps);
 int mbf_batch_sync(mbf_batch* b);
 int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms /* [2] */, int64_t* launches);
 int mbf_batch_step_bytes(const mbf_batch* b, double* bytes /* [3] */);
-/* mbf_autotune for a whole batch (the schedule is timed on the batched
- * launches and applied to the batch and every member). */
+/* mbf_autotune for a whole batch: the schedule is timed on graph-replayed
+ * batched chunks, then group_mb (0, 64, 128, 192) for the best schedule; the
+ * result applies to the batch and every member. */
 int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen);
 
 #ifdef __cplusplus

@@ -78,7 +78,7 @@ struct mbf_handle {
         mur_c[mbf::kMaxMurTasks] = {};
     Coef co{};
     double Na_si = 0.0;
-    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1};
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1, 0};
     void* prof = nullptr;     // lossy-layer profiles: [axis][integer, half][n_axis + 1]
     int64_t prof_stride = 0;
     bool has_layer = false;
@@ -507,11 +507,11 @@ void snap_free(Snap& s) {
 // Candidate schedules tried by the autotuner, the default first.
 std::vector<mbf_tuning> tuning_candidates() {
     std::vector<mbf_tuning> c;
-    c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 1});
+    c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 1, 0});
     for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED})
         for (int ty : {2, 4, 8})
             for (int zs : {2, 4, 8})
-                if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 1});
+                if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 1, 0});
     return c;
 }
 
@@ -1044,6 +1044,7 @@ int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
     if (t->tile_y != 2 && t->tile_y != 4 && t->tile_y != 8 && t->tile_y != 16)
         return fail(h, MBF_EINVAL, "tile_y must be 2, 4, 8 or 16");
     if (t->zseg < 0) return fail(h, MBF_EINVAL, "zseg must be >= 0");
+    if (t->group_mb < 0) return fail(h, MBF_EINVAL, "group_mb must be >= 0");
     h->tun = *t;
     h->tun.xcd_remap = t->xcd_remap ? 1 : 0;
     drop_graph(h);
@@ -1356,13 +1357,19 @@ struct mbf_batch {
     bool own_stream = false;
     int precision = MBF_FP32;
     std::string err;
-    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1};
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1, 0};
     void* d_views = nullptr;
     mbf::Geom* d_geoms = nullptr;
     uint32_t* d_items = nullptr;
     int nitems = 0;
-    int mur_tasks = 0;
-    int64_t mur_sites = 0;
+    struct Group {
+        int r0, r1;               // members [r0, r1)
+        int i0, i1;               // work-table entries [i0, i1)
+        int mur_tasks;
+        int64_t mur_sites;
+    };
+    std::vector<Group> groups;
+    Group all{0, 0, 0, 0, 0, 0};  // every member as one group (timed steps)
     std::vector<uint64_t> seen;   // member versions the device tables describe
     bool tables = false;
     hipGraphExec_t gexec = nullptr;
@@ -1410,19 +1417,30 @@ int batch_tables(mbf_batch* b) {
     std::vector<mbf::SimView<T>> views(R);
     std::vector<mbf::Geom> geoms(R);
     std::vector<uint32_t> items;
-    b->mur_tasks = 0;
-    b->mur_sites = 0;
+    b->groups.clear();
+    const double budget = (double)b->tun.group_mb * 1048576.0;
+    double gbytes = 0.0;
     for (int r = 0; r < R; ++r) {
         mbf_handle* h = b->m[r];
         geoms[r] = step_geom(h);
         views[r] = view<T>(h);
         views[r].n_part = geoms[r].nblk;
         if (geoms[r].nblk >= (1 << 24)) return bfail(b, MBF_EINVAL, "member grid has too many work items");
+        // a new group when this member would overflow the budget
+        const double mb = (double)snap_bytes(h);
+        if (b->groups.empty() || (budget > 0.0 && gbytes + mb > budget)) {
+            b->groups.push_back({r, r, (int)items.size(), (int)items.size(), 0, 0});
+            gbytes = 0.0;
+        }
+        mbf_batch::Group& gr = b->groups.back();
+        gbytes += mb;
         for (int w = 0; w < geoms[r].nblk; ++w) items.push_back(((uint32_t)r << 24) | (uint32_t)w);
+        gr.r1 = r + 1;
+        gr.i1 = (int)items.size();
         if (h->mur_tasks > 0) {
             const int64_t nmax = std::max({h->cfg.nx, h->cfg.ny, h->cfg.nz}) + 1;
-            b->mur_tasks = std::max(b->mur_tasks, h->mur_tasks);
-            b->mur_sites = std::max(b->mur_sites, nmax * nmax);
+            gr.mur_tasks = std::max(gr.mur_tasks, h->mur_tasks);
+            gr.mur_sites = std::max(gr.mur_sites, nmax * nmax);
         }
     }
     if (hipMalloc(&b->d_views, sizeof(mbf::SimView<T>) * R) != hipSuccess ||
@@ -1435,66 +1453,77 @@ int batch_tables(mbf_batch* b) {
     BHIPCHK(b, hipMemcpy(b->d_geoms, geoms.data(), sizeof(mbf::Geom) * R, hipMemcpyHostToDevice));
     BHIPCHK(b, hipMemcpy(b->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice));
     b->nitems = (int)items.size();
+    b->all = {0, R, 0, b->nitems, 0, 0};
+    for (const mbf_batch::Group& gr : b->groups) {
+        b->all.mur_tasks = std::max(b->all.mur_tasks, gr.mur_tasks);
+        b->all.mur_sites = std::max(b->all.mur_sites, gr.mur_sites);
+    }
     b->seen.resize(R);
     for (int r = 0; r < R; ++r) b->seen[r] = b->m[r]->version;
     b->tables = true;
     return MBF_OK;
 }
 
+// One step of the members of group gi, or of all members when gi < 0.
 template <typename T>
-int batch_launch_step(mbf_batch* b, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
+int batch_launch_step(mbf_batch* b, int gi, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
                       hipEvent_t ev1 = nullptr) {
-    const mbf::BatchView<T> bv{reinterpret_cast<const mbf::SimView<T>*>(b->d_views), b->d_geoms,
-                               b->d_items, b->nitems, b->tun.xcd_remap};
-    const dim3 g((unsigned)b->nitems);
+    const mbf_batch::Group& gr = gi < 0 ? b->all : b->groups[gi];
+    const mbf::SimView<T>* vw = reinterpret_cast<const mbf::SimView<T>*>(b->d_views);
+    const mbf::Geom* gw = b->d_geoms;
+    const uint32_t* it = b->d_items + gr.i0;
+    const int ni = gr.i1 - gr.i0, rm = b->tun.xcd_remap;
+    const dim3 g((unsigned)ni);
     hipStream_t st = b->stream;
     if (ev0) BHIPCHK(b, hipEventRecord(ev0, st));
     if (b->tun.variant == MBF_VARIANT_FUSED) {
         switch (b->tun.tile_y) {
-            case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, bv); break;
-            case 4: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 4>), g, dim3(64, 4), 0, st, bv); break;
-            case 16: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 16>), g, dim3(64, 16), 0, st, bv); break;
-            default: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 8>), g, dim3(64, 8), 0, st, bv); break;
+            case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
+            case 4: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm); break;
+            case 16: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm); break;
+            default: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm); break;
         }
         if (evm) BHIPCHK(b, hipEventRecord(evm, st));
     } else {
         switch (b->tun.tile_y) {
             case 2:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
                 if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
                 break;
             case 4:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
                 if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
                 break;
             case 16:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
                 if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
                 break;
             default:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
                 if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, bv);
+                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
                 break;
         }
     }
     if (ev1) BHIPCHK(b, hipEventRecord(ev1, st));
-    const mbf::SimView<T>* views = reinterpret_cast<const mbf::SimView<T>*>(b->d_views);
-    if (b->mur_tasks > 0) {
-        const dim3 gm((unsigned)((b->mur_sites + 255) / 256), (unsigned)b->mur_tasks, (unsigned)b->m.size());
+    const mbf::SimView<T>* views = reinterpret_cast<const mbf::SimView<T>*>(b->d_views) + gr.r0;
+    const unsigned nm = (unsigned)(gr.r1 - gr.r0);
+    if (gr.mur_tasks > 0) {
+        const dim3 gm((unsigned)((gr.mur_sites + 255) / 256), (unsigned)gr.mur_tasks, nm);
         hipLaunchKernelGGL(mbf::k_mur_batch<T>, gm, dim3(256), 0, st, views);
     }
-    hipLaunchKernelGGL(mbf::k_end_step_batch<T>, dim3((unsigned)b->m.size()), dim3(mbf::kEndThreads), 0, st, views);
+    hipLaunchKernelGGL(mbf::k_end_step_batch<T>, dim3(nm), dim3(mbf::kEndThreads), 0, st, views);
     BHIPCHK(b, hipGetLastError());
     return MBF_OK;
 }
 
-int batch_dispatch(mbf_batch* b, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr, hipEvent_t ev1 = nullptr) {
-    return b->precision == MBF_FP64 ? batch_launch_step<double>(b, ev0, evm, ev1)
-                                    : batch_launch_step<float>(b, ev0, evm, ev1);
+int batch_dispatch(mbf_batch* b, int gi, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
+                   hipEvent_t ev1 = nullptr) {
+    return b->precision == MBF_FP64 ? batch_launch_step<double>(b, gi, ev0, evm, ev1)
+                                    : batch_launch_step<float>(b, gi, ev0, evm, ev1);
 }
 
 // Probe decimation shared by the members with probes (0: none has probes,
@@ -1514,12 +1543,15 @@ int batch_build_graph(mbf_batch* b, int64_t n) {
     hipGraph_t g = nullptr;
     BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
     int rc = MBF_OK;
-    for (int64_t q = 0; q < n && rc == MBF_OK; ++q) rc = batch_dispatch(b);
-    for (mbf_handle* h : b->m)
-        if (rc == MBF_OK && h->n_probes > 0) {
-            rc = dispatch_dft(h, (int)n);
-            if (rc) b->err = h->err;
-        }
+    // the whole chunk for one group, then the next group
+    for (int gi = 0; gi < (int)b->groups.size() && rc == MBF_OK; ++gi) {
+        for (int64_t q = 0; q < n && rc == MBF_OK; ++q) rc = batch_dispatch(b, gi);
+        for (int r = b->groups[gi].r0; r < b->groups[gi].r1 && rc == MBF_OK; ++r)
+            if (b->m[r]->n_probes > 0) {
+                rc = dispatch_dft(b->m[r], (int)n);
+                if (rc) b->err = b->m[r]->err;
+            }
+    }
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc != MBF_OK) {
         if (g) hipGraphDestroy(g);
@@ -1564,7 +1596,12 @@ int run_batch(mbf_batch* b, int64_t nsteps, std::vector<hipEvent_t>* ev) {
             left -= chunk;
             continue;
         }
-        rc = ev ? batch_dispatch(b, (*ev)[e], (*ev)[e + 1], (*ev)[e + 2]) : batch_dispatch(b);
+        // a single step: every group once (timed steps run as one group)
+        if (ev) {
+            rc = batch_dispatch(b, -1, (*ev)[e], (*ev)[e + 1], (*ev)[e + 2]);
+        } else {
+            for (int gi = 0; gi < (int)b->groups.size() && rc == MBF_OK; ++gi) rc = batch_dispatch(b, gi);
+        }
         if (rc) return rc;
         e += 3;
         left -= 1;
@@ -1711,33 +1748,64 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
         if (!rc) rc = snap_copy(b->m[r], sn[r], true);
         if (rc) b->err = b->m[r]->err;
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = bfail(b, MBF_EHIP, "hipEventCreate failed");
+    const int decim = batch_decim(b);
+    const int64_t chunk = decim > 0 ? decim : 32;
+    // time two graph-replayed chunks after one that builds the graph, then
+    // put the saved state back
+    auto trial = [&](const mbf_tuning& cand, double& ms) -> int {
+        int q = mbf_batch_set_tuning(b, &cand);
+        if (!q) q = run_batch(b, chunk, nullptr);
+        if (!q && hipEventRecord(e0, b->stream) != hipSuccess) q = bfail(b, MBF_EHIP, "hipEventRecord failed");
+        if (!q) q = run_batch(b, 2 * chunk, nullptr);
+        if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = bfail(b, MBF_EHIP, "hipEventRecord failed");
+        if (!q && hipEventSynchronize(e1) != hipSuccess) q = bfail(b, MBF_EHIP, "hipEventSynchronize failed");
+        float f = 0.0f;
+        if (!q && hipEventElapsedTime(&f, e0, e1) != hipSuccess) q = bfail(b, MBF_EHIP, "hipEventElapsedTime failed");
+        ms = f;
+        for (size_t r = 0; r < b->m.size() && !q; ++r) {
+            q = snap_copy(b->m[r], sn[r], false);
+            if (q) b->err = b->m[r]->err;
+        }
+        return q;
+    };
     const mbf_tuning keep = b->tun;
     mbf_tuning best = keep;
     double best_ms = 1e300;
     const auto t0 = std::chrono::steady_clock::now();
+    auto over = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > budget_ms;
+    };
     int tried = 0;
-    for (const mbf_tuning& cand : tuning_candidates()) {
-        if (rc) break;
-        const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (tried > 0 && el > budget_ms) break;
-        rc = mbf_batch_set_tuning(b, &cand);
-        double ms[2];
-        int64_t cnt = 0;
-        if (!rc) rc = mbf_batch_step_timed(b, 1, ms, &cnt);
-        if (!rc) rc = mbf_batch_step_timed(b, 3, ms, &cnt);
-        for (size_t r = 0; r < b->m.size() && !rc; ++r) {
-            rc = snap_copy(b->m[r], sn[r], false);
-            if (rc) b->err = b->m[r]->err;
-        }
-        if (rc) break;
+    for (mbf_tuning cand : tuning_candidates()) {        // schedule, at the current grouping
+        if (rc || (tried > 0 && over())) break;
+        cand.group_mb = keep.group_mb;
+        double ms = 0.0;
+        rc = trial(cand, ms);
         ++tried;
-        if (ms[0] + ms[1] < best_ms) {
-            best_ms = ms[0] + ms[1];
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    for (int g : {0, 64, 128, 192}) {                    // then the grouping
+        if (rc || over()) break;
+        if (g == best.group_mb) continue;
+        mbf_tuning cand = best;
+        cand.group_mb = g;
+        double ms = 0.0;
+        rc = trial(cand, ms);
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
             best = cand;
         }
     }
     const int rc2 = mbf_batch_set_tuning(b, rc ? &keep : &best);
     if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = bfail(b, MBF_EHIP, "synchronise failed");
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
     for (Snap& q : sn) snap_free(q);
     if (rc) return rc;
     if (rc2) return rc2;

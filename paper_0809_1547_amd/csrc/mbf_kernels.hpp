@@ -174,6 +174,27 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
     return r;
 }
 
+// Loads and stores at a 32-bit element offset from a uniform base: the
+// address is base + zero-extended 32-bit byte offset, which maps to the
+// scalar-base form of the global memory instructions.  The pointers are
+// cast to the global address space: a pointer read from a view in memory
+// (the batched kernels) would otherwise be generic and use flat accesses.
+#define MBF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t off) {
+    const MBF_GLOBAL char* b = (const MBF_GLOBAL char*)base;
+    return *(const MBF_GLOBAL T*)(b + off * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, uint32_t off, T val) {
+    MBF_GLOBAL char* b = (MBF_GLOBAL char*)base;
+    *(MBF_GLOBAL T*)(b + off * (uint32_t)sizeof(T)) = val;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const MBF_GLOBAL T*)p;
+}
+
 // Field pointers of one step, chosen once per kernel from the step parity
 // (uniform selects; the kernel-argument arrays are only ever indexed with
 // compile-time constants, so nothing is copied to private memory).
@@ -212,29 +233,17 @@ __device__ __forceinline__ Fields<T> bind_fields(const SimView<T>& v, int par) {
 // of component c (half positions along the two other axes).
 template <typename T>
 __device__ __forceinline__ T loss_e(const SimView<T>& v, int c, int i, int j, int k) {
-    return (v.prof[0][c == 0][i] + v.prof[1][c == 1][j]) + v.prof[2][c == 2][k];
+    return (gld(v.prof[0][c == 0] + i) + gld(v.prof[1][c == 1] + j)) + gld(v.prof[2][c == 2] + k);
 }
 template <typename T>
 __device__ __forceinline__ T loss_h(const SimView<T>& v, int c, int i, int j, int k) {
-    return (v.prof[0][c != 0][i] + v.prof[1][c != 1][j]) + v.prof[2][c != 2][k];
+    return (gld(v.prof[0][c != 0] + i) + gld(v.prof[1][c != 1] + j)) + gld(v.prof[2][c != 2] + k);
 }
 
 // Faraday update with the semi-implicit loss of the layer
 // (H' - H = -S curl - a (H' + H)); a = 0 is the plain Yee update.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-
-// Loads and stores at a 32-bit element offset from a uniform base: the
-// address is base + zero-extended 32-bit byte offset, which maps to the
-// scalar-base form of the global memory instructions.
-template <typename T>
-__device__ __forceinline__ T ldo(const T* base, uint32_t off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * (uint32_t)sizeof(T));
-}
-template <typename T>
-__device__ __forceinline__ void sto(T* base, uint32_t off, T val) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off * (uint32_t)sizeof(T)) = val;
-}
 
 // Compact index of the calling lane's cell in the Bloch-state arrays.  Must
 // be called by the whole wave that covers x segment bx of row (j, k) (lanes
@@ -247,7 +256,7 @@ __device__ __forceinline__ uint32_t gain_index(const SimView<T>& v, int bx, int 
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     const int seg = __builtin_amdgcn_readfirstlane(bx + v.nbx * (j + v.ny * k));
-    const uint32_t base = row_ok ? v.seg_base[seg] : 0u;
+    const uint32_t base = row_ok ? gld(v.seg_base + seg) : 0u;
     return base + below;
 }
 
@@ -301,18 +310,10 @@ __device__ __forceinline__ void decode_item(const Geom& g, int w, int& bx, int& 
 // (member << 24) | work item; entries run member by member, each member's
 // items in order.  Energy and loss partials are indexed by the member's own
 // work item, so a member's sums match its solo run term for term.
-template <typename T>
-struct BatchView {
-    const SimView<T>* views;
-    const Geom* geoms;
-    const uint32_t* items;
-    int nitems;
-    int xcd_remap;
-};
 
-template <typename T>
-__device__ __forceinline__ void batch_item(const BatchView<T>& b, int& r, int& w) {
-    const uint32_t e = b.items[xcd_work_item((int)blockIdx.x, b.nitems, b.xcd_remap)];
+__device__ __forceinline__ void batch_item(const uint32_t* __restrict__ items, int nitems, int remap,
+                                           int& r, int& w) {
+    const uint32_t e = items[xcd_work_item((int)blockIdx.x, nitems, remap)];
     r = (int)(e >> 24);
     w = (int)(e & 0xFFFFFFu);
 }
@@ -328,7 +329,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
     decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
-    const int64_t n = v.ctl->step;
+    const int64_t n = gld(&v.ctl->step);
     const int par = (int)(n & 1);
     const Fields<T> f = bind_fields(v, par);
     T wsum = (T)0;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             sto(f.hn[0], x, nhx);
             sto(f.hn[1], x, nhy);
             sto(f.hn[2], x, nhz);
-            const T eps = v.lut_eps[ldo(v.mat, x)];
+            const T eps = gld(v.lut_eps + ldo(v.mat, x));
             T acc = (T)0;
             if (j >= 1 && k >= 1) acc += eps * ex * ex;
             if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -374,7 +375,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
         }
     }
     const double s = block_sum((double)wsum, sh);
-    if (threadIdx.x == 0 && threadIdx.y == 0) v.e_part[w] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) sto(v.e_part, (uint32_t)w, s);
 }
 
 template <typename T, int TY>
@@ -382,11 +383,15 @@ __global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
     curl_h_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
 }
 
+// The tables are separate no-alias read-only arguments, so the compiler may
+// keep the member's view in scalar registers across the kernel's stores.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_h_batch(BatchView<T> b) {
+__global__ void __launch_bounds__(64 * TY) k_curl_h_batch(const SimView<T>* __restrict__ views,
+                                                const Geom* __restrict__ geoms,
+                                                const uint32_t* __restrict__ items, int nitems, int remap) {
     int r, w;
-    batch_item(b, r, w);
-    curl_h_body<T, TY>(b.views[r], b.geoms[r], w);
+    batch_item(items, nitems, remap, r, w);
+    curl_h_body<T, TY>(views[r], geoms[r], w);
 }
 
 // ---------------------------------------------------- rows a2, a3, a4, a5
@@ -456,7 +461,7 @@ __device__ __forceinline__ void source3(const SimView<T>& v, int i, int j, int k
     s0 = s1 = s2 = (T)0;
     (void)n;
     if (v.src_on && i == v.src_i && j == v.src_j && k == v.src_k) {
-        const T sv = (T)v.ctl->src_val;
+        const T sv = (T)gld(&v.ctl->src_val);
         s0 = v.src_comp == 0 ? sv : (T)0;
         s1 = v.src_comp == 1 ? sv : (T)0;
         s2 = v.src_comp == 2 ? sv : (T)0;
@@ -470,7 +475,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
     decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
-    const int64_t n = v.ctl->step;
+    const int64_t n = gld(&v.ctl->step);
     const int par = (int)(n & 1);
     const Fields<T> f = bind_fields(v, par);
     double lsum = 0.0;
@@ -498,7 +503,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
             const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
             const T hx = ldo(Hx, x), hy = ldo(Hy, x), hz = ldo(Hz, x);
-            const T ie = v.lut_inv_eps[m];
+            const T ie = gld(v.lut_inv_eps + m);
             T xi[3] = {(T)0, (T)0, (T)0};
             if (g && v.noise && (inx || iny || inz)) {
                 const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
@@ -538,7 +543,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
     }
     if (v.box_on) {
         const double s = block_sum(lsum, sh);
-        if (threadIdx.x == 0 && threadIdx.y == 0) v.l_part[w] = s;
+        if (threadIdx.x == 0 && threadIdx.y == 0) sto(v.l_part, (uint32_t)w, s);
     }
 }
 
@@ -547,11 +552,15 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
     curl_e_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
 }
 
+// The tables are separate no-alias read-only arguments, so the compiler may
+// keep the member's view in scalar registers across the kernel's stores.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_e_batch(BatchView<T> b) {
+__global__ void __launch_bounds__(64 * TY) k_curl_e_batch(const SimView<T>* __restrict__ views,
+                                                const Geom* __restrict__ geoms,
+                                                const uint32_t* __restrict__ items, int nitems, int remap) {
     int r, w;
-    batch_item(b, r, w);
-    curl_e_body<T, TY>(b.views[r], b.geoms[r], w);
+    batch_item(items, nitems, remap, r, w);
+    curl_e_body<T, TY>(views[r], geoms[r], w);
 }
 
 // ------------------------------------------------ fused step (a1 to a5)
@@ -572,7 +581,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
     decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
-    const int64_t n = v.ctl->step;
+    const int64_t n = gld(&v.ctl->step);
     const Fields<T> f = bind_fields(v, (int)(n & 1));
     T wsum = (T)0;
     double lsum = 0.0;
@@ -634,7 +643,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 sto(f.hn[0], x, nhx);
                 sto(f.hn[1], x, nhy);
                 sto(f.hn[2], x, nhz);
-                const T eps = v.lut_eps[m];
+                const T eps = gld(v.lut_eps + m);
                 T acc = (T)0;
                 if (j >= 1 && k >= 1) acc += eps * ex * ex;
                 if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -668,7 +677,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             }
             // ---- a2-a5 on the own row
             if (act) {
-                const T ie = v.lut_inv_eps[m];
+                const T ie = gld(v.lut_inv_eps + m);
                 T xi[3] = {(T)0, (T)0, (T)0};
                 if (g && v.noise && (inx || iny || inz)) {
                     const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
@@ -714,8 +723,8 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
     __syncthreads();
     const double ls = v.box_on ? block_sum(lsum, sh) : 0.0;
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        v.e_part[w] = ws;
-        if (v.box_on) v.l_part[w] = ls;
+        sto(v.e_part, (uint32_t)w, ws);
+        if (v.box_on) sto(v.l_part, (uint32_t)w, ls);
     }
 }
 
@@ -724,11 +733,15 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
     step_fused_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
 }
 
+// The tables are separate no-alias read-only arguments, so the compiler may
+// keep the member's view in scalar registers across the kernel's stores.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_step_fused_batch(BatchView<T> b) {
+__global__ void __launch_bounds__(64 * TY) k_step_fused_batch(const SimView<T>* __restrict__ views,
+                                                const Geom* __restrict__ geoms,
+                                                const uint32_t* __restrict__ items, int nitems, int remap) {
     int r, w;
-    batch_item(b, r, w);
-    step_fused_body<T, TY>(b.views[r], b.geoms[r], w);
+    batch_item(items, nitems, remap, r, w);
+    step_fused_body<T, TY>(views[r], geoms[r], w);
 }
 
 
@@ -761,7 +774,7 @@ __device__ __forceinline__ void mur_body(const SimView<T>& v, int task) {
     const bool on_t = (w == 0 || w == ntd);
     const bool t_is_mur = ((v.mur_axes >> t) & 1) != 0;
     if (on_t && (!t_is_mur || t > a)) return;
-    const int par = (int)(v.ctl->step & 1);   // parity of the step being finished
+    const int par = (int)(gld(&v.ctl->step) & 1);   // parity of the step being finished
     const Fields<T> f = bind_fields(v, par);
     const T* __restrict__ Ec = c == 0 ? f.e[0] : (c == 1 ? f.e[1] : f.e[2]);
     T* __restrict__ En = c == 0 ? f.en[0] : (c == 1 ? f.en[1] : f.en[2]);
@@ -825,7 +838,7 @@ template <typename T>
 __device__ __forceinline__ void end_step_body(const SimView<T>& v) {
     __shared__ double sh[kEndThreads / 64];
     const int t = threadIdx.x;
-    const int64_t n = v.ctl->step;
+    const int64_t n = gld(&v.ctl->step);
     const double W = sum_partials(v.e_part, v.n_part, sh);
     __syncthreads();
     const double L = v.box_on ? sum_partials(v.l_part, v.n_part, sh) : 0.0;

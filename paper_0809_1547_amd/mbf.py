@@ -59,7 +59,7 @@ class mbf_config(C.Structure):
 
 class mbf_tuning(C.Structure):
     _fields_ = [("variant", C.c_int32), ("tile_y", C.c_int32), ("zseg", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("group_mb", C.c_int32)]
 
 
 MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED = 0, 1
@@ -295,8 +295,8 @@ def mbf_load_state(h: int, buf: bytes) -> None:
 
 
 def mbf_set_tuning(h: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
-                   xcd_remap: int = 1) -> None:
-    t = mbf_tuning(variant, tile_y, zseg, xcd_remap)
+                   xcd_remap: int = 1, group_mb: int = 0) -> None:
+    t = mbf_tuning(variant, tile_y, zseg, xcd_remap, group_mb)
     _check(lib.mbf_set_tuning(h, C.byref(t)), h)
 
 
@@ -323,7 +323,7 @@ def mbf_step_bytes(h: int) -> Tuple[float, float, float]:
 
 def _tuning_dict(t: mbf_tuning) -> dict:
     return dict(variant={v: k for k, v in _VARIANTS.items()}[t.variant], tile_y=t.tile_y,
-                zseg=t.zseg, xcd_remap=t.xcd_remap)
+                zseg=t.zseg, xcd_remap=t.xcd_remap, group_mb=t.group_mb)
 
 
 def mbf_autotune(h: int, budget_ms: int = 2000) -> dict:
@@ -360,8 +360,8 @@ def mbf_batch_member(b: int, r: int) -> int:
 
 
 def mbf_batch_set_tuning(b: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
-                         xcd_remap: int = 1) -> None:
-    t = mbf_tuning(variant, tile_y, zseg, xcd_remap)
+                         xcd_remap: int = 1, group_mb: int = 0) -> None:
+    t = mbf_tuning(variant, tile_y, zseg, xcd_remap, group_mb)
     _bcheck(lib.mbf_batch_set_tuning(b, C.byref(t)), b)
 
 
@@ -493,8 +493,8 @@ class Sim:
     def loss(self):
         return mbf_read_loss(self.h)
 
-    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1):
-        mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap)
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1, group_mb=0):
+        mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)
 
     def tuning(self):
         return _tuning_dict(mbf_get_tuning(self.h))
@@ -530,8 +530,8 @@ class Batch:
     def __getitem__(self, r):
         return self.members[r]
 
-    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1):
-        mbf_batch_set_tuning(self.b, _VARIANTS[variant], tile_y, zseg, xcd_remap)
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1, group_mb=0):
+        mbf_batch_set_tuning(self.b, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)
 
     def tuning(self):
         return _tuning_dict(mbf_batch_get_tuning(self.b))

@@ -52,12 +52,14 @@ def _snapshot(sim, probes):
     return out
 
 
-@pytest.mark.parametrize("variant", ["two_pass", "fused"])
-def test_batch_members_equal_solo_runs(variant):
+@pytest.mark.parametrize("variant,group_mb", [("two_pass", 0), ("fused", 0), ("two_pass", 1), ("fused", 2)])
+def test_batch_members_equal_solo_runs(variant, group_mb):
+    # group_mb 1 and 2 split the members into groups that run whole graph
+    # chunks one after the other
     mbf = _mbf()
     hist = 120
     batch = mbf.Batch([_cfg(s, hist) for s in MEMBERS])
-    batch.set_tuning(variant, tile_y=4, zseg=4)
+    batch.set_tuning(variant, tile_y=4, zseg=4, group_mb=group_mb)
     for r, s in enumerate(MEMBERS):
         _setup(batch[r], s, r)
     batch.step(3)          # unaligned start: single batched steps
