@@ -81,6 +81,10 @@ def lib():
         L.orc_pop_next.argtypes = [dp, dp, C.c_double, C.c_double]
         L.orc_p_series.argtypes = [dp, dp, dp, C.c_int64, dp]
         L.orc_pop_series.argtypes = [dp, dp, dp, dp, C.c_int64, dp]
+        pp = C.POINTER(dp)
+        L.orc_adjoint_run.argtypes = [P, C.c_int64, dp, dp, dp]
+        L.orc_tangent_step.argtypes = [P, pp, pp]
+        L.orc_adjoint_step.argtypes = [P, pp, pp]
         _lib = L
     return _lib
 
@@ -219,6 +223,33 @@ class Oracle:
 
     def loss(self) -> float:
         return lib().orc_read_loss(self._h)
+
+    def adjoint_run(self, nsteps: int):
+        """(L, dL/d eps_r per cell (nz, ny, nx), dL/dN_a) of the loss-box
+        objective over nsteps from the pump; advances the run."""
+        g = np.zeros((self.n[2], self.n[1], self.n[0]))
+        gna, L = C.c_double(), C.c_double()
+        if lib().orc_adjoint_run(self._h, int(nsteps), _dp(g), C.byref(gna), C.byref(L)) != 0:
+            raise ValueError("adjoint needs a loss box, step 0 and no Mur walls")
+        return L.value, g, gna.value
+
+    def _lin(self, fn, vecs):
+        vin = [np.ascontiguousarray(v, dtype=np.float64) for v in vecs]
+        assert len(vin) == 24 and all(v.shape == self.shape for v in vin)
+        vout = [np.empty(self.shape) for _ in range(24)]
+        pin = (C.POINTER(C.c_double) * 24)(*[_dp(v) for v in vin])
+        pout = (C.POINTER(C.c_double) * 24)(*[_dp(v) for v in vout])
+        if fn(self._h, pin, pout) != 0:
+            raise ValueError("not available with Mur walls")
+        return vout
+
+    def tangent_step(self, v):
+        """J v for one step at the current state (24 field arrays in id order)."""
+        return self._lin(lib().orc_tangent_step, v)
+
+    def adjoint_step(self, w):
+        """J^T w for one step at the current state."""
+        return self._lin(lib().orc_adjoint_step, w)
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:

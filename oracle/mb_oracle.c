@@ -48,6 +48,7 @@ struct orc_sim {
     int64_t hist_len, hist_cap;
     double* plane_sum;         /* per-plane partial sums, summed in order */
     double* prof[3][2];        /* loss profile per axis at integer / half positions */
+    int init_kind;             /* initial populations of the last orc_set_pump */
 };
 
 static double rnd(const orc_sim* s, double v) { return s->p.round_f32 ? (double)(float)v : v; }
@@ -309,6 +310,7 @@ int orc_set_pump(orc_sim* s, double Na_si, int init) {
     } else {
         return -1;
     }
+    s->init_kind = init;
     for (int q = 0; q < 12; ++q) memset(s->f[q], 0, sizeof(double) * s->ntot);
     for (int q = 12; q < 24; ++q) memset(s->f[q], 0, sizeof(double) * s->ntot);
     for (int k = 0; k <= s->nz; ++k)
@@ -644,3 +646,317 @@ int orc_step(orc_sim* s, int64_t nsteps) {
     }
     return 0;
 }
+
+/* ============================================================ adjoint
+ * Reverse-mode derivative of the loss-box objective
+ *     L = sum over steps n = 1..N of sum over interior E-sites in the box of (E^n)^2
+ * with respect to eps_r of every cell and to the pump density N_a, for runs
+ * that start from orc_set_pump (step 0).  The state of step n is the 24 site
+ * arrays X^n = (E, H, P, P_prev, N1, N2, N3, N0); one step is the map
+ * X^{n+1} = F(X^n; eps, N_a) of orc_step, and the adjoint runs the transposed
+ * linearisation of F backwards over the stored trajectory.  Mur walls are not
+ * supported (their coefficient would make the wall rows depend on eps). */
+
+typedef double* state_t[ORC_NFIELDS];
+
+static int state_alloc(const orc_sim* s, state_t X) {
+    for (int q = 0; q < ORC_NFIELDS; ++q) {
+        X[q] = (double*)calloc(s->ntot, sizeof(double));
+        if (!X[q]) return -1;
+    }
+    return 0;
+}
+
+static void state_free(state_t X) {
+    for (int q = 0; q < ORC_NFIELDS; ++q) { free(X[q]); X[q] = NULL; }
+}
+
+/* The sim's fields after one more step, computed on a copy. */
+static int forward_copy(const orc_sim* s, state_t X1) {
+    orc_sim* t = orc_create(&s->p);
+    if (!t) return -1;
+    size_t ncell = (size_t)s->nx * s->ny * s->nz;
+    memcpy(t->eps, s->eps, ncell * sizeof(double));
+    memcpy(t->inv_eps, s->inv_eps, ncell * sizeof(double));
+    memcpy(t->gain, s->gain, ncell);
+    memcpy(t->coef, s->coef, sizeof(s->coef));
+    memcpy(t->rates, s->rates, sizeof(s->rates));
+    for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(t->f[q], s->f[q], sizeof(double) * s->ntot);
+    t->step = s->step;
+    t->src_on = s->src_on; t->src_comp = s->src_comp;
+    t->src_i = s->src_i; t->src_j = s->src_j; t->src_k = s->src_k;
+    t->src_amp = s->src_amp; t->src_ws = s->src_ws; t->src_tp = s->src_tp; t->src_t0 = s->src_t0;
+    orc_step(t, 1);
+    for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(X1[q], t->f[q], sizeof(double) * s->ntot);
+    orc_destroy(t);
+    return 0;
+}
+
+static int has_mur(const orc_sim* s) {
+    return s->p.bc[0] == ORC_MUR1 || s->p.bc[1] == ORC_MUR1 || s->p.bc[2] == ORC_MUR1;
+}
+
+/* curl- of an H-type array at E-site (c; i,j,k) and curl+ of an E-type array
+ * at H-site (c; i,j,k), the stencils of a3 and a1.  Values outside the
+ * extended range count as zero. */
+static double get0(const orc_sim* s, const double* a, int i, int j, int k) {
+    if (i < 0 || j < 0 || k < 0 || i > s->nx || j > s->ny || k > s->nz) return 0.0;
+    return a[at(s, i, j, k)];
+}
+
+static double curl_minus(const orc_sim* s, double* const* h, int c, int i, int j, int k) {
+    if (c == 0) return (get0(s, h[2], i, j, k) - get0(s, h[2], i, j - 1, k)) - (get0(s, h[1], i, j, k) - get0(s, h[1], i, j, k - 1));
+    if (c == 1) return (get0(s, h[0], i, j, k) - get0(s, h[0], i, j, k - 1)) - (get0(s, h[2], i, j, k) - get0(s, h[2], i - 1, j, k));
+    return (get0(s, h[1], i, j, k) - get0(s, h[1], i - 1, j, k)) - (get0(s, h[0], i, j, k) - get0(s, h[0], i, j - 1, k));
+}
+
+static double curl_plus(const orc_sim* s, double* const* e, int c, int i, int j, int k) {
+    if (c == 0) return (get0(s, e[2], i, j + 1, k) - get0(s, e[2], i, j, k)) - (get0(s, e[1], i, j, k + 1) - get0(s, e[1], i, j, k));
+    if (c == 1) return (get0(s, e[0], i, j, k + 1) - get0(s, e[0], i, j, k)) - (get0(s, e[2], i + 1, j, k) - get0(s, e[2], i, j, k));
+    return (get0(s, e[1], i + 1, j, k) - get0(s, e[1], i, j, k)) - (get0(s, e[0], i, j + 1, k) - get0(s, e[0], i, j, k));
+}
+
+static int h_updated(const orc_sim* s, int i, int j, int k) {
+    return i < s->nx && j < s->ny && k < s->nz;
+}
+
+/* Tangent-linear step: dX1 = J(X0) dX0, the derivative of one step taken at
+ * X0 (X1 = F(X0) given) with eps and N_a fixed. */
+static void tangent_step(const orc_sim* s, state_t X0, state_t X1, double* const* v, double** y) {
+    const double* c = s->coef;
+    const double S = c[ORC_C_S];
+    for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(y[q], v[q], sizeof(double) * s->ntot);
+    /* H' = da H - db S curl+ E on [0,n)^3; the step leaves the other H-sites at
+     * zero (they are never updated), so their derivative is zero */
+    for (int q = 3; q < 6; ++q) memset(y[q], 0, sizeof(double) * s->ntot);
+    for (int k = 0; k < s->nz; ++k)
+        for (int j = 0; j < s->ny; ++j)
+            for (int i = 0; i < s->nx; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    const double a = site_loss(s, 1, cc, i, j, k);
+                    const double da = (1.0 - a) / (1.0 + a), db = 1.0 / (1.0 + a);
+                    y[3 + cc][at(s, i, j, k)] = da * v[3 + cc][at(s, i, j, k)] - db * S * curl_plus(s, (double* const*)v, cc, i, j, k);
+                }
+    for (int k = 0; k <= s->nz; ++k)
+        for (int j = 0; j <= s->ny; ++j)
+            for (int i = 0; i <= s->nx; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    if (!e_interior(s, cc, i, j, k)) continue;
+                    const size_t x = at(s, i, j, k), cell = cell_of(s, i, j, k);
+                    const double ie = s->inv_eps[cell];
+                    const double a = site_loss(s, 0, cc, i, j, k);
+                    const double ca = (1.0 - a) / (1.0 + a), cb = 1.0 / (1.0 + a);
+                    double ddP = 0.0;
+                    if (s->gain[cell]) {
+                        const double E = X0[cc][x], dN = X0[12 + cc][x] - X0[15 + cc][x];
+                        const double dPn = c[ORC_C_A] * v[6 + cc][x] + c[ORC_C_B] * v[9 + cc][x] +
+                                           c[ORC_C_CK] * (v[12 + cc][x] - v[15 + cc][x]) * E +
+                                           c[ORC_C_CK] * dN * v[cc][x];
+                        ddP = dPn - v[6 + cc][x];
+                        y[6 + cc][x] = dPn;
+                        y[9 + cc][x] = v[6 + cc][x];
+                    }
+                    const double dEn = ca * v[cc][x] + cb * ie * (S * curl_minus(s, y + 3, cc, i, j, k) - ddP);
+                    y[cc][x] = dEn;
+                    if (s->gain[cell]) {
+                        const double dPf = X1[6 + cc][x] - X0[6 + cc][x];
+                        const double dW = c[ORC_C_BETA] * 0.5 * ((dEn + v[cc][x]) * dPf + (X1[cc][x] + X0[cc][x]) * ddP);
+                        const double n0 = v[21 + cc][x], n1 = v[12 + cc][x], n2 = v[15 + cc][x], n3 = v[18 + cc][x];
+                        y[21 + cc][x] = n0 + c[ORC_C_DT10] * n1 - c[ORC_C_DTWP] * n0;
+                        y[12 + cc][x] = n1 + c[ORC_C_DT21] * n2 - c[ORC_C_DT10] * n1 - dW;
+                        y[15 + cc][x] = n2 + c[ORC_C_DT32] * n3 - c[ORC_C_DT21] * n2 + dW;
+                        y[18 + cc][x] = n3 + c[ORC_C_DTWP] * n0 - c[ORC_C_DT32] * n3;
+                    }
+                }
+}
+
+/* Adjoint step: z = J(X0)^T w, plus the parameter terms of this step:
+ * g_eps[cell] += dL/d eps_r and *g_na += dL/d(N_a / N_ref) through the noise
+ * amplitude (both may be NULL).  step_n is the index of the step X0 -> X1. */
+static void adjoint_step(const orc_sim* s, state_t X0, state_t X1, int64_t step_n,
+                         double* const* w, double** z, double* g_eps, double* g_na) {
+    const double* c = s->coef;
+    const double S = c[ORC_C_S];
+    const size_t nt = s->ntot;
+    double* etot[3];
+    double* u[3];
+    double* htot[3];
+    double* vh[3];
+    for (int q = 0; q < 3; ++q) {
+        etot[q] = (double*)calloc(nt, sizeof(double));
+        u[q] = (double*)calloc(nt, sizeof(double));
+        htot[q] = (double*)calloc(nt, sizeof(double));
+        vh[q] = (double*)calloc(nt, sizeof(double));
+    }
+    for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(z[q], w[q], sizeof(double) * nt);   /* identity rows */
+    /* E' enters W: the total adjoint of E' and u = cb ie etot at interior sites */
+    for (int k = 0; k <= s->nz; ++k)
+        for (int j = 0; j <= s->ny; ++j)
+            for (int i = 0; i <= s->nx; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    const size_t x = at(s, i, j, k);
+                    etot[cc][x] = w[cc][x];
+                    if (!e_interior(s, cc, i, j, k)) continue;
+                    const size_t cell = cell_of(s, i, j, k);
+                    if (s->gain[cell]) {
+                        const double Wh = w[15 + cc][x] - w[12 + cc][x];
+                        const double dPf = X1[6 + cc][x] - X0[6 + cc][x];
+                        etot[cc][x] += Wh * c[ORC_C_BETA] * 0.5 * dPf;
+                    }
+                    const double a = site_loss(s, 0, cc, i, j, k);
+                    u[cc][x] = (1.0 / (1.0 + a)) * s->inv_eps[cell] * etot[cc][x];
+                }
+    /* H: the adjoint of H' collects S curl+ u (the transpose of curl- is curl+) */
+    for (int k = 0; k <= s->nz; ++k)
+        for (int j = 0; j <= s->ny; ++j)
+            for (int i = 0; i <= s->nx; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    const size_t x = at(s, i, j, k);
+                    if (!h_updated(s, i, j, k)) {   /* zeroed by the step */
+                        htot[cc][x] = 0.0;
+                        z[3 + cc][x] = 0.0;
+                        continue;
+                    }
+                    htot[cc][x] = w[3 + cc][x] + S * curl_plus(s, u, cc, i, j, k);
+                    const double a = site_loss(s, 1, cc, i, j, k);
+                    z[3 + cc][x] = ((1.0 - a) / (1.0 + a)) * htot[cc][x];
+                    vh[cc][x] = (1.0 / (1.0 + a)) * htot[cc][x];
+                }
+    /* E: identity or ca etot, minus S curl- (db htot) (the transpose of curl+),
+     * and the Bloch terms at interior gain sites */
+    double* Hn[3] = {X1[3], X1[4], X1[5]};
+    for (int k = 0; k <= s->nz; ++k)
+        for (int j = 0; j <= s->ny; ++j)
+            for (int i = 0; i <= s->nx; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    const size_t x = at(s, i, j, k);
+                    double e_adj = w[cc][x];
+                    const int in = e_interior(s, cc, i, j, k);
+                    if (in) {
+                        const double a = site_loss(s, 0, cc, i, j, k);
+                        e_adj = ((1.0 - a) / (1.0 + a)) * etot[cc][x];
+                    }
+                    e_adj -= S * curl_minus(s, vh, cc, i, j, k);
+                    if (in) {
+                        const size_t cell = cell_of(s, i, j, k);
+                        const double ie = s->inv_eps[cell];
+                        const double a = site_loss(s, 0, cc, i, j, k);
+                        const double cb = 1.0 / (1.0 + a);
+                        double dPf = 0.0;
+                        if (s->gain[cell]) {
+                            dPf = X1[6 + cc][x] - X0[6 + cc][x];
+                            const double E = X0[cc][x], En = X1[cc][x];
+                            const double Wh = w[15 + cc][x] - w[12 + cc][x];
+                            const double dPh = Wh * c[ORC_C_BETA] * 0.5 * (En + E) - cb * ie * etot[cc][x];
+                            const double pn = w[6 + cc][x] + dPh;
+                            const double dN = X0[12 + cc][x] - X0[15 + cc][x];
+                            e_adj += c[ORC_C_CK] * dN * pn + Wh * c[ORC_C_BETA] * 0.5 * dPf;
+                            z[6 + cc][x] = w[9 + cc][x] + c[ORC_C_A] * pn - dPh;
+                            z[9 + cc][x] = c[ORC_C_B] * pn;
+                            const double n0 = w[21 + cc][x], n1 = w[12 + cc][x], n2 = w[15 + cc][x], n3 = w[18 + cc][x];
+                            z[21 + cc][x] = n0 * (1.0 - c[ORC_C_DTWP]) + n3 * c[ORC_C_DTWP];
+                            z[12 + cc][x] = n1 * (1.0 - c[ORC_C_DT10]) + n0 * c[ORC_C_DT10] + c[ORC_C_CK] * E * pn;
+                            z[15 + cc][x] = n2 * (1.0 - c[ORC_C_DT21]) + n1 * c[ORC_C_DT21] - c[ORC_C_CK] * E * pn;
+                            z[18 + cc][x] = n3 * (1.0 - c[ORC_C_DT32]) + n2 * c[ORC_C_DT32];
+                            if (g_na && s->p.noise && c[ORC_C_CF] != 0.0) {
+                                double xi[3];
+                                orc_normals3(s->p.seed, (uint32_t)cell, (uint32_t)step_n, s->p.realization, xi);
+                                *g_na += c[ORC_C_CK] * s->p.E_sp * xi[cc] * pn;
+                            }
+                        }
+                        if (g_eps) {
+                            /* E' depends on eps through ie = 1/eps: d ie / d eps = -ie^2 */
+                            const double rhs = S * curl_minus(s, Hn, cc, i, j, k) - dPf;
+                            g_eps[cell] += etot[cc][x] * cb * rhs * (-ie * ie);
+                        }
+                    }
+                    z[cc][x] = e_adj;
+                }
+    for (int q = 0; q < 3; ++q) { free(etot[q]); free(u[q]); free(htot[q]); free(vh[q]); }
+}
+
+int orc_tangent_step(orc_sim* s, double* const* v, double** y) {
+    if (has_mur(s)) return -1;
+    state_t X0, X1;
+    for (int q = 0; q < ORC_NFIELDS; ++q) X0[q] = s->f[q];
+    if (state_alloc(s, X1) || forward_copy(s, X1)) { state_free(X1); return -1; }
+    tangent_step(s, X0, X1, v, y);
+    state_free(X1);
+    return 0;
+}
+
+int orc_adjoint_step(orc_sim* s, double* const* w, double** z) {
+    if (has_mur(s)) return -1;
+    state_t X0, X1;
+    for (int q = 0; q < ORC_NFIELDS; ++q) X0[q] = s->f[q];
+    if (state_alloc(s, X1) || forward_copy(s, X1)) { state_free(X1); return -1; }
+    adjoint_step(s, X0, X1, s->step, w, z, NULL, NULL);
+    state_free(X1);
+    return 0;
+}
+
+int orc_adjoint_run(orc_sim* s, int64_t nsteps, double* grad_eps, double* grad_Na, double* loss) {
+    if (has_mur(s) || !s->box_on || s->step != 0 || nsteps < 1) return -1;
+    const size_t nt = s->ntot;
+    const size_t ncell = (size_t)s->nx * s->ny * s->nz;
+    state_t* X = (state_t*)calloc((size_t)nsteps + 1, sizeof(state_t));
+    if (!X) return -1;
+    int rc = 0;
+    for (int64_t n = 0; n <= nsteps && !rc; ++n) rc = state_alloc(s, X[n]);
+    /* forward, keeping every state */
+    double L = 0.0;
+    for (int64_t n = 0; n <= nsteps && !rc; ++n) {
+        if (n > 0) {
+            const double l0 = s->loss;
+            orc_step(s, 1);
+            L += s->loss - l0;
+        }
+        for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(X[n][q], s->f[q], sizeof(double) * nt);
+    }
+    state_t lam, nxt;
+    if (!rc) rc = state_alloc(s, lam);
+    if (!rc) rc = state_alloc(s, nxt);
+    double g_na = 0.0;
+    if (!rc) {
+        memset(grad_eps, 0, ncell * sizeof(double));
+        for (int64_t n = nsteps; n >= 1; --n) {
+            /* dL/dE^n = 2 E^n on the interior sites of the box */
+            for (int k = s->box[2]; k < s->box[5]; ++k)
+                for (int j = s->box[1]; j < s->box[4]; ++j)
+                    for (int i = s->box[0]; i < s->box[3]; ++i)
+                        for (int cc = 0; cc < 3; ++cc)
+                            if (e_interior(s, cc, i, j, k)) {
+                                const size_t x = at(s, i, j, k);
+                                lam[cc][x] += 2.0 * X[n][cc][x];
+                            }
+            adjoint_step(s, X[n - 1], X[n], n - 1, lam, nxt, grad_eps, &g_na);
+            for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(lam[q], nxt[q], sizeof(double) * nt);
+        }
+        /* initial populations: N_i^0 = r_i (N_a / N_ref) on interior gain sites */
+        double r[4] = {0.0, 0.0, 0.0, 0.0};   /* N0, N1, N2, N3 */
+        if (s->init_kind == ORC_INIT_GROUND) {
+            r[0] = 1.0;
+        } else {
+            double d32 = s->rates[0], d21 = s->rates[1], d10 = s->rates[2], dwp = s->rates[3];
+            double r0 = 1.0 / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
+            r[0] = r0; r[3] = dwp * r0 / d32; r[2] = dwp * r0 / d21; r[1] = dwp * r0 / d10;
+        }
+        for (int k = 0; k <= s->nz; ++k)
+            for (int j = 0; j <= s->ny; ++j)
+                for (int i = 0; i <= s->nx; ++i)
+                    for (int cc = 0; cc < 3; ++cc) {
+                        if (!e_interior(s, cc, i, j, k) || !s->gain[cell_of(s, i, j, k)]) continue;
+                        const size_t x = at(s, i, j, k);
+                        g_na += r[0] * lam[21 + cc][x] + r[1] * lam[12 + cc][x] + r[2] * lam[15 + cc][x] +
+                                r[3] * lam[18 + cc][x];
+                    }
+        *grad_Na = g_na / s->p.N_ref;
+        *loss = L;
+    }
+    state_free(lam);
+    state_free(nxt);
+    for (int64_t n = 0; n <= nsteps; ++n) state_free(X[n]);
+    free(X);
+    return rc;
+}
+

@@ -99,6 +99,18 @@ int64_t  orc_energy_history(const orc_sim* s, double* out, int64_t cap);
 void     orc_read_spectrum(const orc_sim* s, double* re_im);
 double   orc_read_loss(const orc_sim* s);
 
+/* Adjoint of the loss-box objective L = sum_{n=1..N} sum_{box} (E^n)^2 over a
+ * run of nsteps that starts at orc_set_pump (step 0), with PEC or lossy-layer
+ * walls (no Mur).  Advances the sim by nsteps and returns L, dL/d eps_r per
+ * cell (grad_eps[nx*ny*nz]) and dL/dN_a (per m^-3).  The whole trajectory is
+ * kept in memory (small grids only).  -1 when not applicable. */
+int      orc_adjoint_run(orc_sim* s, int64_t nsteps, double* grad_eps, double* grad_Na,
+                         double* loss);
+/* One step's linearisation at the current state (not advanced), on the 24
+ * field arrays in field-id order: tangent y = J v and adjoint z = J^T w. */
+int      orc_tangent_step(orc_sim* s, double* const* v, double** y);
+int      orc_adjoint_step(orc_sim* s, double* const* w, double** z);
+
 /* building blocks, exported so the tests can pin them in isolation; the grid
  * stepper calls exactly these */
 void     orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

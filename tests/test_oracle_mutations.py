@@ -10,8 +10,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mb_oracle.c")
-PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_yee.py", "tests/test_oracle_bloch.py",
-        "tests/test_oracle_monitors.py"]
+# the adjoint pins run first: they take under a second, and their comparison
+# of the tangent step with differences of the forward step also trips on most
+# mistakes in the forward step
+PINS = ["tests/test_oracle_adjoint.py", "tests/test_oracle_rng.py", "tests/test_oracle_yee.py",
+        "tests/test_oracle_bloch.py", "tests/test_oracle_monitors.py"]
 
 # (name, original text, mutated text)
 MUTATIONS = [
@@ -43,6 +46,18 @@ MUTATIONS = [
     ("layer_loss_sign", "s->Hn[c][x] = ((1.0 - a) / (1.0 + a)) * H3[c][x]", "s->Hn[c][x] = ((1.0 + a) / (1.0 + a)) * H3[c][x]"),
     ("layer_e_scale", "(1.0 / (1.0 + a)) * (ie * (S * curl - dP));", "(ie * (S * curl - dP));"),
     ("prepump_fixed_point", "N[2] = rnd(s, dwp * n0 / d21);", "N[2] = rnd(s, dwp * n0 / d32);"),
+    ("adjoint_curl_transpose_sign", "htot[cc][x] = w[3 + cc][x] + S * curl_plus(s, u, cc, i, j, k);",
+     "htot[cc][x] = w[3 + cc][x] - S * curl_plus(s, u, cc, i, j, k);"),
+    ("adjoint_missing_work_term", "e_adj += c[ORC_C_CK] * dN * pn + Wh * c[ORC_C_BETA] * 0.5 * dPf;",
+     "e_adj += c[ORC_C_CK] * dN * pn;"),
+    ("adjoint_history_coefficient", "z[9 + cc][x] = c[ORC_C_B] * pn;", "z[9 + cc][x] = c[ORC_C_A] * pn;"),
+    ("adjoint_eps_derivative", "g_eps[cell] += etot[cc][x] * cb * rhs * (-ie * ie);",
+     "g_eps[cell] += etot[cc][x] * cb * rhs * (-ie);"),
+    ("adjoint_initial_populations", "r[0] = r0; r[3] = dwp * r0 / d32;", "r[0] = r0; r[3] = dwp * r0 / d21;"),
+    ("adjoint_noise_amplitude", "*g_na += c[ORC_C_CK] * s->p.E_sp * xi[cc] * pn;",
+     "*g_na += c[ORC_C_CK] * xi[cc] * pn;"),
+    ("adjoint_layer_scale", "vh[cc][x] = (1.0 / (1.0 + a)) * htot[cc][x];", "vh[cc][x] = htot[cc][x];"),
+    ("tangent_inversion_term", "c[ORC_C_CK] * dN * v[cc][x];", "c[ORC_C_CK] * dN * v[cc][x] * 0.5;"),
 ]
 
 
