@@ -146,7 +146,7 @@ const char* mbf_last_error(const mbf_handle* h);
  * Returns MBF_EINVAL for NULL or sizes < 2. */
 int mbf_config_default(mbf_config* cfg, int nx, int ny, int nz);
 
-/* Validate cfg (sizes >= 2, ny and nz <= 65535, every site array below 4 GiB,
+/* Validate cfg (sizes >= 2, ny and nz < 65535, every site array below 4 GiB,
  * Courant number, finite positive parameters) before any allocation, then
  * allocate E and H on the current device and zero them (the Bloch state is
  * allocated by mbf_set_material, one value per gain cell).  *out receives the
@@ -291,6 +291,24 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes /* [3] */);
 int mbf_state_size(const mbf_handle* h, size_t* out);
 int mbf_save_state(mbf_handle* h, void* buf, size_t n);
 int mbf_load_state(mbf_handle* h, const void* buf, size_t n);
+
+/* ---------------------------------------------------------------- adjoint
+ * Gradient of the loss-box objective (the loss-box monitor summed over the
+ * run) L = sum_{n=1..nsteps} sum_{interior E-sites in the box} (E^n)^2 with
+ * respect to eps_r of every cell and to the pump density N_a, by reverse-mode
+ * differentiation of the discrete step (rows a2-a4 transposed, curl- and
+ * curl+ exchanged).  The run starts right after mbf_set_pump (step 0;
+ * MBF_ESTATE otherwise) with the loss box set (MBF_ESTATE), PEC or absorbing
+ * walls (Mur walls: MBF_EINVAL).  The forward run keeps a device snapshot of
+ * the state every K steps; the reverse sweep recomputes each segment of K
+ * steps from its snapshot, storing E, P, N1 and N2 of every step, and then
+ * runs the K reverse steps, so device memory grows with nsteps/K + K.
+ * grad_eps receives nx*ny*nz doubles, x fastest (host or device memory per
+ * mem_kind, caller-owned), *grad_Na dL/dN_a in m^3, *loss L.  The handle is
+ * left at step nsteps, as after mbf_step(nsteps).  The gradient is the same,
+ * bit for bit, for every K. */
+int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_kind, double* grad_Na,
+                    double* loss);
 
 /* ---------------------------------------------------------------- batches
  * Many realizations advanced together (Simulations section: the emission is

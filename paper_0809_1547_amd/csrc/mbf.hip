@@ -19,6 +19,7 @@
 
 #include "../../include/mbf.h"
 #include "mbf_kernels.hpp"
+#include "mbf_adjoint.hpp"
 
 namespace {
 
@@ -84,6 +85,7 @@ struct mbf_handle {
     bool has_layer = false;
     int64_t gain_sites = 0;   // interior E-sites of gain cells
     bool have_material = false, have_pump = false;
+    int init_kind = MBF_INIT_GROUND;
     int64_t step = 0;
     uint64_t version = 0;     // bumped whenever the device view of the handle changes
     // graph of a chunk of steps
@@ -564,7 +566,7 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
     *out = nullptr;
     const mbf_config& c = *cfg;
     if (c.nx < 2 || c.ny < 2 || c.nz < 2) return fail(nullptr, MBF_EINVAL, "grid sizes must be >= 2");
-    if (c.ny > 65535 || c.nz > 65535) return fail(nullptr, MBF_EINVAL, "ny and nz must be <= 65535");
+    if (c.ny >= 65535 || c.nz >= 65535) return fail(nullptr, MBF_EINVAL, "ny and nz must be < 65535");
     const double ext = (double)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
     if (ext * (c.precision == MBF_FP64 ? 8.0 : 4.0) >= 4294967296.0)
         return fail(nullptr, MBF_EINVAL, "grid too large (one site array must stay below 4 GiB)");
@@ -828,6 +830,7 @@ int mbf_set_pump(mbf_handle* h, double Na, int init) {
     const mbf_config& c = h->cfg;
     h->co = c.precision == MBF_FP64 ? make_coef<double>(c, Na) : make_coef<float>(c, Na);
     h->Na_si = Na;
+    h->init_kind = init;
     double N1 = 0, N2 = 0, N3 = 0;
     if (init == MBF_INIT_PREPUMPED) {
         const double d32 = h->co.rates[0], d21 = h->co.rates[1], d10 = h->co.rates[2], dwp = h->co.rates[3];
@@ -1825,3 +1828,219 @@ int mbf_batch_step_bytes(const mbf_batch* b, double* bytes) {
 }
 
 }  // extern "C"
+
+// ================================================================ adjoint
+namespace {
+
+// Device buffers of one adjoint run, freed on scope exit.
+struct AdjBuffers {
+    std::vector<Snap> ckpt;
+    Snap end;
+    void* traj = nullptr;       // K+1 slots of (E dense x3, P compact x3, N1 x3, N2 x3) + one P slot
+    void* adj = nullptr;        // et x3, hb x3 (dense), lp x3, lq x3, ln x9 (compact)
+    double* g_eps = nullptr;
+    double* g_na = nullptr;
+    double* g_pop = nullptr;
+    ~AdjBuffers() {
+        for (Snap& q : ckpt) snap_free(q);
+        snap_free(end);
+        if (traj) hipFree(traj);
+        if (adj) hipFree(adj);
+        if (g_eps) hipFree(g_eps);
+        if (g_na) hipFree(g_na);
+        if (g_pop) hipFree(g_pop);
+    }
+};
+
+// The soft-source value added during step n, as the forward computes it.
+double host_source_value(const mbf_handle* h, int64_t n) {
+    if (!h->src_on) return 0.0;
+    const double t = (double)(n + 1) * h->co.dt - h->src_t0;
+    const double q = t / h->src_tp;
+    return h->src_amp * std::sin(h->src_ws * t) * std::exp(-q * q);
+}
+
+template <typename T>
+int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_kind, double* grad_Na,
+                double* loss) {
+    const mbf_config& c = h->cfg;
+    const size_t esz = sizeof(T);
+    const size_t E3 = (size_t)h->nsite * 3, C3 = (size_t)h->glen * 3;
+    const size_t slot = (E3 + 3 * C3) * esz;          // E, P, N1, N2
+    const int64_t nseg = (nsteps + K - 1) / K;
+    const size_t ncell = (size_t)c.nx * c.ny * c.nz;
+    AdjBuffers B;
+    B.ckpt.resize((size_t)nseg);
+    int rc = MBF_OK;
+    for (auto& q : B.ckpt)
+        if (!rc) rc = snap_alloc(h, q);
+    if (!rc) rc = snap_alloc(h, B.end);
+    if (rc) return rc;
+    mbf::Geom gm{};
+    gm.tiles_x = h->nbx;
+    gm.tiles_y = (c.ny + 3) / 4;
+    gm.zseg = std::min(4, c.nz);
+    gm.segs = (c.nz + gm.zseg - 1) / gm.zseg;
+    gm.nblk = gm.tiles_x * gm.tiles_y * gm.segs;
+    gm.xcd_remap = 1;
+    const size_t npop = (size_t)h->nbx * c.ny * c.nz;
+    if (hipMalloc(&B.traj, slot * (size_t)(K + 1) + C3 * esz) != hipSuccess ||
+        hipMalloc(&B.adj, (2 * E3 + 5 * C3) * esz) != hipSuccess ||
+        hipMalloc(&B.g_eps, ncell * sizeof(double)) != hipSuccess ||
+        hipMalloc(&B.g_na, (size_t)gm.nblk * sizeof(double)) != hipSuccess ||
+        hipMalloc(&B.g_pop, npop * sizeof(double)) != hipSuccess)
+        return fail(h, MBF_ENOMEM, "device allocation for the adjoint failed");
+    // ---- forward, with a checkpoint at the start of every segment
+    for (int64_t sg = 0; sg < nseg && !rc; ++sg) {
+        rc = snap_copy(h, B.ckpt[(size_t)sg], true);
+        if (!rc) rc = run_steps(h, std::min<int64_t>(K, nsteps - sg * K), nullptr);
+    }
+    if (!rc) rc = snap_copy(h, B.end, true);
+    if (rc) return rc;
+    mbf::Ctl ctl{};
+    HIPCHK(h, hipMemcpyAsync(&ctl, h->ctl, sizeof(ctl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *loss = ctl.loss;
+    if (ctl.nonfinite) return fail(h, MBF_ENONFINITE, "the forward run produced a non-finite energy");
+    // ---- reverse sweep
+    char* adj = (char*)B.adj;
+    HIPCHK(h, hipMemsetAsync(adj, 0, (2 * E3 + 5 * C3) * esz, h->stream));
+    HIPCHK(h, hipMemsetAsync(B.g_eps, 0, ncell * sizeof(double), h->stream));
+    HIPCHK(h, hipMemsetAsync(B.g_na, 0, (size_t)gm.nblk * sizeof(double), h->stream));
+    mbf::AdjView<T> v{};
+    for (int q = 0; q < 3; ++q) {
+        v.et[q] = (T*)(adj + ((size_t)q * h->nsite) * esz);
+        v.hb[q] = (T*)(adj + (E3 + (size_t)q * h->nsite) * esz);
+        v.lp[q] = (T*)(adj + (2 * E3 + (size_t)q * h->glen) * esz);
+        v.lq[q] = (T*)(adj + (2 * E3 + C3 + (size_t)q * h->glen) * esz);
+        for (int p = 0; p < 3; ++p) v.ln[p][q] = (T*)(adj + (2 * E3 + (2 + p) * C3 + (size_t)q * h->glen) * esz);
+    }
+    v.g_eps = B.g_eps;
+    v.g_na = B.g_na;
+    v.mat = h->mat;
+    v.seg_base = h->seg_base;
+    v.nbx = h->nbx;
+    v.lut_inv_eps = reinterpret_cast<const T*>(h->lut);
+    v.nx = c.nx; v.ny = c.ny; v.nz = c.nz;
+    v.sx = h->sx; v.sxy = h->sxy;
+    for (int a = 0; a < 3; ++a)
+        for (int hf = 0; hf < 2; ++hf)
+            v.prof[a][hf] = reinterpret_cast<const T*>(h->prof) + (2 * a + hf) * h->prof_stride;
+    v.has_layer = h->has_layer ? 1 : 0;
+    const Coef& k = h->co;
+    v.S = (T)k.S; v.a = (T)k.a; v.b = (T)k.b; v.ck = (T)k.ck; v.beta = (T)k.beta;
+    v.dt32 = (T)k.dt32; v.dt21 = (T)k.dt21; v.dt10 = (T)k.dt10; v.dtWp = (T)k.dtWp;
+    v.noise = c.noise && k.cF != 0.0;
+    v.ck_esp = v.noise ? (T)(k.ck * c.E_sp) : (T)0;
+    v.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFull);
+    v.seed_hi = (uint32_t)(c.seed >> 32);
+    v.realization = c.realization;
+    v.src_on = h->src_on; v.src_comp = h->src_comp;
+    v.src_i = h->src_i; v.src_j = h->src_j; v.src_k = h->src_k;
+    for (int q = 0; q < 6; ++q) v.box[q] = h->box[q];
+    char* traj = (char*)B.traj;
+    auto sE = [&](int64_t q) { return (T*)(traj + (size_t)q * slot); };
+    auto sP = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + E3 * esz); };
+    auto sN1 = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + (E3 + C3) * esz); };
+    auto sN2 = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + (E3 + 2 * C3) * esz); };
+    T* sPm = (T*)(traj + slot * (size_t)(K + 1));
+    // copy the current forward state into trajectory slot q
+    auto store = [&](int64_t q) -> int {
+        void *e = nullptr, *p = nullptr;
+        int r = field_array(h, 0, h->step, false, &e);
+        if (!r) r = field_array(h, 6, h->step, false, &p);
+        if (r) return r;
+        HIPCHK(h, hipMemcpyAsync(sE(q), e, E3 * esz, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(sP(q), p, C3 * esz, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(sN1(q), h->arr[18], 2 * C3 * esz, hipMemcpyDeviceToDevice, h->stream));
+        return MBF_OK;
+    };
+    const dim3 gblk((unsigned)gm.nblk), tb(64, 4);
+    for (int64_t sg = nseg - 1; sg >= 0 && !rc; --sg) {
+        rc = snap_copy(h, B.ckpt[(size_t)sg], false);
+        const int64_t n0 = sg * K, kp = std::min<int64_t>(K, nsteps - n0);
+        void* pm = nullptr;
+        if (!rc) rc = field_array(h, 9, h->step, false, &pm);
+        if (!rc && hipMemcpyAsync(sPm, pm, C3 * esz, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+            rc = fail(h, MBF_EHIP, "trajectory copy failed");
+        if (!rc) rc = store(0);
+        for (int64_t q = 1; q <= kp && !rc; ++q) {
+            rc = run_steps(h, 1, nullptr);
+            if (!rc) rc = store(q);
+        }
+        if (rc) break;
+        if (sg == nseg - 1) {                          // etot = 2 E^N in the box
+            for (int q = 0; q < 3; ++q) v.E1[q] = sE(kp) + (size_t)q * h->nsite;
+            hipLaunchKernelGGL(mbf::k_adj_seed<T>, dim3((unsigned)((c.nx + 64) / 64), (unsigned)(c.ny + 1), (unsigned)(c.nz + 1)),
+                               dim3(64), 0, h->stream, v);
+        }
+        for (int64_t n = n0 + kp - 1; n >= n0; --n) {
+            const int64_t q = n - n0;
+            for (int cc = 0; cc < 3; ++cc) {
+                v.E0[cc] = sE(q) + (size_t)cc * h->nsite;
+                v.E1[cc] = sE(q + 1) + (size_t)cc * h->nsite;
+                v.P0[cc] = sP(q) + (size_t)cc * h->glen;
+                v.P1[cc] = sP(q + 1) + (size_t)cc * h->glen;
+                v.Pm[cc] = (q >= 1 ? sP(q - 1) : sPm) + (size_t)cc * h->glen;
+                v.N1[cc] = sN1(q) + (size_t)cc * h->glen;
+                v.N2[cc] = sN2(q) + (size_t)cc * h->glen;
+            }
+            v.n = n;
+            v.src = (T)host_source_value(h, n);
+            hipLaunchKernelGGL((mbf::k_adj_h<T, 4>), gblk, tb, 0, h->stream, v, gm);
+            hipLaunchKernelGGL((mbf::k_adj_e<T, 4>), gblk, tb, 0, h->stream, v, gm);
+        }
+        if (hipGetLastError() != hipSuccess) rc = fail(h, MBF_EHIP, "adjoint kernel launch failed");
+    }
+    if (rc) return rc;
+    // initial populations of the prepumped start
+    double r[3] = {0.0, 0.0, 0.0};
+    if (h->init_kind == MBF_INIT_PREPUMPED) {
+        const double d32 = k.rates[0], d21 = k.rates[1], d10 = k.rates[2], dwp = k.rates[3];
+        const double r0 = 1.0 / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
+        r[0] = dwp * r0 / d10;
+        r[1] = dwp * r0 / d21;
+        r[2] = dwp * r0 / d32;
+    }
+    hipLaunchKernelGGL(mbf::k_adj_init_pop<T>, dim3((unsigned)h->nbx, (unsigned)c.ny, (unsigned)c.nz), dim3(64), 0,
+                       h->stream, v, r[0], r[1], r[2], B.g_pop);
+    HIPCHK(h, hipGetLastError());
+    std::vector<double> pa((size_t)gm.nblk), pb(npop);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(pa.data(), B.g_na, pa.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(pb.data(), B.g_pop, pb.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double gna = 0.0;
+    for (double x : pa) gna += x;
+    for (double x : pb) gna += x;
+    *grad_Na = gna / c.N_ref;
+    if (mem_kind == MBF_MEM_HOST)
+        HIPCHK(h, hipMemcpy(grad_eps, B.g_eps, ncell * sizeof(double), hipMemcpyDeviceToHost));
+    else
+        HIPCHK(h, hipMemcpyAsync(grad_eps, B.g_eps, ncell * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    // leave the handle at the end of the forward run
+    rc = snap_copy(h, B.end, false);
+    if (!rc) HIPCHK(h, hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_kind, double* grad_Na,
+                    double* loss) {
+    if (!h || !grad_eps || !grad_Na || !loss) return fail(h, MBF_EINVAL, "null argument");
+    if (nsteps < 1 || K < 1) return fail(h, MBF_EINVAL, "need nsteps >= 1 and K >= 1");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(h, MBF_EINVAL, "bad mem_kind");
+    for (int a = 0; a < 3; ++a)
+        if (h->cfg.boundary[a] == MBF_MUR1) return fail(h, MBF_EINVAL, "the adjoint supports PEC and absorbing walls only");
+    if (!h->have_material || !h->have_pump || h->step != 0)
+        return fail(h, MBF_ESTATE, "the adjoint run starts right after mbf_set_pump");
+    if (!h->box_on) return fail(h, MBF_ESTATE, "set the loss box first");
+    if (h->step + nsteps >= (int64_t)1 << 32) return fail(h, MBF_EINVAL, "step index would exceed 2^32");
+    return h->cfg.precision == MBF_FP64 ? adjoint_run<double>(h, nsteps, K, grad_eps, mem_kind, grad_Na, loss)
+                                        : adjoint_run<float>(h, nsteps, K, grad_eps, mem_kind, grad_Na, loss);
+}
+
+}  // extern "C"
+

@@ -1,0 +1,245 @@
+// Device code of the adjoint (reverse) step of the Maxwell-Bloch FDTD step.
+//
+// Objective: L = sum over steps n = 1..N of sum over the interior E-sites of
+// the loss box of (E^n)^2.  The forward step X^{n+1} = F(X^n; eps, N_a) is
+// linearised at the stored trajectory and its transpose is applied backwards.
+// Writing etot for the total adjoint of E^{n+1} (its later uses plus the
+// work term W of step n), the reverse step is
+//   H-sites:  htot = da * htot_prev + S curl+(u),  u = cb ie etot on interior
+//             E-sites (the transpose of curl- is curl+)
+//   E-sites:  lambda_E^n = ca etot - S curl-(db htot) + Bloch terms + 2 E^n
+//             in the box (the transpose of curl+ is curl-),
+// with the transposed Lorentz-oscillator and rate-equation Jacobians at the
+// gain sites, and the parameter terms
+//   dL/d eps(cell) += etot . (E^{n+1} - ca E^n - src) . (-1/eps)  (E' depends
+//   on eps through ie = 1/eps), and dL/dN_a from the pump term of N3 and the
+//   noise amplitude c_F = ck N_a E_sp.
+// The populations carry N1..N3 (N0 = N_a - N1 - N2 - N3), as in the forward
+// kernels.  Wall sites are constant and never feed a parameter, so they are
+// skipped; H-sites outside [0,n)^3 are never used.
+#pragma once
+
+#include "mbf_kernels.hpp"
+
+namespace mbf {
+
+template <typename T>
+struct AdjView {
+    // forward trajectory around the step n being reversed
+    const T* E0[3];      // E^n (dense)
+    const T* E1[3];      // E^{n+1}
+    const T* Pm[3];      // P^{n-1} (compact)
+    const T* P0[3];      // P^n
+    const T* P1[3];      // P^{n+1}
+    const T* N1[3];      // N1^n (compact)
+    const T* N2[3];      // N2^n
+    // adjoint state, updated in place
+    T* et[3];            // in: total adjoint of E^{n+1}; out: total adjoint of E^n (for step n-1)
+    T* hb[3];            // htot of the previous reverse step on entry, of this one on exit
+    T* lp[3];            // adjoint of P^{n+1} in, of P^n out (compact)
+    T* lq[3];            // adjoint of the P^n copy (P_prev slot of step n+1) in, of P^{n-1} out
+    T* ln[3][3];         // adjoint of N1..N3 at n+1 in, at n out
+    double* g_eps;       // dL/d eps per cell, x fastest (nx*ny*nz)
+    double* g_na;        // per work item partial sums of dL/d(N_a/N_ref)
+    // material and geometry
+    const uint8_t* mat;
+    const uint32_t* seg_base;
+    int nbx;
+    const T* lut_inv_eps;
+    int nx, ny, nz;
+    int64_t sx, sxy;
+    const T* prof[3][2];
+    int has_layer;
+    // coefficients of the forward step
+    T S, a, b, ck, beta, dt32, dt21, dt10, dtWp;
+    T ck_esp;            // d c_F / d(N_a/N_ref) = ck E_sp (0 without noise)
+    int noise;
+    uint32_t seed_lo, seed_hi, realization;
+    int64_t n;           // index of the step being reversed
+    T src;               // soft-source value of step n (at its site)
+    int src_on, src_comp, src_i, src_j, src_k;
+    int box[6];
+};
+
+template <typename T>
+__device__ __forceinline__ T adj_loss_e(const AdjView<T>& v, int c, int i, int j, int k) {
+    return (gld(v.prof[0][c == 0] + i) + gld(v.prof[1][c == 1] + j)) + gld(v.prof[2][c == 2] + k);
+}
+template <typename T>
+__device__ __forceinline__ T adj_loss_h(const AdjView<T>& v, int c, int i, int j, int k) {
+    return (gld(v.prof[0][c != 0] + i) + gld(v.prof[1][c != 1] + j)) + gld(v.prof[2][c != 2] + k);
+}
+
+// Interior E-site test (updated by Ampere's law).
+template <typename T>
+__device__ __forceinline__ bool e_in(const AdjView<T>& v, int c, int i, int j, int k) {
+    const bool ox = c == 0 ? (i >= 0 && i < v.nx) : (i >= 1 && i < v.nx);
+    const bool oy = c == 1 ? (j >= 0 && j < v.ny) : (j >= 1 && j < v.ny);
+    const bool oz = c == 2 ? (k >= 0 && k < v.nz) : (k >= 1 && k < v.nz);
+    return ox && oy && oz;
+}
+
+// u = cb ie etot at E-site (c; i,j,k), zero off the interior.
+template <typename T>
+__device__ __forceinline__ T adj_u(const AdjView<T>& v, int c, int i, int j, int k) {
+    if (!e_in(v, c, i, j, k)) return (T)0;
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+    const T ie = gld(v.lut_inv_eps + ldo(v.mat, x));
+    T cb = (T)1;
+    if (v.has_layer) cb = recip((T)1 + adj_loss_e(v, c, i, j, k));
+    return cb * ie * ldo(v.et[c], x);
+}
+
+// H part: htot = da htot_prev + S curl+(u) on the H-sites of [0,n)^3.
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_adj_h(AdjView<T> v, Geom gm) {
+    int bx, by, bz;
+    decode_item(gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap), bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * TY + threadIdx.y;
+    if (i >= v.nx || j >= v.ny) return;
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    for (int k = kz0; k < kz1; ++k) {
+        const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+        const T cx = (adj_u(v, 2, i, j + 1, k) - adj_u(v, 2, i, j, k)) - (adj_u(v, 1, i, j, k + 1) - adj_u(v, 1, i, j, k));
+        const T cy = (adj_u(v, 0, i, j, k + 1) - adj_u(v, 0, i, j, k)) - (adj_u(v, 2, i + 1, j, k) - adj_u(v, 2, i, j, k));
+        const T cz = (adj_u(v, 1, i + 1, j, k) - adj_u(v, 1, i, j, k)) - (adj_u(v, 0, i, j + 1, k) - adj_u(v, 0, i, j, k));
+        const T cc[3] = {cx, cy, cz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T da = (T)1;
+            if (v.has_layer) {
+                const T a = adj_loss_h(v, c, i, j, k);
+                da = ((T)1 - a) * recip((T)1 + a);
+            }
+            sto(v.hb[c], x, da * ldo(v.hb[c], x) + v.S * cc[c]);
+        }
+    }
+}
+
+// vh = db htot at H-site (c; i,j,k) of [0,n)^3.
+template <typename T>
+__device__ __forceinline__ T adj_vh(const AdjView<T>& v, int c, int i, int j, int k) {
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+    T db = (T)1;
+    if (v.has_layer) db = recip((T)1 + adj_loss_h(v, c, i, j, k));
+    return db * ldo(v.hb[c], x);
+}
+
+// E part with the Bloch terms, the parameter terms and the loss term.
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
+    __shared__ double sh[TY];
+    const int w = xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap);
+    int bx, by, bz;
+    decode_item(gm, w, bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * TY + threadIdx.y;
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    double gna = 0.0;
+    if (j < v.ny) {
+        const bool act = i < v.nx;
+        for (int k = kz0; k < kz1; ++k) {
+            const uint32_t x = (uint32_t)(act ? i : 0) + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+            const uint8_t m = ldo(v.mat, x);
+            const bool g = act && m >= kGainId;
+            const uint32_t gi = gain_index(v, bx, j, k, g, true);
+            if (!act) continue;
+            const T ie = gld(v.lut_inv_eps + m);
+            double geps = 0.0;
+            T xi[3] = {(T)0, (T)0, (T)0};
+            if (g && v.noise) noise3(v, (uint32_t)(i + v.nx * (j + v.ny * k)), (uint32_t)v.n, xi);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!e_in(v, c, i, j, k)) continue;
+                T curl;
+                if (c == 0)
+                    curl = (adj_vh(v, 2, i, j, k) - adj_vh(v, 2, i, j - 1, k)) - (adj_vh(v, 1, i, j, k) - adj_vh(v, 1, i, j, k - 1));
+                else if (c == 1)
+                    curl = (adj_vh(v, 0, i, j, k) - adj_vh(v, 0, i, j, k - 1)) - (adj_vh(v, 2, i, j, k) - adj_vh(v, 2, i - 1, j, k));
+                else
+                    curl = (adj_vh(v, 1, i, j, k) - adj_vh(v, 1, i - 1, j, k)) - (adj_vh(v, 0, i, j, k) - adj_vh(v, 0, i, j - 1, k));
+                T ca = (T)1, cb = (T)1;
+                if (v.has_layer) {
+                    const T a = adj_loss_e(v, c, i, j, k);
+                    cb = recip((T)1 + a);
+                    ca = ((T)1 - a) * cb;
+                }
+                const T et = ldo(v.et[c], x);
+                const T E = ldo(v.E0[c], x), En = ldo(v.E1[c], x);
+                T lam = ca * et - v.S * curl;
+                T Wh_prev = (T)0, dP_prev = (T)0;
+                if (g) {
+                    const T P0 = ldo(v.P0[c], gi), P1 = ldo(v.P1[c], gi);
+                    const T dPf = P1 - P0;
+                    const T dN = ldo(v.N1[c], gi) - ldo(v.N2[c], gi);
+                    const T n1 = ldo(v.ln[0][c], gi), n2 = ldo(v.ln[1][c], gi), n3 = ldo(v.ln[2][c], gi);
+                    const T Wh = n2 - n1;
+                    const T dPh = Wh * v.beta * (T)0.5 * (En + E) - cb * ie * et;
+                    const T pn = ldo(v.lp[c], gi) + dPh;
+                    lam += v.ck * dN * pn + Wh * v.beta * (T)0.5 * dPf;
+                    sto(v.lp[c], gi, ldo(v.lq[c], gi) + v.a * pn - dPh);
+                    sto(v.lq[c], gi, v.b * pn);
+                    const T m1 = n1 * ((T)1 - v.dt10) - n3 * v.dtWp + v.ck * E * pn;
+                    const T m2 = n2 * ((T)1 - v.dt21) + n1 * v.dt21 - n3 * v.dtWp - v.ck * E * pn;
+                    const T m3 = n3 * ((T)1 - v.dt32 - v.dtWp) + n2 * v.dt32;
+                    sto(v.ln[0][c], gi, m1);
+                    sto(v.ln[1][c], gi, m2);
+                    sto(v.ln[2][c], gi, m3);
+                    gna += (double)(n3 * v.dtWp) + (double)(v.ck_esp * xi[c] * pn);
+                    Wh_prev = m2 - m1;
+                    dP_prev = P0 - ldo(v.Pm[c], gi);
+                }
+                // E^{n+1} = ca E^n + cb ie (S curl- H' - dP) + src: its eps derivative
+                const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? v.src : (T)0;
+                geps += (double)et * (double)((En - ca * E) - s) * (double)(-ie);
+                // loss term of E^n and the work term of step n-1
+                if (v.n >= 1) {
+                    if (i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5])
+                        lam += (T)2 * E;
+                    lam += Wh_prev * v.beta * (T)0.5 * dP_prev;
+                }
+                sto(v.et[c], x, lam);
+            }
+            const uint32_t cell = (uint32_t)i + (uint32_t)v.nx * ((uint32_t)j + (uint32_t)v.ny * (uint32_t)k);
+            sto(v.g_eps, cell, gld(v.g_eps + cell) + geps);
+        }
+    }
+    const double s = block_sum(gna, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0) sto(v.g_na, (uint32_t)w, gld(v.g_na + w) + s);
+}
+
+// Start of the reverse sweep: etot = 2 E^N on the interior sites of the box
+// (and zero elsewhere); the other adjoint arrays start at zero.
+template <typename T>
+__global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    if (i > v.nx) return;
+    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+    const bool inb = i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sto(v.et[c], x, (inb && e_in(v, c, i, j, k)) ? (T)2 * ldo(v.E1[c], x) : (T)0);
+}
+
+// dL/d(N_a/N_ref) through the initial populations N_i^0 = r_i N_a/N_ref of
+// the prepumped start: per-work-item partials of sum r_i lambda_Ni^0.
+template <typename T>
+__global__ void __launch_bounds__(64) k_adj_init_pop(AdjView<T> v, double r1, double r2, double r3, double* part) {
+    __shared__ double sh[1];
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const bool act = i < v.nx;
+    const uint32_t x = (uint32_t)(act ? i : 0) + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
+    const bool g = act && ldo(v.mat, x) >= kGainId;
+    const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+    double acc = 0.0;
+    if (g) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (e_in(v, c, i, j, k))
+                acc += r1 * (double)ldo(v.ln[0][c], gi) + r2 * (double)ldo(v.ln[1][c], gi) + r3 * (double)ldo(v.ln[2][c], gi);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
+}
+
+}  // namespace mbf

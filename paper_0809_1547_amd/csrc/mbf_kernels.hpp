@@ -145,9 +145,8 @@ __device__ __forceinline__ void box_muller3(uint32_t w0, uint32_t w1, uint32_t w
     xi[2] = r1 * c3;
 }
 
-template <typename T>
-__device__ __forceinline__ void noise3(const SimView<T>& v, uint32_t cell, uint32_t step,
-                                       T xi[3]) {
+template <typename V, typename T>
+__device__ __forceinline__ void noise3(const V& v, uint32_t cell, uint32_t step, T xi[3]) {
     uint32_t x0 = cell, x1 = step, x2 = v.realization, x3 = 0u;
     philox4x32_10(x0, x1, x2, x3, v.seed_lo, v.seed_hi);
     box_muller3(x0, x1, x2, x3, xi);
@@ -249,9 +248,8 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // be called by the whole wave that covers x segment bx of row (j, k) (lanes
 // outside the grid inactive or with g = false); j and k are wave-uniform and
 // row_ok is false for a wave past the last row (its result is then unused).
-template <typename T>
-__device__ __forceinline__ uint32_t gain_index(const SimView<T>& v, int bx, int j, int k, bool g,
-                                               bool row_ok) {
+template <typename V>
+__device__ __forceinline__ uint32_t gain_index(const V& v, int bx, int j, int k, bool g, bool row_ok) {
     const uint64_t mask = __ballot(g);
     const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

@@ -120,6 +120,7 @@ def _load():
         "mbf_batch_step_timed": (I, [P, I64, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "mbf_batch_step_bytes": (I, [P, C.POINTER(C.c_double)]),
         "mbf_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
+        "mbf_adjoint_run": (I, [P, I64, I, VP, I, dp, dp]),
         "mbf_batch_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
     }
     for name, (res, args) in sigs.items():
@@ -140,7 +141,7 @@ EXPORTED = [
     "mbf_batch_create", "mbf_batch_destroy", "mbf_batch_last_error", "mbf_batch_size",
     "mbf_batch_member", "mbf_batch_set_tuning", "mbf_batch_get_tuning", "mbf_batch_step",
     "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes", "mbf_autotune",
-    "mbf_batch_autotune",
+    "mbf_batch_autotune", "mbf_adjoint_run",
 ]
 
 
@@ -338,6 +339,18 @@ def mbf_batch_autotune(b: int, budget_ms: int = 2000) -> dict:
     return _tuning_dict(t)
 
 
+def mbf_adjoint_run(h: int, nsteps: int, K: int, grad_eps) -> Tuple[float, float]:
+    """Run the loss-box adjoint over nsteps from the pump; grad_eps (caller
+    owned: a float64 numpy array or device tensor of nx*ny*nz values) receives
+    dL/d eps_r.  Returns (L, dL/dN_a)."""
+    if isinstance(grad_eps, np.ndarray):
+        assert grad_eps.dtype == np.float64 and grad_eps.flags.c_contiguous
+    p, kind, _keep = _ptr_kind(grad_eps)
+    gna, L = C.c_double(), C.c_double()
+    _check(lib.mbf_adjoint_run(h, int(nsteps), int(K), p, kind, C.byref(gna), C.byref(L)), h)
+    return L.value, gna.value
+
+
 def mbf_batch_create(cfgs: Sequence[mbf_config], stream: Optional[int] = None) -> int:
     arr = (mbf_config * len(cfgs))(*cfgs)
     b = C.c_void_p()
@@ -501,6 +514,13 @@ class Sim:
 
     def autotune(self, budget_ms=2000):
         return mbf_autotune(self.h, budget_ms)
+
+    def adjoint_run(self, nsteps, K=50):
+        """(L, dL/d eps_r (nz, ny, nx), dL/dN_a) of the loss-box objective over
+        nsteps from the pump; leaves the run at step nsteps."""
+        g = np.zeros((self.cfg.nz, self.cfg.ny, self.cfg.nx), dtype=np.float64)
+        L, gna = mbf_adjoint_run(self.h, nsteps, K, g)
+        return L, g, gna
 
     def step_timed(self, n):
         return mbf_step_timed(self.h, n)
