@@ -88,6 +88,9 @@ struct mbf_handle {
     int init_kind = MBF_INIT_GROUND;
     int64_t step = 0;
     uint64_t version = 0;     // bumped whenever the device view of the handle changes
+    void* tap = nullptr;      // trajectory recording buffer of the adjoint (nullptr: off)
+    int64_t tap_stride = 0;   // values per trajectory slot
+    int64_t tap_base = 0;     // host copy of ctl->tap_base
     // graph of a chunk of steps
     hipGraphExec_t gexec = nullptr;
     int64_t gsteps = 0;
@@ -175,6 +178,10 @@ mbf::SimView<T> view(mbf_handle* h) {
     const T* lut = reinterpret_cast<const T*>(h->lut);
     v.seg_base = h->seg_base;
     v.nbx = h->nbx;
+    v.tap = reinterpret_cast<T*>(h->tap);
+    v.tap_stride = h->tap_stride;
+    v.tap_e = h->nsite;
+    v.tap_c = h->glen;
     v.mat = h->mat;
     v.lut_inv_eps = lut;
     v.lut_eps = lut + mbf::kMaxMat;
@@ -1860,13 +1867,32 @@ double host_source_value(const mbf_handle* h, int64_t n) {
     return h->src_amp * std::sin(h->src_ws * t) * std::exp(-q * q);
 }
 
+// Turn trajectory recording on (buffer) or off (nullptr); slot 0 is the state
+// at step `base`.
+template <typename T>
+int set_tap(mbf_handle* h, void* buffer, int64_t base) {
+    if (buffer != h->tap) {
+        h->tap = buffer;
+        h->tap_stride = (int64_t)h->nsite * 3 + (int64_t)h->glen * 6;
+        drop_graph(h);
+    }
+    if (!buffer) return MBF_OK;
+    h->tap_base = base;
+    HIPCHK(h, hipMemcpyAsync(&h->ctl->tap_base, &h->tap_base, sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+    // slot of the current state
+    hipLaunchKernelGGL(mbf::k_tap_state<T>, dim3((unsigned)h->nbx, (unsigned)h->cfg.ny, (unsigned)h->cfg.nz),
+                       dim3(64), 0, h->stream, view<T>(h));
+    HIPCHK(h, hipGetLastError());
+    return MBF_OK;
+}
+
 template <typename T>
 int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_kind, double* grad_Na,
                 double* loss) {
     const mbf_config& c = h->cfg;
     const size_t esz = sizeof(T);
     const size_t E3 = (size_t)h->nsite * 3, C3 = (size_t)h->glen * 3;
-    const size_t slot = (E3 + 3 * C3) * esz;          // E, P, N1, N2
+    const size_t slot = (E3 + 2 * C3) * esz;          // E, P^{m} - P^{m-1}, N1 - N2
     const int64_t nseg = (nsteps + K - 1) / K;
     const size_t ncell = (size_t)c.nx * c.ny * c.nz;
     AdjBuffers B;
@@ -1884,15 +1910,21 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     gm.nblk = gm.tiles_x * gm.tiles_y * gm.segs;
     gm.xcd_remap = 1;
     const size_t npop = (size_t)h->nbx * c.ny * c.nz;
-    if (hipMalloc(&B.traj, slot * (size_t)(K + 1) + C3 * esz) != hipSuccess ||
+    if (hipMalloc(&B.traj, slot * (size_t)(K + 1)) != hipSuccess ||
         hipMalloc(&B.adj, (2 * E3 + 5 * C3) * esz) != hipSuccess ||
         hipMalloc(&B.g_eps, ncell * sizeof(double)) != hipSuccess ||
         hipMalloc(&B.g_na, (size_t)gm.nblk * sizeof(double)) != hipSuccess ||
         hipMalloc(&B.g_pop, npop * sizeof(double)) != hipSuccess)
         return fail(h, MBF_ENOMEM, "device allocation for the adjoint failed");
-    // ---- forward, with a checkpoint at the start of every segment
+    struct TapOff {                                   // recording ends with the run
+        mbf_handle* h;
+        ~TapOff() { if (h->tap) { h->tap = nullptr; drop_graph(h); } }
+    } tap_off{h};
+    // ---- forward, with a checkpoint at the start of every segment; the last
+    // segment is recorded on the way
     for (int64_t sg = 0; sg < nseg && !rc; ++sg) {
         rc = snap_copy(h, B.ckpt[(size_t)sg], true);
+        if (!rc && sg == nseg - 1) rc = set_tap<T>(h, B.traj, sg * K);
         if (!rc) rc = run_steps(h, std::min<int64_t>(K, nsteps - sg * K), nullptr);
     }
     if (!rc) rc = snap_copy(h, B.end, true);
@@ -1909,7 +1941,7 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     HIPCHK(h, hipMemsetAsync(B.g_na, 0, (size_t)gm.nblk * sizeof(double), h->stream));
     mbf::AdjView<T> v{};
     for (int q = 0; q < 3; ++q) {
-        v.et[q] = (T*)(adj + ((size_t)q * h->nsite) * esz);
+        v.u[q] = (T*)(adj + ((size_t)q * h->nsite) * esz);
         v.hb[q] = (T*)(adj + (E3 + (size_t)q * h->nsite) * esz);
         v.lp[q] = (T*)(adj + (2 * E3 + (size_t)q * h->glen) * esz);
         v.lq[q] = (T*)(adj + (2 * E3 + C3 + (size_t)q * h->glen) * esz);
@@ -1939,51 +1971,30 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     v.src_i = h->src_i; v.src_j = h->src_j; v.src_k = h->src_k;
     for (int q = 0; q < 6; ++q) v.box[q] = h->box[q];
     char* traj = (char*)B.traj;
-    auto sE = [&](int64_t q) { return (T*)(traj + (size_t)q * slot); };
-    auto sP = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + E3 * esz); };
-    auto sN1 = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + (E3 + C3) * esz); };
-    auto sN2 = [&](int64_t q) { return (T*)(traj + (size_t)q * slot + (E3 + 2 * C3) * esz); };
-    T* sPm = (T*)(traj + slot * (size_t)(K + 1));
-    // copy the current forward state into trajectory slot q
-    auto store = [&](int64_t q) -> int {
-        void *e = nullptr, *p = nullptr;
-        int r = field_array(h, 0, h->step, false, &e);
-        if (!r) r = field_array(h, 6, h->step, false, &p);
-        if (r) return r;
-        HIPCHK(h, hipMemcpyAsync(sE(q), e, E3 * esz, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(sP(q), p, C3 * esz, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(sN1(q), h->arr[18], 2 * C3 * esz, hipMemcpyDeviceToDevice, h->stream));
-        return MBF_OK;
-    };
+    auto sE = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot) + (size_t)cc * h->nsite; };
+    auto sdP = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot + E3 * esz) + (size_t)cc * h->glen; };
+    auto sdN = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot + (E3 + C3) * esz) + (size_t)cc * h->glen; };
     const dim3 gblk((unsigned)gm.nblk), tb(64, 4);
     for (int64_t sg = nseg - 1; sg >= 0 && !rc; --sg) {
-        rc = snap_copy(h, B.ckpt[(size_t)sg], false);
         const int64_t n0 = sg * K, kp = std::min<int64_t>(K, nsteps - n0);
-        void* pm = nullptr;
-        if (!rc) rc = field_array(h, 9, h->step, false, &pm);
-        if (!rc && hipMemcpyAsync(sPm, pm, C3 * esz, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
-            rc = fail(h, MBF_EHIP, "trajectory copy failed");
-        if (!rc) rc = store(0);
-        for (int64_t q = 1; q <= kp && !rc; ++q) {
-            rc = run_steps(h, 1, nullptr);
-            if (!rc) rc = store(q);
-        }
-        if (rc) break;
-        if (sg == nseg - 1) {                          // etot = 2 E^N in the box
-            for (int q = 0; q < 3; ++q) v.E1[q] = sE(kp) + (size_t)q * h->nsite;
+        if (sg != nseg - 1) {                          // recompute and record the segment
+            rc = snap_copy(h, B.ckpt[(size_t)sg], false);
+            if (!rc) rc = set_tap<T>(h, B.traj, n0);
+            if (!rc) rc = run_steps(h, kp, nullptr);
+            if (rc) break;
+        } else {                                       // etot = 2 E^N in the box
+            for (int q = 0; q < 3; ++q) v.E1[q] = sE(kp, q);
             hipLaunchKernelGGL(mbf::k_adj_seed<T>, dim3((unsigned)((c.nx + 64) / 64), (unsigned)(c.ny + 1), (unsigned)(c.nz + 1)),
                                dim3(64), 0, h->stream, v);
         }
         for (int64_t n = n0 + kp - 1; n >= n0; --n) {
             const int64_t q = n - n0;
             for (int cc = 0; cc < 3; ++cc) {
-                v.E0[cc] = sE(q) + (size_t)cc * h->nsite;
-                v.E1[cc] = sE(q + 1) + (size_t)cc * h->nsite;
-                v.P0[cc] = sP(q) + (size_t)cc * h->glen;
-                v.P1[cc] = sP(q + 1) + (size_t)cc * h->glen;
-                v.Pm[cc] = (q >= 1 ? sP(q - 1) : sPm) + (size_t)cc * h->glen;
-                v.N1[cc] = sN1(q) + (size_t)cc * h->glen;
-                v.N2[cc] = sN2(q) + (size_t)cc * h->glen;
+                v.E0[cc] = sE(q, cc);
+                v.E1[cc] = sE(q + 1, cc);
+                v.dP0[cc] = sdP(q, cc);
+                v.dP1[cc] = sdP(q + 1, cc);
+                v.dN[cc] = sdN(q, cc);
             }
             v.n = n;
             v.src = (T)host_source_value(h, n);

@@ -6,9 +6,11 @@
 // Writing etot for the total adjoint of E^{n+1} (its later uses plus the
 // work term W of step n), the reverse step is
 //   H-sites:  htot = da * htot_prev + S curl+(u),  u = cb ie etot on interior
-//             E-sites (the transpose of curl- is curl+)
+//             E-sites, zero elsewhere (the transpose of curl- is curl+)
 //   E-sites:  lambda_E^n = ca etot - S curl-(db htot) + Bloch terms + 2 E^n
 //             in the box (the transpose of curl+ is curl-),
+// and the E part stores u rather than etot, so that the H part reads plain
+// values like the forward a1.
 // with the transposed Lorentz-oscillator and rate-equation Jacobians at the
 // gain sites, and the parameter terms
 //   dL/d eps(cell) += etot . (E^{n+1} - ca E^n - src) . (-1/eps)  (E' depends
@@ -28,13 +30,11 @@ struct AdjView {
     // forward trajectory around the step n being reversed
     const T* E0[3];      // E^n (dense)
     const T* E1[3];      // E^{n+1}
-    const T* Pm[3];      // P^{n-1} (compact)
-    const T* P0[3];      // P^n
-    const T* P1[3];      // P^{n+1}
-    const T* N1[3];      // N1^n (compact)
-    const T* N2[3];      // N2^n
+    const T* dP0[3];     // P^n - P^{n-1} (compact)
+    const T* dP1[3];     // P^{n+1} - P^n
+    const T* dN[3];      // N1^n - N2^n
     // adjoint state, updated in place
-    T* et[3];            // in: total adjoint of E^{n+1}; out: total adjoint of E^n (for step n-1)
+    T* u[3];             // in: cb ie etot of E^{n+1}; out: of E^n (for step n-1); zero off the interior
     T* hb[3];            // htot of the previous reverse step on entry, of this one on exit
     T* lp[3];            // adjoint of P^{n+1} in, of P^n out (compact)
     T* lq[3];            // adjoint of the P^n copy (P_prev slot of step n+1) in, of P^{n-1} out
@@ -79,16 +79,6 @@ __device__ __forceinline__ bool e_in(const AdjView<T>& v, int c, int i, int j, i
     return ox && oy && oz;
 }
 
-// u = cb ie etot at E-site (c; i,j,k), zero off the interior.
-template <typename T>
-__device__ __forceinline__ T adj_u(const AdjView<T>& v, int c, int i, int j, int k) {
-    if (!e_in(v, c, i, j, k)) return (T)0;
-    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
-    const T ie = gld(v.lut_inv_eps + ldo(v.mat, x));
-    T cb = (T)1;
-    if (v.has_layer) cb = recip((T)1 + adj_loss_e(v, c, i, j, k));
-    return cb * ie * ldo(v.et[c], x);
-}
 
 // H part: htot = da htot_prev + S curl+(u) on the H-sites of [0,n)^3.
 template <typename T, int TY>
@@ -99,11 +89,15 @@ __global__ void __launch_bounds__(64 * TY) k_adj_h(AdjView<T> v, Geom gm) {
     const int j = by * TY + threadIdx.y;
     if (i >= v.nx || j >= v.ny) return;
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+    const T* __restrict__ ux = v.u[0];
+    const T* __restrict__ uy = v.u[1];
+    const T* __restrict__ uz = v.u[2];
     for (int k = kz0; k < kz1; ++k) {
-        const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
-        const T cx = (adj_u(v, 2, i, j + 1, k) - adj_u(v, 2, i, j, k)) - (adj_u(v, 1, i, j, k + 1) - adj_u(v, 1, i, j, k));
-        const T cy = (adj_u(v, 0, i, j, k + 1) - adj_u(v, 0, i, j, k)) - (adj_u(v, 2, i + 1, j, k) - adj_u(v, 2, i, j, k));
-        const T cz = (adj_u(v, 1, i + 1, j, k) - adj_u(v, 1, i, j, k)) - (adj_u(v, 0, i, j + 1, k) - adj_u(v, 0, i, j, k));
+        const uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)k;
+        const T cx = (ldo(uz, x + sx) - ldo(uz, x)) - (ldo(uy, x + sxy) - ldo(uy, x));
+        const T cy = (ldo(ux, x + sxy) - ldo(ux, x)) - (ldo(uz, x + 1u) - ldo(uz, x));
+        const T cz = (ldo(uy, x + 1u) - ldo(uy, x)) - (ldo(ux, x + sx) - ldo(ux, x));
         const T cc[3] = {cx, cy, cz};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -165,14 +159,13 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
                     cb = recip((T)1 + a);
                     ca = ((T)1 - a) * cb;
                 }
-                const T et = ldo(v.et[c], x);
+                const T et = ldo(v.u[c], x) / (cb * ie);
                 const T E = ldo(v.E0[c], x), En = ldo(v.E1[c], x);
                 T lam = ca * et - v.S * curl;
                 T Wh_prev = (T)0, dP_prev = (T)0;
                 if (g) {
-                    const T P0 = ldo(v.P0[c], gi), P1 = ldo(v.P1[c], gi);
-                    const T dPf = P1 - P0;
-                    const T dN = ldo(v.N1[c], gi) - ldo(v.N2[c], gi);
+                    const T dPf = ldo(v.dP1[c], gi);
+                    const T dN = ldo(v.dN[c], gi);
                     const T n1 = ldo(v.ln[0][c], gi), n2 = ldo(v.ln[1][c], gi), n3 = ldo(v.ln[2][c], gi);
                     const T Wh = n2 - n1;
                     const T dPh = Wh * v.beta * (T)0.5 * (En + E) - cb * ie * et;
@@ -188,7 +181,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
                     sto(v.ln[2][c], gi, m3);
                     gna += (double)(n3 * v.dtWp) + (double)(v.ck_esp * xi[c] * pn);
                     Wh_prev = m2 - m1;
-                    dP_prev = P0 - ldo(v.Pm[c], gi);
+                    dP_prev = ldo(v.dP0[c], gi);
                 }
                 // E^{n+1} = ca E^n + cb ie (S curl- H' - dP) + src: its eps derivative
                 const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? v.src : (T)0;
@@ -199,7 +192,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
                         lam += (T)2 * E;
                     lam += Wh_prev * v.beta * (T)0.5 * dP_prev;
                 }
-                sto(v.et[c], x, lam);
+                sto(v.u[c], x, cb * ie * lam);
             }
             const uint32_t cell = (uint32_t)i + (uint32_t)v.nx * ((uint32_t)j + (uint32_t)v.ny * (uint32_t)k);
             sto(v.g_eps, cell, gld(v.g_eps + cell) + geps);
@@ -210,7 +203,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
 }
 
 // Start of the reverse sweep: etot = 2 E^N on the interior sites of the box
-// (and zero elsewhere); the other adjoint arrays start at zero.
+// (u = cb ie etot; zero elsewhere); the other adjoint arrays start at zero.
 template <typename T>
 __global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
     const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
@@ -218,7 +211,16 @@ __global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
     const bool inb = i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) sto(v.et[c], x, (inb && e_in(v, c, i, j, k)) ? (T)2 * ldo(v.E1[c], x) : (T)0);
+    for (int c = 0; c < 3; ++c) {
+        T u = (T)0;
+        if (inb && e_in(v, c, i, j, k)) {
+            const T ie = gld(v.lut_inv_eps + ldo(v.mat, x));
+            T cb = (T)1;
+            if (v.has_layer) cb = recip((T)1 + adj_loss_e(v, c, i, j, k));
+            u = cb * ie * ((T)2 * ldo(v.E1[c], x));
+        }
+        sto(v.u[c], x, u);
+    }
 }
 
 // dL/d(N_a/N_ref) through the initial populations N_i^0 = r_i N_a/N_ref of

@@ -38,6 +38,7 @@ struct Ctl {                  // per-simulation control block (device memory)
     int32_t nonfinite;        // set once a step produced a non-finite energy
     int32_t pad;
     double src_val;           // soft-source value added during the current step
+    int64_t tap_base;         // step of trajectory slot 0 while a trajectory is recorded
 };
 
 template <typename T>
@@ -47,6 +48,12 @@ struct SimView {
     T* P[2][3];               // compact, one value per gain cell
     T* N[3][3];               // N1, N2, N3 x component, compact
     const uint32_t* seg_base; // gain cells before segment (bx, j, k), bx + nbx (j + ny k)
+    // trajectory recording for the adjoint (tap == nullptr: off): the E pass
+    // writes E^{n+1}, P^{n+1} - P^n and N1 - N2 at n+1 into slot
+    // n + 1 - ctl->tap_base of tap_stride values: E (3 x tap_e dense), dP
+    // (3 x tap_c compact), N1 - N2 (3 x tap_c compact)
+    T* tap;
+    int64_t tap_stride, tap_e, tap_c;
     int nbx;                  // 64-wide segments per row
     const uint8_t* mat;       // per site of the extended range
     const T* lut_inv_eps;     // per material id
@@ -420,7 +427,7 @@ __device__ __forceinline__ BlochIn<T> bloch_load(const Fields<T>& f, int c, uint
 template <typename T>
 __device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f, int c, uint32_t gi,
                                         T e, T curl, T ie, bool upd, bool gain,
-                                        const BlochIn<T>& b, T xi, T src, T loss) {
+                                        const BlochIn<T>& b, T xi, T src, T loss, T* tslot) {
     T dP = (T)0;
     T Pn = (T)0;
     if (gain) {
@@ -440,16 +447,30 @@ __device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f,
     en = upd ? en : e;
     if (gain) {
         sto(f.q[c], gi, Pn);
+        T d12 = b.n1 - b.n2;
         if (!v.frozen_pop) {
             const T n1 = b.n1, n2 = b.n2, n3 = b.n3;
             const T W = v.beta * ((T)0.5 * (en + e)) * dP;
             const T n0 = v.Na - n1 - n2 - n3;
+            const T m2 = n2 + (v.dt32 * n3 - v.dt21 * n2) + W;
+            const T m1 = n1 + (v.dt21 * n2 - v.dt10 * n1) - W;
             sto(f.n3[c], gi, n3 + (v.dtWp * n0 - v.dt32 * n3));
-            sto(f.n2[c], gi, n2 + (v.dt32 * n3 - v.dt21 * n2) + W);
-            sto(f.n1[c], gi, n1 + (v.dt21 * n2 - v.dt10 * n1) - W);
+            sto(f.n2[c], gi, m2);
+            sto(f.n1[c], gi, m1);
+            d12 = m1 - m2;
+        }
+        if (tslot) {
+            sto(tslot + 3 * v.tap_e + c * v.tap_c, gi, dP);
+            sto(tslot + 3 * v.tap_e + 3 * v.tap_c + c * v.tap_c, gi, d12);
         }
     }
     return en;
+}
+
+// Base of the trajectory slot that step n writes (nullptr when not recording).
+template <typename T>
+__device__ __forceinline__ T* tap_slot(const SimView<T>& v, int64_t n) {
+    return v.tap ? v.tap + (n + 1 - gld(&v.ctl->tap_base)) * v.tap_stride : nullptr;
 }
 
 // The soft source's value for component c at this site (zero elsewhere).
@@ -476,6 +497,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
     const int64_t n = gld(&v.ctl->step);
     const int par = (int)(n & 1);
     const Fields<T> f = bind_fields(v, par);
+    T* const tslot = tap_slot(v, n);
     double lsum = 0.0;
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
     if (i < v.nx && j < v.ny) {
@@ -513,22 +535,25 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             {
                 const T curl = inx ? (hz - ldo(Hz, x - sx)) - (hy - hym) : (T)0;
                 const T en = bloch_site(v, f, 0, gi, ldo(f.e[0], x), curl, ie, inx, g && inx, b0, xi[0], s0,
-                                        v.has_layer ? loss_e(v, 0, i, j, k) : (T)0);
+                                        v.has_layer ? loss_e(v, 0, i, j, k) : (T)0, tslot);
                 sto(f.en[0], x, en);
+                if (tslot) sto(tslot, x, en);
                 if (inx) acc += en * en;
             }
             {
                 const T curl = iny ? (hx - hxm) - (hz - ldo(Hz, x - 1u)) : (T)0;
                 const T en = bloch_site(v, f, 1, gi, ldo(f.e[1], x), curl, ie, iny, g && iny, b1, xi[1], s1,
-                                        v.has_layer ? loss_e(v, 1, i, j, k) : (T)0);
+                                        v.has_layer ? loss_e(v, 1, i, j, k) : (T)0, tslot);
                 sto(f.en[1], x, en);
+                if (tslot) sto(tslot + v.tap_e, x, en);
                 if (iny) acc += en * en;
             }
             {
                 const T curl = inz ? (hy - ldo(Hy, x - 1u)) - (hx - ldo(Hx, x - sx)) : (T)0;
                 const T en = bloch_site(v, f, 2, gi, ldo(f.e[2], x), curl, ie, inz, g && inz, b2, xi[2], s2,
-                                        v.has_layer ? loss_e(v, 2, i, j, k) : (T)0);
+                                        v.has_layer ? loss_e(v, 2, i, j, k) : (T)0, tslot);
                 sto(f.en[2], x, en);
+                if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                 if (inz) acc += en * en;
             }
             if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
@@ -581,6 +606,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
     const int j = by * TY + threadIdx.y;
     const int64_t n = gld(&v.ctl->step);
     const Fields<T> f = bind_fields(v, (int)(n & 1));
+    T* const tslot = tap_slot(v, n);
     T wsum = (T)0;
     double lsum = 0.0;
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
@@ -687,22 +713,25 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 {
                     const T curl = inx ? (nhz - nhz_m) - (nhy - hyp) : (T)0;
                     const T en = bloch_site(v, f, 0, gi, ex, curl, ie, inx, g && inx, b0, xi[0], s0,
-                                            lay ? loss_e(v, 0, i, j, k) : (T)0);
+                                            lay ? loss_e(v, 0, i, j, k) : (T)0, tslot);
                     sto(f.en[0], x, en);
+                    if (tslot) sto(tslot, x, en);
                     if (inx) acc += en * en;
                 }
                 {
                     const T curl = iny ? (nhx - hxp) - (nhz - nhz_l) : (T)0;
                     const T en = bloch_site(v, f, 1, gi, ey, curl, ie, iny, g && iny, b1, xi[1], s1,
-                                            lay ? loss_e(v, 1, i, j, k) : (T)0);
+                                            lay ? loss_e(v, 1, i, j, k) : (T)0, tslot);
                     sto(f.en[1], x, en);
+                    if (tslot) sto(tslot + v.tap_e, x, en);
                     if (iny) acc += en * en;
                 }
                 {
                     const T curl = inz ? (nhy - nhy_l) - (nhx - nhx_m) : (T)0;
                     const T en = bloch_site(v, f, 2, gi, ez, curl, ie, inz, g && inz, b2, xi[2], s2,
-                                            lay ? loss_e(v, 2, i, j, k) : (T)0);
+                                            lay ? loss_e(v, 2, i, j, k) : (T)0, tslot);
                     sto(f.en[2], x, en);
+                    if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                     if (inz) acc += en * en;
                 }
                 if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
@@ -917,6 +946,30 @@ __global__ void __launch_bounds__(64) k_init_pop(SimView<T> v, T n1, T n2, T n3)
         v.N[0][c][gi] = in[c] ? n1 : (T)0;
         v.N[1][c][gi] = in[c] ? n2 : (T)0;
         v.N[2][c][gi] = in[c] ? n3 : (T)0;
+    }
+}
+
+// Record the current state (step n = ctl->step) into trajectory slot
+// n - ctl->tap_base: E^n, P^n - P^{n-1} and N1 - N2, as the E pass does for
+// the states it produces.  Grid (nbx, ny, nz) of one wave each.
+template <typename T>
+__global__ void __launch_bounds__(64) k_tap_state(SimView<T> v) {
+    const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const bool act = i < v.nx;
+    const uint32_t x = (uint32_t)(act ? i : 0) + (uint32_t)v.sx * j + (uint32_t)v.sxy * k;
+    const bool g = act && v.mat[x] >= kGainId;
+    const uint32_t gi = gain_index(v, (int)blockIdx.x, j, k, g, true);
+    if (!act) return;
+    const int64_t n = gld(&v.ctl->step);
+    const Fields<T> f = bind_fields(v, (int)(n & 1));
+    T* slot = v.tap + (n - gld(&v.ctl->tap_base)) * v.tap_stride;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sto(slot + c * v.tap_e, x, ldo(f.e[c], x));
+        if (g) {
+            sto(slot + 3 * v.tap_e + c * v.tap_c, gi, ldo(f.p[c], gi) - ldo(f.q[c], gi));
+            sto(slot + 3 * v.tap_e + 3 * v.tap_c + c * v.tap_c, gi, ldo(f.n1[c], gi) - ldo(f.n2[c], gi));
+        }
     }
 }
 
