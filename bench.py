@@ -61,10 +61,82 @@ def parse():
                     help="also run one plain elementwise kernel of known traffic (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarise rocprofv3 results under DIR and exit")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the calibrated HBM traffic summary of --kernel from two rocprofv3 "
+                         "--pmc runs (FETCH_SIZE, WRITE_SIZE, each with --calib-copy) and exit")
+    ap.add_argument("--kernel", default="k_curl_e_batch")
+    ap.add_argument("--tuning", default="two_pass/4/4/1",
+                    help="variant/tile_y/zseg/xcd_remap the counter runs used")
     return ap.parse_args()
 
 
 CALIB_BYTES = 1 << 30          # the calibration kernel reads 1 GiB and writes 1 GiB
+
+
+def pmc_means(d):
+    """{(kernel name, counter): mean per dispatch} of the rocprofv3 databases under d."""
+    import glob
+    import sqlite3
+    acc = {}
+    for path in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        db = sqlite3.connect(path)
+        for name, _, cn, val in db.execute(
+                "select kernel_name, dispatch_id, counter_name, sum(value) from counters_collection "
+                "group by dispatch_id, counter_name"):
+            acc.setdefault((name, cn), []).append(val)
+        db.close()
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def write_traffic(fetch_dir, write_dir, kernel, workload, tuning):
+    """profiles/<kernel>_<workload>_traffic.md from a FETCH_SIZE and a
+    WRITE_SIZE run, each calibrated by the plain add kernel of --calib-copy
+    (reads and writes CALIB_BYTES)."""
+    f, w = pmc_means(fetch_dir), pmc_means(write_dir)
+
+    def pick(m, counter, pred):
+        hits = [(k[0], v) for k, v in m.items() if k[1] == counter and pred(k[0])]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel for {counter}, found {[h[0] for h in hits]}")
+        return hits[0]
+    is_k = lambda name: name.startswith(f"void mbf::{kernel}<float")
+    is_cal = lambda name: "CUDAFunctorOnSelf_add<float>" in name
+    kname, kf = pick(f, "FETCH_SIZE", is_k)
+    _, kw = pick(w, "WRITE_SIZE", is_k)
+    _, cf = pick(f, "FETCH_SIZE", is_cal)
+    _, cw = pick(w, "WRITE_SIZE", is_cal)
+    ff = CALIB_BYTES / (cf * 1024.0)
+    fw = CALIB_BYTES / (cw * 1024.0)
+    rd, wr = kf * 1024.0 * ff, kw * 1024.0 * fw
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d $REPO/gpurun_out/{d} -o run -- "
+           "python3 $REPO/bench.py --workload " + workload + " --steps 8 --warmup 4 --no-cpu-baseline --calib-copy")
+    out = f"""# HBM traffic of `{kernel}` on the {workload} bench workload
+
+Kernel: `{kname}`
+
+Commands (the bench's own launch configuration, 8 timed steps; counters per dispatch):
+
+    {cmd.format(c="FETCH_SIZE", d="fetch")}
+    {cmd.format(c="WRITE_SIZE", d="write")}
+    python3 bench.py --write-traffic gpurun_out/fetch gpurun_out/write --kernel {kernel} --workload {workload} --tuning {tuning}
+
+Calibration: the plain elementwise add of `--calib-copy` reads and writes {CALIB_BYTES} B.
+FETCH_SIZE reads {cf:.6g} KiB for it (factor {ff:.4f}: the counter counts a 128-byte request
+as 64 bytes); WRITE_SIZE reads {cw:.6g} KiB (factor {fw:.4f}).
+
+| | counter KiB / dispatch | factor | bytes / dispatch |
+|---|---:|---:|---:|
+| read (FETCH_SIZE) | {kf:.6g} | {ff:.4f} | {rd:.6g} |
+| write (WRITE_SIZE) | {kw:.6g} | {fw:.4f} | {wr:.6g} |
+
+traffic_bytes_per_launch: {rd + wr:.6g}
+kernel_source_sha256: {kernel_source_sha()}
+tuning: {tuning}
+"""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    open(path, "w").write(out)
+    print(out)
 
 
 def summarize_profile(d):
@@ -235,6 +307,11 @@ def main():
     args = parse()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile)
+        return
+    if args.write_traffic:
+        t = args.tuning.split("/")
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.kernel, args.workload,
+                      "/".join(t[:4]))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "

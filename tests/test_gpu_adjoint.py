@@ -187,3 +187,25 @@ def test_c4_adjoint_against_fp64_differences():
     print(f"C4: eps gradient error {err:.2e} over 20 cells, N_a gradient error {errn:.2e}")
     assert err <= 1e-3
     assert errn <= 1e-3
+
+
+def test_torch_autograd_binding():
+    import torch
+    from paper_0809_1547_amd.autograd import loss_box_objective
+    eps, gain = _material()
+    e = torch.tensor(eps, requires_grad=True)
+    Na = torch.tensor(2e24, dtype=torch.float64, requires_grad=True)
+    setup = dict(n=N, gain=gain, box=BOX, nsteps=40, K=9, init="prepumped", source=(*SRC, 0.3),
+                 precision="fp64", seed=3, realization=1, E_sp=1e-2)
+    L = loss_box_objective(e, Na, setup)
+    L.backward()
+    mbf = _mbf()
+    sim = mbf.Sim(N, precision="fp64", seed=3, realization=1, E_sp=1e-2)
+    sim.set_material(eps, gain)
+    sim.set_pump(2e24)
+    sim.set_source(*SRC, amp=0.3)
+    sim.set_loss_box(*BOX)
+    L2, g2, gna2 = sim.adjoint_run(40, K=9)
+    assert float(L) == L2
+    assert np.array_equal(e.grad.numpy(), g2.astype(np.float32))
+    assert float(Na.grad) == gna2
