@@ -1,0 +1,58 @@
+"""GPU parity at the benchmark's full size and launch configuration: two
+320^3 realizations of the paper-scale packing advanced as one batch (two-pass
+schedule, tile 64 x 4, 4-plane segments, XCD-grouped, graph-replayed chunks
+of 32 steps with probes), member 0 against the FP64 oracle over 40 steps."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0809_1547_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N = 320
+STEPS = 40
+
+
+def test_320_cubed_batch_member_matches_oracle():
+    from paper_0809_1547_amd import mbf
+    print("320^3 full-size parity: packing", flush=True)
+    eps, gain = I.voxelize(I.rsa_pack(N, seed=0, fill=0.4))
+    probes = I.select_probes(eps, gain, 256, seed=0)
+    cfgs = [mbf.make_config(N, boundary="absorb", seed=0, realization=r, E_sp=1e-2) for r in range(2)]
+    batch = mbf.Batch(cfgs)
+    batch.set_tuning("two_pass", tile_y=4, zseg=4, xcd_remap=1)
+    for r, s in enumerate(batch.members):
+        s.set_material(eps, gain)
+        s.set_pump((2e24, 5e24)[r], "prepumped")
+        dt = s.coefficients()[mbf.MBF_C_DT]
+        s.set_probes(probes, I.dft_omegas(450e-9, 800e-9, 78675, dt), decim=32)
+    print("320^3 full-size parity: GPU steps", flush=True)
+    batch.step(STEPS)
+    batch.sync()
+    print("320^3 full-size parity: oracle steps", flush=True)
+    ora = O.Oracle(O.default_params(N, bc=(O.ABSORB,) * 3, round_f32=True, seed=0, realization=0,
+                                    E_sp=1e-2))
+    ora.set_material(eps, gain)
+    ora.set_pump(2e24, O.PREPUMPED)
+    ora.step(STEPS)
+    m = batch[0]
+    worst = 0.0
+    for grp in ((0, 1, 2), (3, 4, 5), (6, 7, 8), (12, 13, 14), (15, 16, 17), (18, 19, 20)):
+        num = den = 0.0
+        for f in grp:
+            a, b = m.field(f).astype(np.float64), ora.field(f)
+            num += float(np.sum((a - b) ** 2))
+            den += float(np.sum(b ** 2))
+        err = math.sqrt(num / den)
+        print("group", grp, "rel L2", err, flush=True)
+        worst = max(worst, err)
+    W, _ = m.energy()
+    Wo, _ = ora.energy()
+    print("energy", W, Wo, flush=True)
+    assert worst <= 1e-5
+    assert W == pytest.approx(Wo, rel=1e-5)
+    ora.close()
+    batch.close()
