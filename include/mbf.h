@@ -231,9 +231,13 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 
 /* Kernel schedule.  Both variants give bitwise identical fields; they differ
  * in how the step is cut into kernels.  Workgroups cover 64 x tile_y columns
- * over zseg planes (zseg = 0: 4) and are grouped per XCD when xcd_remap = 1.
- * tile_y must be 2, 4, 8 or 16.
- *   MBF_VARIANT_TWO_PASS (default: tile_y 4, zseg 4): a1 in one kernel,
+ * over zseg planes (zseg = 0: 4).  xcd_remap chooses which XCD runs which
+ * workgroup (the hardware deals launch-order workgroups to the 8 XCDs in
+ * turn): 0 launch order; 1 each XCD a contiguous range of (x tile, y tile,
+ * z segment) work items; 2 (default) whole z-segment layers dealt to the XCDs
+ * in turn, so neighbouring tiles share an L2 and the XCDs stream one window of
+ * planes together.  tile_y must be 2, 4, 8 or 16.
+ *   MBF_VARIANT_TWO_PASS (default: tile_y 4, zseg 4, xcd_remap 2): a1 in one kernel,
  *     a2-a5 in a second.
  *   MBF_VARIANT_FUSED: rows a1-a5 in one z-marching kernel in which every
  *     wave owns a row and forms again the few H^{n+1/2} values of the
@@ -338,9 +342,10 @@ int mbf_batch_step(mbf_batch* b, int64_t nsteps);
 int mbf_batch_sync(mbf_batch* b);
 int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms /* [2] */, int64_t* launches);
 int mbf_batch_step_bytes(const mbf_batch* b, double* bytes /* [3] */);
-/* mbf_autotune for a whole batch: the schedule is timed on graph-replayed
- * batched chunks, then group_mb (0, 64, 128, 192) for the best schedule; the
- * result applies to the batch and every member. */
+/* mbf_autotune for a whole batch, timed on graph-replayed batched chunks:
+ * group_mb (0, 1, 96, 192) at the default schedule, then the schedules at the
+ * best grouping, then the other groupings (32, 64, 128) for the best
+ * schedule; the result applies to the batch and every member. */
 int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen);
 
 #ifdef __cplusplus

@@ -79,7 +79,7 @@ struct mbf_handle {
         mur_c[mbf::kMaxMurTasks] = {};
     Coef co{};
     double Na_si = 0.0;
-    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1, 0};
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 2, 0};
     void* prof = nullptr;     // lossy-layer profiles: [axis][integer, half][n_axis + 1]
     int64_t prof_stride = 0;
     bool has_layer = false;
@@ -516,11 +516,11 @@ void snap_free(Snap& s) {
 // Candidate schedules tried by the autotuner, the default first.
 std::vector<mbf_tuning> tuning_candidates() {
     std::vector<mbf_tuning> c;
-    c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 1, 0});
+    c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 2, 0});
     for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED})
         for (int ty : {2, 4, 8})
             for (int zs : {2, 4, 8})
-                if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 1, 0});
+                if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 2, 0});
     return c;
 }
 
@@ -1056,7 +1056,7 @@ int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
     if (t->zseg < 0) return fail(h, MBF_EINVAL, "zseg must be >= 0");
     if (t->group_mb < 0) return fail(h, MBF_EINVAL, "group_mb must be >= 0");
     h->tun = *t;
-    h->tun.xcd_remap = t->xcd_remap ? 1 : 0;
+    h->tun.xcd_remap = t->xcd_remap < 0 ? 0 : (t->xcd_remap > 2 ? 2 : t->xcd_remap);
     drop_graph(h);
     return MBF_OK;
 }
@@ -1367,7 +1367,7 @@ struct mbf_batch {
     bool own_stream = false;
     int precision = MBF_FP32;
     std::string err;
-    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 1, 0};
+    mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 2, 0};
     void* d_views = nullptr;
     mbf::Geom* d_geoms = nullptr;
     uint32_t* d_items = nullptr;
@@ -1414,6 +1414,42 @@ void batch_free_tables(mbf_batch* b) {
     b->tables = false;
 }
 
+// Reorder the work-table entries [i0, i1) (member by member, items in order)
+// into dispatch order.  remap 0: as they are; 1: XCD x takes the x-th
+// contiguous range; 2: whole z-segment layers (all tiles of one segment of
+// one member) are dealt to the XCDs in turn, and an XCD whose layers run out
+// takes the remaining entries of the others.
+void dispatch_order(std::vector<uint32_t>& items, int i0, int i1, const std::vector<mbf::Geom>& geoms, int remap) {
+    const int n = i1 - i0;
+    if (remap == 0 || n == 0) return;
+    std::vector<uint32_t> src(items.begin() + i0, items.begin() + i1), out((size_t)n);
+    if (remap == 1) {
+        const int q = n >> 3, r = n & 7;
+        for (int bb = 0; bb < n; ++bb) {
+            const int x = bb & 7, idx = bb >> 3;
+            out[(size_t)bb] = src[(size_t)(x * q + std::min(x, r) + idx)];
+        }
+    } else {
+        std::vector<std::vector<uint32_t>> queue(8);
+        int layer = 0;
+        for (int e = 0; e < n;) {
+            const int r = (int)(src[(size_t)e] >> 24);
+            const int Q = geoms[(size_t)r].tiles_x * geoms[(size_t)r].tiles_y;
+            const int len = std::min(Q, n - e);
+            for (int t = 0; t < len; ++t) queue[(size_t)(layer & 7)].push_back(src[(size_t)(e + t)]);
+            e += len;
+            ++layer;
+        }
+        std::vector<size_t> head(8, 0);
+        for (int bb = 0; bb < n; ++bb) {
+            int x = bb & 7;
+            for (int t = 0; t < 8 && head[(size_t)x] == queue[(size_t)x].size(); ++t) x = (x + 1) & 7;
+            out[(size_t)bb] = queue[(size_t)x][head[(size_t)x]++];
+        }
+    }
+    std::copy(out.begin(), out.end(), items.begin() + i0);
+}
+
 // Rebuild the device views, geometries and work table when a member changed.
 template <typename T>
 int batch_tables(mbf_batch* b) {
@@ -1453,6 +1489,10 @@ int batch_tables(mbf_batch* b) {
             gr.mur_sites = std::max(gr.mur_sites, nmax * nmax);
         }
     }
+    // put each group's entries in dispatch order: the hardware deals workgroup
+    // q of a launch to XCD q mod 8, so entry q is the item that XCD should run
+    for (const mbf_batch::Group& gr : b->groups)
+        dispatch_order(items, gr.i0, gr.i1, geoms, b->tun.xcd_remap);
     if (hipMalloc(&b->d_views, sizeof(mbf::SimView<T>) * R) != hipSuccess ||
         hipMalloc(&b->d_geoms, sizeof(mbf::Geom) * R) != hipSuccess ||
         hipMalloc(&b->d_items, sizeof(uint32_t) * items.size()) != hipSuccess) {
@@ -1788,29 +1828,42 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
     auto over = [&]() {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > budget_ms;
     };
-    int tried = 0;
-    for (mbf_tuning cand : tuning_candidates()) {        // schedule, at the current grouping
-        if (rc || (tried > 0 && over())) break;
-        cand.group_mb = keep.group_mb;
+    std::vector<mbf_tuning> tried;
+    auto consider = [&](const mbf_tuning& cand) {
+        for (const mbf_tuning& t : tried)
+            if (t.variant == cand.variant && t.tile_y == cand.tile_y && t.zseg == cand.zseg &&
+                t.group_mb == cand.group_mb)
+                return;
+        tried.push_back(cand);
         double ms = 0.0;
         rc = trial(cand, ms);
-        ++tried;
         if (!rc && ms < best_ms) {
             best_ms = ms;
             best = cand;
         }
+    };
+    // the grouping first, at the default schedule (a member per group keeps
+    // small members in the last-level cache over a chunk), then the schedule
+    // at the best grouping, then the grouping again
+    const int groups[] = {0, 1, 96, 192, 32, 64, 128};
+    const mbf_tuning base = tuning_candidates()[0];
+    for (int q = 0; q < 4 && !rc && (q == 0 || !over()); ++q) {
+        mbf_tuning cand = base;
+        cand.group_mb = groups[q];
+        consider(cand);
     }
-    for (int g : {0, 64, 128, 192}) {                    // then the grouping
+    const int g_best = best.group_mb;
+    for (mbf_tuning cand : tuning_candidates()) {
         if (rc || over()) break;
-        if (g == best.group_mb) continue;
-        mbf_tuning cand = best;
+        cand.group_mb = g_best;
+        consider(cand);
+    }
+    const mbf_tuning sched = best;
+    for (int g : groups) {
+        if (rc || over()) break;
+        mbf_tuning cand = sched;
         cand.group_mb = g;
-        double ms = 0.0;
-        rc = trial(cand, ms);
-        if (!rc && ms < best_ms) {
-            best_ms = ms;
-            best = cand;
-        }
+        consider(cand);
     }
     const int rc2 = mbf_batch_set_tuning(b, rc ? &keep : &best);
     if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = bfail(b, MBF_EHIP, "synchronise failed");

@@ -297,9 +297,24 @@ struct Geom {
 // share) meet in the same L2.
 __device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
     if (!remap) return b;
+    remap = 1;
     const int q = nblk >> 3, r = nblk & 7;
     const int x = b & 7, idx = b >> 3;
     return x * q + (x < r ? x : r) + idx;
+}
+
+// Work item of this workgroup.  xcd_remap = 2 deals whole z-segment layers
+// (every x, y tile of one segment) to the XCDs in turn instead, so the eight
+// XCDs work in one window of consecutive segments while each layer's tiles
+// share one L2 (when the segment count is a multiple of 8).
+__device__ __forceinline__ int work_item(const Geom& g) {
+    const int b = (int)blockIdx.x;
+    if (g.xcd_remap == 2 && (g.segs & 7) == 0) {
+        const int Q = g.tiles_x * g.tiles_y;
+        const int x = b & 7, s = b >> 3;
+        return (x + 8 * (s / Q)) * Q + s % Q;
+    }
+    return xcd_work_item(b, g.nblk, g.xcd_remap);
 }
 
 // Work item -> (x tile, y tile, z segment), x tile fastest (memory order).
@@ -312,13 +327,15 @@ __device__ __forceinline__ void decode_item(const Geom& g, int w, int& bx, int& 
 
 // A batch of simulations stepped by one launch per kernel: the device array
 // of the members' views and geometries, and a work table whose entry q holds
-// (member << 24) | work item; entries run member by member, each member's
-// items in order.  Energy and loss partials are indexed by the member's own
+// (member << 24) | work item for workgroup q of the launch (the host lays the
+// table out in dispatch order, XCD grouping included).  Energy and loss partials are indexed by the member's own
 // work item, so a member's sums match its solo run term for term.
 
 __device__ __forceinline__ void batch_item(const uint32_t* __restrict__ items, int nitems, int remap,
                                            int& r, int& w) {
-    const uint32_t e = items[xcd_work_item((int)blockIdx.x, nitems, remap)];
+    (void)nitems;
+    (void)remap;                       // the table is already in dispatch order
+    const uint32_t e = items[blockIdx.x];
     r = (int)(e >> 24);
     w = (int)(e & 0xFFFFFFu);
 }
@@ -385,7 +402,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
 
 template <typename T, int TY>
 __global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
-    curl_h_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+    curl_h_body<T, TY>(v, gm, work_item(gm));
 }
 
 // The tables are separate no-alias read-only arguments, so the compiler may
@@ -572,7 +589,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
 
 template <typename T, int TY>
 __global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
-    curl_e_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+    curl_e_body<T, TY>(v, gm, work_item(gm));
 }
 
 // The tables are separate no-alias read-only arguments, so the compiler may
@@ -757,7 +774,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
 
 template <typename T, int TY>
 __global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
-    step_fused_body<T, TY>(v, gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap));
+    step_fused_body<T, TY>(v, gm, work_item(gm));
 }
 
 // The tables are separate no-alias read-only arguments, so the compiler may

@@ -296,7 +296,7 @@ def mbf_load_state(h: int, buf: bytes) -> None:
 
 
 def mbf_set_tuning(h: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
-                   xcd_remap: int = 1, group_mb: int = 0) -> None:
+                   xcd_remap: int = 2, group_mb: int = 0) -> None:
     t = mbf_tuning(variant, tile_y, zseg, xcd_remap, group_mb)
     _check(lib.mbf_set_tuning(h, C.byref(t)), h)
 
@@ -373,7 +373,7 @@ def mbf_batch_member(b: int, r: int) -> int:
 
 
 def mbf_batch_set_tuning(b: int, variant: int = MBF_VARIANT_TWO_PASS, tile_y: int = 4, zseg: int = 0,
-                         xcd_remap: int = 1, group_mb: int = 0) -> None:
+                         xcd_remap: int = 2, group_mb: int = 0) -> None:
     t = mbf_tuning(variant, tile_y, zseg, xcd_remap, group_mb)
     _bcheck(lib.mbf_batch_set_tuning(b, C.byref(t)), b)
 
@@ -506,7 +506,7 @@ class Sim:
     def loss(self):
         return mbf_read_loss(self.h)
 
-    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1, group_mb=0):
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=2, group_mb=0):
         mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)
 
     def tuning(self):
@@ -550,7 +550,7 @@ class Batch:
     def __getitem__(self, r):
         return self.members[r]
 
-    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=1, group_mb=0):
+    def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=2, group_mb=0):
         mbf_batch_set_tuning(self.b, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)
 
     def tuning(self):

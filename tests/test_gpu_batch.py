@@ -52,14 +52,15 @@ def _snapshot(sim, probes):
     return out
 
 
-@pytest.mark.parametrize("variant,group_mb", [("two_pass", 0), ("fused", 0), ("two_pass", 1), ("fused", 2)])
-def test_batch_members_equal_solo_runs(variant, group_mb):
+@pytest.mark.parametrize("variant,group_mb,remap", [("two_pass", 0, 2), ("fused", 0, 2), ("two_pass", 1, 2),
+                                                     ("fused", 2, 1), ("two_pass", 0, 0)])
+def test_batch_members_equal_solo_runs(variant, group_mb, remap):
     # group_mb 1 and 2 split the members into groups that run whole graph
     # chunks one after the other
     mbf = _mbf()
     hist = 120
     batch = mbf.Batch([_cfg(s, hist) for s in MEMBERS])
-    batch.set_tuning(variant, tile_y=4, zseg=4, group_mb=group_mb)
+    batch.set_tuning(variant, tile_y=4, zseg=4, xcd_remap=remap, group_mb=group_mb)
     for r, s in enumerate(MEMBERS):
         _setup(batch[r], s, r)
     batch.step(3)          # unaligned start: single batched steps
@@ -68,7 +69,7 @@ def test_batch_members_equal_solo_runs(variant, group_mb):
     assert all(batch[r].step_index == 103 for r in range(len(MEMBERS)))
     for r, s in enumerate(MEMBERS):
         solo = mbf.Sim(None, _cfg=_cfg(s, hist))
-        solo.set_tuning(variant, tile_y=4, zseg=4)
+        solo.set_tuning(variant, tile_y=4, zseg=4, xcd_remap=remap)
         _setup(solo, s, r)
         solo.step(103)
         ref = _snapshot(solo, s["probes"])
