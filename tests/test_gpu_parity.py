@@ -367,3 +367,36 @@ def test_bloch_state_lives_on_gain_cells_only():
         mbf.mbf_read_field(sim.h, fid, out)
         sim.sync()
         assert np.array_equal(out.cpu().numpy(), np.where(on, a[::-1], 0.0).astype(np.float32)), fid
+
+
+def test_lasing_spectra_match_oracle():
+    # a closed cavity (C1 packing, PEC) pumped well above threshold: the
+    # noise-seeded field grows by ten orders of magnitude and saturates within
+    # 24000 steps (0.92 ps); the probe spectra of the FP32 run and the FP64
+    # oracle must put every peak in the same DFT bin (within 1) with the same
+    # width (within 2%)
+    mbf = _mbf()
+    n, steps = 32, 24000
+    eps, gain = c1_material()
+    probes = I.select_probes(eps, gain, 16, seed=0)
+    sim, ora = pair(n, eps=eps, gain=gain, Na=5e24, E_sp=1e-3, hist=steps)
+    dt = sim.coefficients()[mbf.MBF_C_DT]
+    om = I.dft_omegas(450e-9, 800e-9, steps, dt)
+    sim.set_probes(probes, om, decim=32)
+    ora.set_probes(probes, om)
+    sim.step(steps)
+    ora.step(steps)
+    h = sim.energy_history()
+    assert h[-1] > 1e10 * h[1999]                      # lasing reached
+    fs, fo = np.abs(sim.spectrum()) ** 2, np.abs(ora.spectrum()) ** 2
+
+    def width(F, k):
+        w = slice(max(k - 5, 0), k + 6)
+        x = np.arange(F.shape[0])[w]
+        y = F[w]
+        m = np.sum(x * y) / np.sum(y)
+        return np.sqrt(np.sum((x - m) ** 2 * y) / np.sum(y))
+    for p in range(len(probes)):
+        ks, ko = int(np.argmax(fs[p])), int(np.argmax(fo[p]))
+        assert abs(ks - ko) <= 1, p
+        assert width(fs[p], ks) == pytest.approx(width(fo[p], ko), rel=0.02), p
