@@ -400,3 +400,18 @@ def test_lasing_spectra_match_oracle():
         ks, ko = int(np.argmax(fs[p])), int(np.argmax(fo[p]))
         assert abs(ks - ko) <= 1, p
         assert width(fs[p], ks) == pytest.approx(width(fo[p], ko), rel=0.02), p
+
+
+def test_c2_size_parity_linear_interval():
+    # the 128^3 workload (RSA fill 0.4, absorbing walls, prepumped, noise)
+    # over the first 1000 steps of its linear interval
+    n = 128
+    eps, gain = I.voxelize(I.packing_for("c2", n, 0))
+    sim, ora = pair(n, bc=("absorb",) * 3, eps=eps, gain=gain, E_sp=1e-3)
+    errs = []
+    for _ in range(4):
+        sim.step(250)
+        ora.step(250)
+        errs.append(worst(sim, ora, range(21)))
+    print("C2 128^3 rel L2 per 250 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= TOL32
