@@ -108,17 +108,18 @@ def write_traffic(fetch_dir, write_dir, kernel, workload, tuning):
     ff = CALIB_BYTES / (cf * 1024.0)
     fw = CALIB_BYTES / (cw * 1024.0)
     rd, wr = kf * 1024.0 * ff, kw * 1024.0 * fw
-    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d $REPO/gpurun_out/{d} -o run -- "
+    cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d $OUT/{d} -o run -- "
            "python3 $REPO/bench.py --workload " + workload + " --steps 8 --warmup 4 --no-cpu-baseline --calib-copy")
     out = f"""# HBM traffic of `{kernel}` on the {workload} bench workload
 
 Kernel: `{kname}`
 
-Commands (the bench's own launch configuration, 8 timed steps; counters per dispatch):
+Commands ($REPO the repository, $OUT a scratch directory; the bench's own launch
+configuration, 8 timed steps; counters per dispatch):
 
     {cmd.format(c="FETCH_SIZE", d="fetch")}
     {cmd.format(c="WRITE_SIZE", d="write")}
-    python3 bench.py --write-traffic gpurun_out/fetch gpurun_out/write --kernel {kernel} --workload {workload} --tuning {tuning}
+    python3 bench.py --write-traffic $OUT/fetch $OUT/write --kernel {kernel} --workload {workload} --tuning {tuning}
 
 Calibration: the plain elementwise add of `--calib-copy` reads and writes {CALIB_BYTES} B.
 FETCH_SIZE reads {cf:.6g} KiB for it (factor {ff:.4f}: the counter counts a 128-byte request
