@@ -260,17 +260,16 @@ def c3_batch(args, I, mbf, stream):
     """Many small realizations of uneven size: 64 packings with N drawn from
     {48, 64, 80, 96}, prepumped, with noise, at eight pump levels."""
     R = 64
-    rng = np.random.default_rng(0)
-    sizes = [int(x) for x in rng.choice([48, 64, 80, 96], size=R)]
+    sizes = I.batch_sizes(R, seed=0)
     cfgs = [mbf.make_config(N, boundary="pec", seed=0, realization=r) for r, N in enumerate(sizes)]
     batch = mbf.Batch(cfgs, stream=stream.cuda_stream)
-    levels = [0.5 * 8 ** (p / 7) * 2e24 for p in range(8)]
+    levels = I.batch_pump_levels(R, 2e24)     # nominal threshold: throughput does not depend on it
     mats = []
     for r, N in enumerate(sizes):
         eps, gain = I.voxelize(I.rsa_pack(N, seed=r, fill=0.4))
         mats.append((eps, gain))
         batch[r].set_material(eps, gain)
-        batch[r].set_pump(levels[r % 8], "prepumped")
+        batch[r].set_pump(levels[r], "prepumped")
     cells = sum(N ** 3 for N in sizes)
     config = {
         "workload": f"{R} realizations of uneven size (N in {{48,64,80,96}}, {cells} cells in all), "
@@ -290,7 +289,7 @@ def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream):
         s = mbf.Sim(N, boundary="pec", seed=0, realization=r, stream=stream.cuda_stream)
         s.set_tuning(**tuning)
         s.set_material(*mats[r])
-        s.set_pump(levels[r % 8], "prepumped")
+        s.set_pump(levels[r], "prepumped")
         s.step(32)
         sims.append(s)
     torch.cuda.synchronize()
