@@ -328,7 +328,9 @@ int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int me
  * fields, energies and spectra after mbf_batch_step are bitwise those of the
  * same member stepped alone with the same tuning.  Every member needs its
  * material and pump set (MBF_ESTATE otherwise).  mbf_batch_set_tuning sets
- * the schedule of the batch and of every member.  Timing and algorithmic
+ * the schedule of the batch and of every member; batched steps always use the
+ * batch's schedule, even for a member whose own schedule was changed later
+ * (that one only applies when the member is stepped alone).  Timing and algorithmic
  * bytes as for a handle, summed over the members.  Errors of batch calls are
  * read with mbf_batch_last_error. */
 int mbf_batch_create(const mbf_config* cfgs, int R, void* stream, mbf_batch** out);

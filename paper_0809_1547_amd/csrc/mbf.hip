@@ -238,21 +238,25 @@ mbf::SimView<T> view(mbf_handle* h) {
 }
 
 // Step kernels: workgroups of 64 x tile_y columns, each over zseg planes.
-int step_zseg(const mbf_handle* h) {
-    return h->tun.zseg > 0 ? std::min(h->tun.zseg, h->cfg.nz) : std::min(4, h->cfg.nz);
+int step_zseg(const mbf_handle* h, const mbf_tuning& t) {
+    return t.zseg > 0 ? std::min(t.zseg, h->cfg.nz) : std::min(4, h->cfg.nz);
 }
+int step_zseg(const mbf_handle* h) { return step_zseg(h, h->tun); }
 
-mbf::Geom step_geom(const mbf_handle* h) {
+// Work-item geometry of a handle's grid under schedule t (a batch steps its
+// members under the batch's schedule, whatever the members' own).
+mbf::Geom step_geom(const mbf_handle* h, const mbf_tuning& t) {
     mbf::Geom g{};
-    const int ty = h->tun.tile_y;
+    const int ty = t.tile_y;
     g.tiles_x = (h->cfg.nx + 63) / 64;
     g.tiles_y = (h->cfg.ny + ty - 1) / ty;
-    g.zseg = step_zseg(h);
+    g.zseg = step_zseg(h, t);
     g.segs = (h->cfg.nz + g.zseg - 1) / g.zseg;
     g.nblk = g.tiles_x * g.tiles_y * g.segs;
-    g.xcd_remap = h->tun.xcd_remap;
+    g.xcd_remap = t.xcd_remap;
     return g;
 }
+mbf::Geom step_geom(const mbf_handle* h) { return step_geom(h, h->tun); }
 
 // Geometry of the fused kernel's work items for the handle's tuning.
 
@@ -1468,7 +1472,7 @@ int batch_tables(mbf_batch* b) {
     double gbytes = 0.0;
     for (int r = 0; r < R; ++r) {
         mbf_handle* h = b->m[r];
-        geoms[r] = step_geom(h);
+        geoms[r] = step_geom(h, b->tun);
         views[r] = view<T>(h);
         views[r].n_part = geoms[r].nblk;
         if (geoms[r].nblk >= (1 << 24)) return bfail(b, MBF_EINVAL, "member grid has too many work items");

@@ -344,6 +344,30 @@ __device__ __forceinline__ void batch_item(const uint32_t* __restrict__ items, i
 // H^{n+1/2} = H^{n-1/2} - S curl+ E^n on the H-sites of [0,n)^3, plus the
 // energy W^n = 1/2 [sum eps E^n^2 (interior E-sites) + sum H^{n-1/2}.H^{n+1/2}
 // (H-sites off the wall normal to their component)].
+// Everything the H pass reads for one plane of a row: E^n at the site and at
+// its +x, +y, +z neighbours, H^{n-1/2} and the material byte.
+template <typename T>
+struct HPlane {
+    T ez, exk, eyk, ezy, ezx, eyx, exy, hx, hy, hz;
+    uint8_t m;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_hplane(HPlane<T>& p, const Fields<T>& f, const uint8_t* mat, uint32_t x,
+                                            uint32_t sx, uint32_t sxy) {
+    p.ez = ldo(f.e[2], x);
+    p.exk = ldo(f.e[0], x + sxy);
+    p.eyk = ldo(f.e[1], x + sxy);
+    p.ezy = ldo(f.e[2], x + sx);
+    p.ezx = ldo(f.e[2], x + 1u);
+    p.eyx = ldo(f.e[1], x + 1u);
+    p.exy = ldo(f.e[0], x + sx);
+    p.hx = ldo(f.h[0], x);
+    p.hy = ldo(f.h[1], x);
+    p.hz = ldo(f.h[2], x);
+    p.m = ldo(mat, x);
+}
+
 template <typename T, int TY>
 __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
@@ -362,15 +386,21 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
         const T* __restrict__ Ez = f.e[2];
         const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
         uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
-        // E^n at plane k is carried from the previous plane's k+1 loads
+        // E^n at plane k is carried from the previous plane's k+1 loads; the
+        // next plane's loads go out before this plane's arithmetic and stores
+        // (all offsets are +1 along x, y or z: at most column nx, row ny,
+        // plane nz of the extended range)
         T ex = ldo(Ex, x), ey = ldo(Ey, x);
+        HPlane<T> P, Q;
+        load_hplane(P, f, v.mat, x, sx, sxy);
         for (int k = kz0; k < kz1; ++k, x += sxy) {
-            const T ez = ldo(Ez, x);
-            const T exk = ldo(Ex, x + sxy), eyk = ldo(Ey, x + sxy);
-            const T cx = (ldo(Ez, x + sx) - ez) - (eyk - ey);
-            const T cy = (exk - ex) - (ldo(Ez, x + 1u) - ez);
-            const T cz = (ldo(Ey, x + 1u) - ey) - (ldo(Ex, x + sx) - ex);
-            const T hx = ldo(f.h[0], x), hy = ldo(f.h[1], x), hz = ldo(f.h[2], x);
+            if (k + 1 < kz1) load_hplane(Q, f, v.mat, x + sxy, sx, sxy);
+            const T ez = P.ez;
+            const T exk = P.exk, eyk = P.eyk;
+            const T cx = (P.ezy - ez) - (eyk - ey);
+            const T cy = (exk - ex) - (P.ezx - ez);
+            const T cz = (P.eyx - ey) - (P.exy - ex);
+            const T hx = P.hx, hy = P.hy, hz = P.hz;
             T ax = (T)0, ay = (T)0, az = (T)0;
             if (v.has_layer) {
                 ax = loss_h(v, 0, i, j, k);
@@ -383,7 +413,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             sto(f.hn[0], x, nhx);
             sto(f.hn[1], x, nhy);
             sto(f.hn[2], x, nhz);
-            const T eps = gld(v.lut_eps + ldo(v.mat, x));
+            const T eps = gld(v.lut_eps + P.m);
             T acc = (T)0;
             if (j >= 1 && k >= 1) acc += eps * ex * ex;
             if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -394,6 +424,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             wsum += (T)0.5 * acc;
             ex = exk;
             ey = eyk;
+            P = Q;
         }
     }
     const double s = block_sum((double)wsum, sh);
@@ -504,6 +535,30 @@ __device__ __forceinline__ void source3(const SimView<T>& v, int i, int j, int k
     }
 }
 
+// Everything the E pass reads for one plane of a row: the Bloch state of the
+// three sites, E^n, H^{n+1/2} and the H neighbours at y-1 and x-1.
+template <typename T>
+struct EPlane {
+    BlochIn<T> b0, b1, b2;
+    T ex, ey, ez, hx, hy, hz, hzy, hzx, hyx, hxy;
+};
+
+// Neighbours at y-1 only for j >= 1 and at x-1 only for i >= 1 (the offsets
+// would wrap below zero otherwise).
+template <typename T>
+__device__ __forceinline__ void load_plane(EPlane<T>& p, const Fields<T>& f, uint32_t x, uint32_t sx,
+                                           uint32_t gi, bool g, bool inx, bool iny, bool inz, int i, int j) {
+    p.b0 = bloch_load(f, 0, gi, g && inx);
+    p.b1 = bloch_load(f, 1, gi, g && iny);
+    p.b2 = bloch_load(f, 2, gi, g && inz);
+    p.hx = ldo(f.hn[0], x); p.hy = ldo(f.hn[1], x); p.hz = ldo(f.hn[2], x);
+    p.hzy = j >= 1 ? ldo(f.hn[2], x - sx) : (T)0;
+    p.hxy = j >= 1 ? ldo(f.hn[0], x - sx) : (T)0;
+    p.hzx = i >= 1 ? ldo(f.hn[2], x - 1u) : (T)0;
+    p.hyx = i >= 1 ? ldo(f.hn[1], x - 1u) : (T)0;
+    p.ex = ldo(f.e[0], x); p.ey = ldo(f.e[1], x); p.ez = ldo(f.e[2], x);
+}
+
 template <typename T, int TY>
 __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
@@ -519,27 +574,28 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
     if (i < v.nx && j < v.ny) {
         const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
-        const T* __restrict__ Hx = f.hn[0];
-        const T* __restrict__ Hy = f.hn[1];
-        const T* __restrict__ Hz = f.hn[2];
         uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
-        // the material byte and the compact index of plane k are known before
-        // the iteration starts, so every load of the plane issues at once
-        uint8_t m_next = ldo(v.mat, x);
-        uint32_t gi_next = gain_index(v, bx, j, kz0, m_next >= kGainId, true);
-        // H^{n+1/2} at plane k-1 is carried from the previous plane
-        T hxm = kz0 >= 1 ? ldo(Hx, x - sxy) : (T)0;
-        T hym = kz0 >= 1 ? ldo(Hy, x - sxy) : (T)0;
+        const bool iny0 = i >= 1, inz0 = i >= 1 && j >= 1;
+        uint8_t m = ldo(v.mat, x);
+        uint32_t gi = gain_index(v, bx, j, kz0, m >= kGainId, true);
+        uint8_t m_n = (kz0 + 1 < kz1) ? ldo(v.mat, x + sxy) : (uint8_t)0;
+        T hxm = kz0 >= 1 ? ldo(f.hn[0], x - sxy) : (T)0;
+        T hym = kz0 >= 1 ? ldo(f.hn[1], x - sxy) : (T)0;
+        EPlane<T> P, Q;
+        load_plane(P, f, x, sx, gi, m >= kGainId, j >= 1 && kz0 >= 1, iny0 && kz0 >= 1, inz0, i, j);
         for (int k = kz0; k < kz1; ++k, x += sxy) {
-            const uint8_t m = m_next;
-            const uint32_t gi = gi_next;
-            if (k + 1 < kz1) m_next = ldo(v.mat, x + sxy);     // one plane ahead
+            // software pipelining: the next plane's loads (its compact index
+            // from the material byte read one plane earlier) go out before this
+            // plane's arithmetic and stores, so two planes are in flight per wave
+            uint32_t gi_n = 0;
+            uint8_t m_nn = 0;
+            if (k + 1 < kz1) {
+                gi_n = gain_index(v, bx, j, k + 1, m_n >= kGainId, true);
+                if (k + 2 < kz1) m_nn = ldo(v.mat, x + 2u * sxy);
+                load_plane(Q, f, x + sxy, sx, gi_n, m_n >= kGainId, j >= 1, iny0, inz0, i, j);
+            }
             const bool g = m >= kGainId;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-            const BlochIn<T> b0 = bloch_load(f, 0, gi, g && inx);
-            const BlochIn<T> b1 = bloch_load(f, 1, gi, g && iny);
-            const BlochIn<T> b2 = bloch_load(f, 2, gi, g && inz);
-            const T hx = ldo(Hx, x), hy = ldo(Hy, x), hz = ldo(Hz, x);
             const T ie = gld(v.lut_inv_eps + m);
             T xi[3] = {(T)0, (T)0, (T)0};
             if (g && v.noise && (inx || iny || inz)) {
@@ -550,24 +606,24 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             source3(v, i, j, k, n, s0, s1, s2);
             T acc = (T)0;
             {
-                const T curl = inx ? (hz - ldo(Hz, x - sx)) - (hy - hym) : (T)0;
-                const T en = bloch_site(v, f, 0, gi, ldo(f.e[0], x), curl, ie, inx, g && inx, b0, xi[0], s0,
+                const T curl = inx ? (P.hz - P.hzy) - (P.hy - hym) : (T)0;
+                const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0,
                                         v.has_layer ? loss_e(v, 0, i, j, k) : (T)0, tslot);
                 sto(f.en[0], x, en);
                 if (tslot) sto(tslot, x, en);
                 if (inx) acc += en * en;
             }
             {
-                const T curl = iny ? (hx - hxm) - (hz - ldo(Hz, x - 1u)) : (T)0;
-                const T en = bloch_site(v, f, 1, gi, ldo(f.e[1], x), curl, ie, iny, g && iny, b1, xi[1], s1,
+                const T curl = iny ? (P.hx - hxm) - (P.hz - P.hzx) : (T)0;
+                const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1,
                                         v.has_layer ? loss_e(v, 1, i, j, k) : (T)0, tslot);
                 sto(f.en[1], x, en);
                 if (tslot) sto(tslot + v.tap_e, x, en);
                 if (iny) acc += en * en;
             }
             {
-                const T curl = inz ? (hy - ldo(Hy, x - 1u)) - (hx - ldo(Hx, x - sx)) : (T)0;
-                const T en = bloch_site(v, f, 2, gi, ldo(f.e[2], x), curl, ie, inz, g && inz, b2, xi[2], s2,
+                const T curl = inz ? (P.hy - P.hyx) - (P.hx - P.hxy) : (T)0;
+                const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2,
                                         v.has_layer ? loss_e(v, 2, i, j, k) : (T)0, tslot);
                 sto(f.en[2], x, en);
                 if (tslot) sto(tslot + 2 * v.tap_e, x, en);
@@ -576,9 +632,12 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
                 k >= v.box[2] && k < v.box[5])
                 lsum += (double)acc;
-            hxm = hx;
-            hym = hy;
-            if (k + 1 < kz1) gi_next = gain_index(v, bx, j, k + 1, m_next >= kGainId, true);
+            hxm = P.hx;
+            hym = P.hy;
+            P = Q;
+            m = m_n;
+            m_n = m_nn;
+            gi = gi_n;
         }
     }
     if (v.box_on) {

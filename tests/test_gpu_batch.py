@@ -163,3 +163,23 @@ def test_autotune_keeps_the_trajectory():
             assert np.array_equal(x, y), r
         solo.close()
     batch.close()
+
+
+def test_member_schedule_change_does_not_break_batched_steps():
+    # a member whose own schedule differs from the batch's is still stepped
+    # whole by the batched kernels (geometry follows the batch's schedule)
+    mbf = _mbf()
+    batch = mbf.Batch([_cfg(s, 0) for s in MEMBERS])
+    batch.set_tuning("two_pass", tile_y=4, zseg=4)
+    for r, s in enumerate(MEMBERS):
+        _setup(batch[r], s, r)
+    batch[1].set_tuning("fused", tile_y=16, zseg=2)
+    batch.step(40)
+    for r, s in enumerate(MEMBERS):
+        solo = mbf.Sim(None, _cfg=_cfg(s, 0))
+        _setup(solo, s, r)
+        solo.step(40)
+        for f in range(21):
+            assert np.array_equal(batch[r].field(f), solo.field(f)), (r, f)
+        solo.close()
+    batch.close()
