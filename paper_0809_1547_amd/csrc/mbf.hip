@@ -91,6 +91,14 @@ struct mbf_handle {
     void* tap = nullptr;      // trajectory recording buffer of the adjoint (nullptr: off)
     int64_t tap_stride = 0;   // values per trajectory slot
     int64_t tap_base = 0;     // host copy of ctl->tap_base
+    // device copy of the view, geometry and work table the step kernels read
+    void* d_view = nullptr;
+    mbf::Geom* d_geom = nullptr;
+    uint32_t* d_items = nullptr;
+    int items_cap = 0;
+    bool tab = false;
+    uint64_t tab_version = 0;
+    mbf::Geom tab_geom{};
     // graph of a chunk of steps
     hipGraphExec_t gexec = nullptr;
     int64_t gsteps = 0;
@@ -258,19 +266,131 @@ mbf::Geom step_geom(const mbf_handle* h, const mbf_tuning& t) {
 }
 mbf::Geom step_geom(const mbf_handle* h) { return step_geom(h, h->tun); }
 
-// Geometry of the fused kernel's work items for the handle's tuning.
-
-template <typename T>
-void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
-    const mbf::Geom g = step_geom(h);
-    v.n_part = g.nblk;
-    const dim3 grid((unsigned)g.nblk);
-    switch (h->tun.tile_y) {
-        case 2: hipLaunchKernelGGL((mbf::k_step_fused<T, 2>), grid, dim3(64, 2), 0, h->stream, v, g); break;
-        case 4: hipLaunchKernelGGL((mbf::k_step_fused<T, 4>), grid, dim3(64, 4), 0, h->stream, v, g); break;
-        case 16: hipLaunchKernelGGL((mbf::k_step_fused<T, 16>), grid, dim3(64, 16), 0, h->stream, v, g); break;
-        default: hipLaunchKernelGGL((mbf::k_step_fused<T, 8>), grid, dim3(64, 8), 0, h->stream, v, g); break;
+// Reorder the work-table entries [i0, i1) (member by member, items in order)
+// into dispatch order.  remap 0: as they are; 1: XCD x takes the x-th
+// contiguous range; 2: whole z-segment layers (all tiles of one segment of
+// one member) are dealt to the XCDs in turn, and an XCD whose layers run out
+// takes the remaining entries of the others.
+void dispatch_order(std::vector<uint32_t>& items, int i0, int i1, const std::vector<mbf::Geom>& geoms, int remap) {
+    const int n = i1 - i0;
+    if (remap == 0 || n == 0) return;
+    std::vector<uint32_t> src(items.begin() + i0, items.begin() + i1), out((size_t)n);
+    if (remap == 1) {
+        const int q = n >> 3, r = n & 7;
+        for (int bb = 0; bb < n; ++bb) {
+            const int x = bb & 7, idx = bb >> 3;
+            out[(size_t)bb] = src[(size_t)(x * q + std::min(x, r) + idx)];
+        }
+    } else {
+        std::vector<std::vector<uint32_t>> queue(8);
+        int layer = 0;
+        for (int e = 0; e < n;) {
+            const int r = (int)(src[(size_t)e] >> 24);
+            const int Q = geoms[(size_t)r].tiles_x * geoms[(size_t)r].tiles_y;
+            const int len = std::min(Q, n - e);
+            for (int t = 0; t < len; ++t) queue[(size_t)(layer & 7)].push_back(src[(size_t)(e + t)]);
+            e += len;
+            ++layer;
+        }
+        std::vector<size_t> head(8, 0);
+        for (int bb = 0; bb < n; ++bb) {
+            int x = bb & 7;
+            for (int t = 0; t < 8 && head[(size_t)x] == queue[(size_t)x].size(); ++t) x = (x + 1) & 7;
+            out[(size_t)bb] = queue[(size_t)x][head[(size_t)x]++];
+        }
     }
+    std::copy(out.begin(), out.end(), items.begin() + i0);
+}
+
+// The field kernels of one step (both passes, or the fused pass) over the
+// work table it[0..ni) of the views vw and geometries gw; evm (optional) is
+// recorded between the two passes.
+template <typename T>
+hipError_t launch_fields(hipStream_t st, const mbf_tuning& tun, const mbf::SimView<T>* vw,
+                         const mbf::Geom* gw, const uint32_t* it, int ni, hipEvent_t evm) {
+    const int rm = tun.xcd_remap;
+    const dim3 g((unsigned)ni);
+    hipError_t e = hipSuccess;
+    if (tun.variant == MBF_VARIANT_FUSED) {
+        switch (tun.tile_y) {
+            case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
+            case 4: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm); break;
+            case 16: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm); break;
+            default: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm); break;
+        }
+        if (evm) e = hipEventRecord(evm, st);
+        return e;
+    }
+    switch (tun.tile_y) {
+        case 2:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
+            break;
+        case 4:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
+            break;
+        case 16:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
+            break;
+        default:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
+            break;
+    }
+    return e;
+}
+
+// A handle steps through the same kernels as a batch, as a batch of one: its
+// view, geometry and work table (in dispatch order) live in device memory, so
+// that the kernels read the view through a pointer instead of holding it in
+// scalar registers.  Rebuilt when the handle's view or schedule changed (never
+// while the stream is being captured: a graph is built on current tables).
+template <typename T>
+int self_tables(mbf_handle* h, const mbf::Geom& g) {
+    if (h->tab && h->tab_version == h->version && std::memcmp(&h->tab_geom, &g, sizeof g) == 0)
+        return MBF_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(h->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(h, MBF_ESTATE, "step tables changed during graph capture");
+    if (g.nblk >= (1 << 24)) return fail(h, MBF_EINVAL, "grid has too many work items");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->tab = false;
+    if (!h->d_view) {
+        if (hipMalloc(&h->d_view, sizeof(mbf::SimView<double>)) != hipSuccess ||
+            hipMalloc(&h->d_geom, sizeof(mbf::Geom)) != hipSuccess)
+            return fail(h, MBF_ENOMEM, "step table allocation failed");
+    }
+    if (g.nblk > h->items_cap) {
+        hipFree(h->d_items);
+        h->d_items = nullptr;
+        h->items_cap = 0;
+        if (hipMalloc(&h->d_items, sizeof(uint32_t) * (size_t)g.nblk) != hipSuccess)
+            return fail(h, MBF_ENOMEM, "step table allocation failed");
+        h->items_cap = g.nblk;
+    }
+    mbf::SimView<T> v = view<T>(h);
+    v.n_part = g.nblk;
+    std::vector<uint32_t> items((size_t)g.nblk);
+    for (int w = 0; w < g.nblk; ++w) items[(size_t)w] = (uint32_t)w;      // member 0
+    dispatch_order(items, 0, g.nblk, std::vector<mbf::Geom>{g}, g.xcd_remap);
+    HIPCHK(h, hipMemcpy(h->d_view, &v, sizeof v, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->d_geom, &g, sizeof g, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice));
+    h->tab = true;
+    h->tab_version = h->version;
+    h->tab_geom = g;
+    return MBF_OK;
+}
+
+int prepare_tables(mbf_handle* h) {
+    const mbf::Geom g = step_geom(h);
+    return h->cfg.precision == MBF_FP64 ? self_tables<double>(h, g) : self_tables<float>(h, g);
 }
 
 // Queue one step.  When ev0/ev1 are given they bracket the step's field
@@ -278,44 +398,20 @@ void launch_fused(mbf_handle* h, mbf::SimView<T>& v) {
 template <typename T>
 int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullptr,
                 hipEvent_t ev1 = nullptr) {
+    const mbf::Geom gm = step_geom(h);
+    const int rc = self_tables<T>(h, gm);
+    if (rc) return rc;
     mbf::SimView<T> v = view<T>(h);
+    v.n_part = gm.nblk;
     if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
-    if (h->tun.variant == MBF_VARIANT_FUSED) {
-        launch_fused<T>(h, v);
-        if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-    } else {
-        const mbf::Geom gm = step_geom(h);
-        const dim3 g((unsigned)gm.nblk);
-        v.n_part = gm.nblk;
-        switch (h->tun.tile_y) {
-            case 2:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 2>), g, dim3(64, 2), 0, h->stream, v, gm);
-                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 2>), g, dim3(64, 2), 0, h->stream, v, gm);
-                break;
-            case 4:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 4>), g, dim3(64, 4), 0, h->stream, v, gm);
-                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 4>), g, dim3(64, 4), 0, h->stream, v, gm);
-                break;
-            case 16:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 16>), g, dim3(64, 16), 0, h->stream, v, gm);
-                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 16>), g, dim3(64, 16), 0, h->stream, v, gm);
-                break;
-            default:
-                hipLaunchKernelGGL((mbf::k_curl_h<T, 8>), g, dim3(64, 8), 0, h->stream, v, gm);
-                if (evm) HIPCHK(h, hipEventRecord(evm, h->stream));
-                hipLaunchKernelGGL((mbf::k_curl_e<T, 8>), g, dim3(64, 8), 0, h->stream, v, gm);
-                break;
-        }
-    }
+    HIPCHK(h, (launch_fields<T>(h->stream, h->tun, reinterpret_cast<const mbf::SimView<T>*>(h->d_view),
+                                h->d_geom, h->d_items, gm.nblk, evm)));
     if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
     if (h->mur_tasks > 0) {
         const int nmax = std::max({h->cfg.nx, h->cfg.ny, h->cfg.nz}) + 1;
         const int64_t sites = (int64_t)nmax * nmax;
-        dim3 gm((unsigned)((sites + 255) / 256), (unsigned)h->mur_tasks, 1);
-        hipLaunchKernelGGL(mbf::k_mur<T>, gm, dim3(256), 0, h->stream, v);
+        dim3 gmur((unsigned)((sites + 255) / 256), (unsigned)h->mur_tasks, 1);
+        hipLaunchKernelGGL(mbf::k_mur<T>, gmur, dim3(256), 0, h->stream, v);
     }
     hipLaunchKernelGGL(mbf::k_end_step<T>, dim3(1), dim3(mbf::kEndThreads), 0, h->stream, v);
     HIPCHK(h, hipGetLastError());
@@ -364,6 +460,8 @@ void drop_graph(mbf_handle* h) {
 // Capture `n` steps (plus the DFT fold when probes are set and n == decim).
 int build_graph(mbf_handle* h, int64_t n) {
     drop_graph(h);
+    const int rc0 = prepare_tables(h);
+    if (rc0) return rc0;
     hipGraph_t g = nullptr;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
     int rc = MBF_OK;
@@ -705,6 +803,7 @@ void mbf_destroy(mbf_handle* h) {
     hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
     hipFree(h->mat); hipFree(h->lut);
     hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
+    hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
 }
@@ -1418,42 +1517,6 @@ void batch_free_tables(mbf_batch* b) {
     b->tables = false;
 }
 
-// Reorder the work-table entries [i0, i1) (member by member, items in order)
-// into dispatch order.  remap 0: as they are; 1: XCD x takes the x-th
-// contiguous range; 2: whole z-segment layers (all tiles of one segment of
-// one member) are dealt to the XCDs in turn, and an XCD whose layers run out
-// takes the remaining entries of the others.
-void dispatch_order(std::vector<uint32_t>& items, int i0, int i1, const std::vector<mbf::Geom>& geoms, int remap) {
-    const int n = i1 - i0;
-    if (remap == 0 || n == 0) return;
-    std::vector<uint32_t> src(items.begin() + i0, items.begin() + i1), out((size_t)n);
-    if (remap == 1) {
-        const int q = n >> 3, r = n & 7;
-        for (int bb = 0; bb < n; ++bb) {
-            const int x = bb & 7, idx = bb >> 3;
-            out[(size_t)bb] = src[(size_t)(x * q + std::min(x, r) + idx)];
-        }
-    } else {
-        std::vector<std::vector<uint32_t>> queue(8);
-        int layer = 0;
-        for (int e = 0; e < n;) {
-            const int r = (int)(src[(size_t)e] >> 24);
-            const int Q = geoms[(size_t)r].tiles_x * geoms[(size_t)r].tiles_y;
-            const int len = std::min(Q, n - e);
-            for (int t = 0; t < len; ++t) queue[(size_t)(layer & 7)].push_back(src[(size_t)(e + t)]);
-            e += len;
-            ++layer;
-        }
-        std::vector<size_t> head(8, 0);
-        for (int bb = 0; bb < n; ++bb) {
-            int x = bb & 7;
-            for (int t = 0; t < 8 && head[(size_t)x] == queue[(size_t)x].size(); ++t) x = (x + 1) & 7;
-            out[(size_t)bb] = queue[(size_t)x][head[(size_t)x]++];
-        }
-    }
-    std::copy(out.begin(), out.end(), items.begin() + i0);
-}
-
 // Rebuild the device views, geometries and work table when a member changed.
 template <typename T>
 int batch_tables(mbf_batch* b) {
@@ -1526,42 +1589,10 @@ int batch_launch_step(mbf_batch* b, int gi, hipEvent_t ev0 = nullptr, hipEvent_t
     const mbf::SimView<T>* vw = reinterpret_cast<const mbf::SimView<T>*>(b->d_views);
     const mbf::Geom* gw = b->d_geoms;
     const uint32_t* it = b->d_items + gr.i0;
-    const int ni = gr.i1 - gr.i0, rm = b->tun.xcd_remap;
-    const dim3 g((unsigned)ni);
+    const int ni = gr.i1 - gr.i0;
     hipStream_t st = b->stream;
     if (ev0) BHIPCHK(b, hipEventRecord(ev0, st));
-    if (b->tun.variant == MBF_VARIANT_FUSED) {
-        switch (b->tun.tile_y) {
-            case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
-            case 4: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm); break;
-            case 16: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm); break;
-            default: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm); break;
-        }
-        if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-    } else {
-        switch (b->tun.tile_y) {
-            case 2:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
-                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
-                break;
-            case 4:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
-                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
-                break;
-            case 16:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
-                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
-                break;
-            default:
-                hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
-                if (evm) BHIPCHK(b, hipEventRecord(evm, st));
-                hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
-                break;
-        }
-    }
+    BHIPCHK(b, (launch_fields<T>(st, b->tun, vw, gw, it, ni, evm)));
     if (ev1) BHIPCHK(b, hipEventRecord(ev1, st));
     const mbf::SimView<T>* views = reinterpret_cast<const mbf::SimView<T>*>(b->d_views) + gr.r0;
     const unsigned nm = (unsigned)(gr.r1 - gr.r0);

@@ -294,27 +294,15 @@ struct Geom {
 // Workgroups are dealt to the 8 XCDs in turn (id mod 8); with remapping, XCD
 // x takes the x-th contiguous range of work items instead, so neighbouring
 // items (the next tile in x or y, whose halo rows and Bloch-array lines they
-// share) meet in the same L2.
+// share) meet in the same L2.  The reverse-step kernels map their workgroups
+// this way; the step kernels read a work table the host writes in dispatch
+// order.
 __device__ __forceinline__ int xcd_work_item(int b, int nblk, int remap) {
     if (!remap) return b;
     remap = 1;
     const int q = nblk >> 3, r = nblk & 7;
     const int x = b & 7, idx = b >> 3;
     return x * q + (x < r ? x : r) + idx;
-}
-
-// Work item of this workgroup.  xcd_remap = 2 deals whole z-segment layers
-// (every x, y tile of one segment) to the XCDs in turn instead, so the eight
-// XCDs work in one window of consecutive segments while each layer's tiles
-// share one L2 (when the segment count is a multiple of 8).
-__device__ __forceinline__ int work_item(const Geom& g) {
-    const int b = (int)blockIdx.x;
-    if (g.xcd_remap == 2 && (g.segs & 7) == 0) {
-        const int Q = g.tiles_x * g.tiles_y;
-        const int x = b & 7, s = b >> 3;
-        return (x + 8 * (s / Q)) * Q + s % Q;
-    }
-    return xcd_work_item(b, g.nblk, g.xcd_remap);
 }
 
 // Work item -> (x tile, y tile, z segment), x tile fastest (memory order).
@@ -383,7 +371,6 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
     if (i < v.nx && j < v.ny) {
         const T* __restrict__ Ex = f.e[0];
         const T* __restrict__ Ey = f.e[1];
-        const T* __restrict__ Ez = f.e[2];
         const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
         uint32_t x = (uint32_t)i + sx * (uint32_t)j + sxy * (uint32_t)kz0;
         // E^n at plane k is carried from the previous plane's k+1 loads; the
@@ -429,11 +416,6 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
     }
     const double s = block_sum((double)wsum, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0) sto(v.e_part, (uint32_t)w, s);
-}
-
-template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_h(SimView<T> v, Geom gm) {
-    curl_h_body<T, TY>(v, gm, work_item(gm));
 }
 
 // The tables are separate no-alias read-only arguments, so the compiler may
@@ -646,11 +628,6 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
     }
 }
 
-template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_curl_e(SimView<T> v, Geom gm) {
-    curl_e_body<T, TY>(v, gm, work_item(gm));
-}
-
 // The tables are separate no-alias read-only arguments, so the compiler may
 // keep the member's view in scalar registers across the kernel's stores.
 template <typename T, int TY>
@@ -829,11 +806,6 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
         sto(v.e_part, (uint32_t)w, ws);
         if (v.box_on) sto(v.l_part, (uint32_t)w, ls);
     }
-}
-
-template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_step_fused(SimView<T> v, Geom gm) {
-    step_fused_body<T, TY>(v, gm, work_item(gm));
 }
 
 // The tables are separate no-alias read-only arguments, so the compiler may
