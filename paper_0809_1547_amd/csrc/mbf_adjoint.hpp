@@ -111,16 +111,61 @@ __global__ void __launch_bounds__(64 * TY) k_adj_h(AdjView<T> v, Geom gm) {
     }
 }
 
-// vh = db htot at H-site (c; i,j,k) of [0,n)^3.
+// Everything the E part reads for one plane of a row: htot at the cell's own
+// H-sites and at the y-1 and x-1 neighbours its curl- needs (z-1 is carried
+// from the previous plane), u, E^n and E^{n+1} of the three E-sites, the
+// Bloch trajectory and adjoint state of the gain sites, and the cell's eps
+// gradient so far.  Loaded ahead of the plane's stores (the arrays may share
+// no memory, but the compiler cannot know that through the view).
 template <typename T>
-__device__ __forceinline__ T adj_vh(const AdjView<T>& v, int c, int i, int j, int k) {
-    const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
-    T db = (T)1;
-    if (v.has_layer) db = recip((T)1 + adj_loss_h(v, c, i, j, k));
-    return db * ldo(v.hb[c], x);
+struct AdjPlane {
+    T hx, hy, hz, hz_y, hx_y, hz_x, hy_x;
+    T u[3], E[3], En[3];
+    T dPf[3], dN[3], n1[3], n2[3], n3[3], lp[3], lq[3], dPp[3];
+    double ge;
+};
+
+// Lanes past the grid read column nx and cell 0 (valid sites; their values
+// are not used); the y-1 and x-1 neighbours only exist for j >= 1 and i >= 1
+// (the offsets would wrap below zero otherwise).
+template <typename T>
+__device__ __forceinline__ void adj_load_plane(AdjPlane<T>& p, const AdjView<T>& v, uint32_t x, uint32_t cell,
+                                               uint32_t gi, bool g, int i, int j, int k) {
+    const uint32_t sx = (uint32_t)v.sx;
+    p.hx = ldo(v.hb[0], x); p.hy = ldo(v.hb[1], x); p.hz = ldo(v.hb[2], x);
+    p.hz_y = j >= 1 ? ldo(v.hb[2], x - sx) : (T)0;
+    p.hx_y = j >= 1 ? ldo(v.hb[0], x - sx) : (T)0;
+    p.hz_x = i >= 1 ? ldo(v.hb[2], x - 1u) : (T)0;
+    p.hy_x = i >= 1 ? ldo(v.hb[1], x - 1u) : (T)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p.u[c] = ldo(v.u[c], x);
+        p.E[c] = ldo(v.E0[c], x);
+        p.En[c] = ldo(v.E1[c], x);
+        const bool gs = g && e_in(v, c, i, j, k);
+        p.dPf[c] = gs ? ldo(v.dP1[c], gi) : (T)0;
+        p.dN[c] = gs ? ldo(v.dN[c], gi) : (T)0;
+        p.n1[c] = gs ? ldo(v.ln[0][c], gi) : (T)0;
+        p.n2[c] = gs ? ldo(v.ln[1][c], gi) : (T)0;
+        p.n3[c] = gs ? ldo(v.ln[2][c], gi) : (T)0;
+        p.lp[c] = gs ? ldo(v.lp[c], gi) : (T)0;
+        p.lq[c] = gs ? ldo(v.lq[c], gi) : (T)0;
+        p.dPp[c] = gs ? ldo(v.dP0[c], gi) : (T)0;
+    }
+    p.ge = gld(v.g_eps + cell);
 }
 
-// E part with the Bloch terms, the parameter terms and the loss term.
+// db htot at H-site c of (i, j, k) from its loaded htot.
+template <typename T>
+__device__ __forceinline__ T adj_db(const AdjView<T>& v, int c, int i, int j, int k, T hb) {
+    T db = (T)1;
+    if (v.has_layer) db = recip((T)1 + adj_loss_h(v, c, i, j, k));
+    return db * hb;
+}
+
+// E part with the Bloch terms, the parameter terms and the loss term.  Each
+// wave owns one row and marches along z (htot of Hx, Hy at k-1 stays in
+// registers); a plane's loads all go out before its arithmetic and stores.
 template <typename T, int TY>
 __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
     __shared__ double sh[TY];
@@ -133,69 +178,95 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
     double gna = 0.0;
     if (j < v.ny) {
         const bool act = i < v.nx;
-        for (int k = kz0; k < kz1; ++k) {
-            const uint32_t x = (uint32_t)(act ? i : 0) + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
-            const uint8_t m = ldo(v.mat, x);
-            const bool g = act && m >= kGainId;
-            const uint32_t gi = gain_index(v, bx, j, k, g, true);
-            if (!act) continue;
-            const T ie = gld(v.lut_inv_eps + m);
-            double geps = 0.0;
-            T xi[3] = {(T)0, (T)0, (T)0};
-            if (g && v.noise) noise3(v, (uint32_t)(i + v.nx * (j + v.ny * k)), (uint32_t)v.n, xi);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (!e_in(v, c, i, j, k)) continue;
-                T curl;
-                if (c == 0)
-                    curl = (adj_vh(v, 2, i, j, k) - adj_vh(v, 2, i, j - 1, k)) - (adj_vh(v, 1, i, j, k) - adj_vh(v, 1, i, j, k - 1));
-                else if (c == 1)
-                    curl = (adj_vh(v, 0, i, j, k) - adj_vh(v, 0, i, j, k - 1)) - (adj_vh(v, 2, i, j, k) - adj_vh(v, 2, i - 1, j, k));
-                else
-                    curl = (adj_vh(v, 1, i, j, k) - adj_vh(v, 1, i - 1, j, k)) - (adj_vh(v, 0, i, j, k) - adj_vh(v, 0, i, j - 1, k));
-                T ca = (T)1, cb = (T)1;
-                if (v.has_layer) {
-                    const T a = adj_loss_e(v, c, i, j, k);
-                    cb = recip((T)1 + a);
-                    ca = ((T)1 - a) * cb;
-                }
-                const T et = ldo(v.u[c], x) / (cb * ie);
-                const T E = ldo(v.E0[c], x), En = ldo(v.E1[c], x);
-                T lam = ca * et - v.S * curl;
-                T Wh_prev = (T)0, dP_prev = (T)0;
-                if (g) {
-                    const T dPf = ldo(v.dP1[c], gi);
-                    const T dN = ldo(v.dN[c], gi);
-                    const T n1 = ldo(v.ln[0][c], gi), n2 = ldo(v.ln[1][c], gi), n3 = ldo(v.ln[2][c], gi);
-                    const T Wh = n2 - n1;
-                    const T dPh = Wh * v.beta * (T)0.5 * (En + E) - cb * ie * et;
-                    const T pn = ldo(v.lp[c], gi) + dPh;
-                    lam += v.ck * dN * pn + Wh * v.beta * (T)0.5 * dPf;
-                    sto(v.lp[c], gi, ldo(v.lq[c], gi) + v.a * pn - dPh);
-                    sto(v.lq[c], gi, v.b * pn);
-                    const T m1 = n1 * ((T)1 - v.dt10) - n3 * v.dtWp + v.ck * E * pn;
-                    const T m2 = n2 * ((T)1 - v.dt21) + n1 * v.dt21 - n3 * v.dtWp - v.ck * E * pn;
-                    const T m3 = n3 * ((T)1 - v.dt32 - v.dtWp) + n2 * v.dt32;
-                    sto(v.ln[0][c], gi, m1);
-                    sto(v.ln[1][c], gi, m2);
-                    sto(v.ln[2][c], gi, m3);
-                    gna += (double)(n3 * v.dtWp) + (double)(v.ck_esp * xi[c] * pn);
-                    Wh_prev = m2 - m1;
-                    dP_prev = ldo(v.dP0[c], gi);
-                }
-                // E^{n+1} = ca E^n + cb ie (S curl- H' - dP) + src: its eps derivative
-                const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? v.src : (T)0;
-                geps += (double)et * (double)((En - ca * E) - s) * (double)(-ie);
-                // loss term of E^n and the work term of step n-1
-                if (v.n >= 1) {
-                    if (i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5])
-                        lam += (T)2 * E;
-                    lam += Wh_prev * v.beta * (T)0.5 * dP_prev;
-                }
-                sto(v.u[c], x, cb * ie * lam);
+        const uint32_t sxy = (uint32_t)v.sxy;
+        const uint32_t pcell = (uint32_t)v.nx * (uint32_t)v.ny;
+        uint32_t x = (uint32_t)(act ? i : v.nx) + (uint32_t)v.sx * (uint32_t)j + sxy * (uint32_t)kz0;
+        uint32_t cell = (uint32_t)(act ? i : 0) + (uint32_t)v.nx * ((uint32_t)j + (uint32_t)v.ny * (uint32_t)kz0);
+        uint8_t m = ldo(v.mat, x);
+        uint32_t gi = gain_index(v, bx, j, kz0, act && m >= kGainId, true);
+        uint8_t m_n = (kz0 + 1 < kz1) ? ldo(v.mat, x + sxy) : (uint8_t)0;
+        // db htot of Hx, Hy at plane k-1, carried along z
+        T vhx_z = (T)0, vhy_z = (T)0;
+        if (act && kz0 >= 1) {
+            vhx_z = adj_db(v, 0, i, j, kz0 - 1, ldo(v.hb[0], x - sxy));
+            vhy_z = adj_db(v, 1, i, j, kz0 - 1, ldo(v.hb[1], x - sxy));
+        }
+        for (int k = kz0; k < kz1; ++k, x += sxy, cell += pcell) {
+            AdjPlane<T> P;
+            adj_load_plane(P, v, x, cell, gi, act && m >= kGainId, i, j, k);
+            uint32_t gi_n = 0;
+            uint8_t m_nn = 0;
+            if (k + 1 < kz1) {
+                gi_n = gain_index(v, bx, j, k + 1, act && m_n >= kGainId, true);
+                if (k + 2 < kz1) m_nn = ldo(v.mat, x + 2u * sxy);
             }
-            const uint32_t cell = (uint32_t)i + (uint32_t)v.nx * ((uint32_t)j + (uint32_t)v.ny * (uint32_t)k);
-            sto(v.g_eps, cell, gld(v.g_eps + cell) + geps);
+            const bool g = act && m >= kGainId;
+            const T vhx = adj_db(v, 0, i, j, k, P.hx);
+            const T vhy = adj_db(v, 1, i, j, k, P.hy);
+            if (act) {
+                const T vhz = adj_db(v, 2, i, j, k, P.hz);
+                const T ie = gld(v.lut_inv_eps + m);
+                double geps = 0.0;
+                T xi[3] = {(T)0, (T)0, (T)0};
+                if (g && v.noise) noise3(v, cell, (uint32_t)v.n, xi);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!e_in(v, c, i, j, k)) continue;
+                    T curl;
+                    if (c == 0)
+                        curl = (vhz - adj_db(v, 2, i, j - 1, k, P.hz_y)) - (vhy - vhy_z);
+                    else if (c == 1)
+                        curl = (vhx - vhx_z) - (vhz - adj_db(v, 2, i - 1, j, k, P.hz_x));
+                    else
+                        curl = (vhy - adj_db(v, 1, i - 1, j, k, P.hy_x)) - (vhx - adj_db(v, 0, i, j - 1, k, P.hx_y));
+                    T ca = (T)1, cb = (T)1;
+                    if (v.has_layer) {
+                        const T a = adj_loss_e(v, c, i, j, k);
+                        cb = recip((T)1 + a);
+                        ca = ((T)1 - a) * cb;
+                    }
+                    const T et = P.u[c] / (cb * ie);
+                    const T E = P.E[c], En = P.En[c];
+                    T lam = ca * et - v.S * curl;
+                    T Wh_prev = (T)0, dP_prev = (T)0;
+                    if (g) {
+                        const T dPf = P.dPf[c];
+                        const T dN = P.dN[c];
+                        const T n1 = P.n1[c], n2 = P.n2[c], n3 = P.n3[c];
+                        const T Wh = n2 - n1;
+                        const T dPh = Wh * v.beta * (T)0.5 * (En + E) - cb * ie * et;
+                        const T pn = P.lp[c] + dPh;
+                        lam += v.ck * dN * pn + Wh * v.beta * (T)0.5 * dPf;
+                        sto(v.lp[c], gi, P.lq[c] + v.a * pn - dPh);
+                        sto(v.lq[c], gi, v.b * pn);
+                        const T m1 = n1 * ((T)1 - v.dt10) - n3 * v.dtWp + v.ck * E * pn;
+                        const T m2 = n2 * ((T)1 - v.dt21) + n1 * v.dt21 - n3 * v.dtWp - v.ck * E * pn;
+                        const T m3 = n3 * ((T)1 - v.dt32 - v.dtWp) + n2 * v.dt32;
+                        sto(v.ln[0][c], gi, m1);
+                        sto(v.ln[1][c], gi, m2);
+                        sto(v.ln[2][c], gi, m3);
+                        gna += (double)(n3 * v.dtWp) + (double)(v.ck_esp * xi[c] * pn);
+                        Wh_prev = m2 - m1;
+                        dP_prev = P.dPp[c];
+                    }
+                    // E^{n+1} = ca E^n + cb ie (S curl- H' - dP) + src: its eps derivative
+                    const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? v.src : (T)0;
+                    geps += (double)et * (double)((En - ca * E) - s) * (double)(-ie);
+                    // loss term of E^n and the work term of step n-1
+                    if (v.n >= 1) {
+                        if (i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5])
+                            lam += (T)2 * E;
+                        lam += Wh_prev * v.beta * (T)0.5 * dP_prev;
+                    }
+                    sto(v.u[c], x, cb * ie * lam);
+                }
+                sto(v.g_eps, cell, P.ge + geps);
+            }
+            vhx_z = vhx;
+            vhy_z = vhy;
+            m = m_n;
+            m_n = m_nn;
+            gi = gi_n;
         }
     }
     const double s = block_sum(gna, sh);
