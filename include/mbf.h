@@ -220,6 +220,50 @@ int mbf_read_spectrum(mbf_handle* h, double* re_im);
 /* Loss-box integral. */
 int mbf_read_loss(mbf_handle* h, double* out);
 
+/* ------------------------------------------------------ spectral statistics
+ * Peak and width of an emission spectrum (Results section: the linewidth of
+ * the Maxwell-Bloch spectra comes from a Gaussian fit, Fig. 5b; the width of
+ * the measured spectra is their standard deviation, Fig. 4).  From complex
+ * probe amplitudes F[p][k] (the running DFT of mbf_set_probes):
+ *   S_k = sum_p |F[p][k]|^2 (probes added in index order, FP64);
+ *   peak_bin = the first k holding the largest S_k (-1 when S is all zero);
+ *   mean_omega, std_omega = first moment and standard deviation of omega
+ *   under the weight S;
+ *   fit_lo..fit_hi = the run of bins around the peak with S_k >= level *
+ *   S_peak; over it a weighted least-squares parabola
+ *   ln(S_k / S_peak) = a + b x + c x^2, weights (S_k / S_peak)^2,
+ *   x = (omega_k - omega_peak) / s with s the mean bin spacing in the run,
+ *   gives the Gaussian fit_amplitude * exp(-(omega - fit_center)^2 /
+ *   (2 fit_sigma^2)); fit_ok = 1 when the run has at least 3 bins and c < 0
+ *   (fit_* are 0 otherwise).  Frequencies in rad/s. */
+typedef struct {
+    double total;          /* sum_k S_k */
+    double peak_omega;     /* omega[peak_bin] */
+    double peak_value;     /* S at the peak */
+    double mean_omega;
+    double std_omega;
+    double fit_center;
+    double fit_sigma;
+    double fit_amplitude;
+    int32_t peak_bin;
+    int32_t fit_lo, fit_hi;
+    int32_t fit_ok;
+} mbf_spec_stats;
+
+/* Statistics of the handle's probe spectra (pending DFT work is flushed
+ * first); runs on the handle's stream and synchronises.  0 < level < 1
+ * (MBF_EINVAL otherwise); MBF_ESTATE without probes. */
+int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out);
+
+/* The same statistics of caller data: spec[2 * n_probes * n_freq] (probe-
+ * major, interleaved re, im) and omega[n_freq], both host or both device
+ * memory per mem_kind (caller-owned, unchanged).  Runs on `stream` (NULL: the
+ * null stream) in device memory it allocates and frees; returns when *out
+ * holds the result.  n_probes >= 1, n_freq >= 1, 0 < level < 1 (MBF_EINVAL
+ * otherwise). */
+int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
+                       int mem_kind, void* stream, mbf_spec_stats* out);
+
 /* Copy one site array out of / into the device state (see field ids), in the
  * packed layout of (nx+1)*(ny+1)*(nz+1) values, x fastest; dst/src are host
  * or device memory per mem_kind, owned by the caller.  Reading P gives P^n,
@@ -349,6 +393,9 @@ int mbf_batch_step_bytes(const mbf_batch* b, double* bytes /* [3] */);
  * best grouping, then the other groupings (32, 64, 128) for the best
  * schedule; the result applies to the batch and every member. */
 int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen);
+/* mbf_spectrum_stats of every member: out[R], member order (the linewidth
+ * and peak against the members' pump levels). */
+int mbf_batch_spectrum_stats(mbf_batch* b, double level, mbf_spec_stats* out);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@
 #include "../../include/mbf.h"
 #include "mbf_kernels.hpp"
 #include "mbf_adjoint.hpp"
+#include "mbf_spectra.hpp"
 
 namespace {
 
@@ -1257,6 +1258,73 @@ int mbf_read_spectrum(mbf_handle* h, double* re_im) {
     return MBF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Statistics of np x nf device amplitudes on stream st; the power-spectrum
+// scratch and the result live in device memory allocated here.
+int spec_stats_device(mbf_handle* h, const double* dspec, int np, int nf, const double* domega, double level,
+                      hipStream_t st, mbf_spec_stats* out) {
+    double* pw = nullptr;
+    mbf_spec_stats* dout = nullptr;
+    struct Free {
+        double*& pw;
+        mbf_spec_stats*& dout;
+        ~Free() { hipFree(pw); hipFree(dout); }
+    } fr{pw, dout};
+    if (hipMalloc(&pw, sizeof(double) * (size_t)nf) != hipSuccess ||
+        hipMalloc(&dout, sizeof(mbf_spec_stats)) != hipSuccess)
+        return fail(h, MBF_ENOMEM, "device allocation for the spectral statistics failed");
+    hipLaunchKernelGGL(mbf::k_spec_stats, dim3(1), dim3(mbf::kStatThreads), 0, st, dspec, np, nf, domega, level,
+                       pw, dout);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(out, dout, sizeof(mbf_spec_stats), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    return MBF_OK;
+}
+
+bool stat_level_ok(double level) { return std::isfinite(level) && level > 0.0 && level < 1.0; }
+
+}  // namespace
+
+extern "C" {
+
+int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out) {
+    if (!h || !out) return fail(h, MBF_EINVAL, "null argument");
+    if (!stat_level_ok(level)) return fail(h, MBF_EINVAL, "level must lie in (0, 1)");
+    if (h->n_probes == 0 || h->n_freq == 0) return fail(h, MBF_ESTATE, "no probes or frequencies set");
+    const int64_t pending = h->step - h->flushed;
+    if (pending > 0) {
+        int rc = dispatch_dft(h, (int)pending);
+        if (rc) return rc;
+        h->flushed = h->step;
+    }
+    return spec_stats_device(h, h->d_spec, h->n_probes, h->n_freq, h->d_omega, level, h->stream, out);
+}
+
+int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
+                       int mem_kind, void* stream, mbf_spec_stats* out) {
+    if (!spec || !omega || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n_probes < 1 || n_freq < 1) return fail(nullptr, MBF_EINVAL, "n_probes and n_freq must be >= 1");
+    if (!stat_level_ok(level)) return fail(nullptr, MBF_EINVAL, "level must lie in (0, 1)");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    hipStream_t st = (hipStream_t)stream;
+    if (mem_kind == MBF_MEM_DEVICE) return spec_stats_device(nullptr, spec, n_probes, n_freq, omega, level, st, out);
+    const size_t ns = sizeof(double) * 2 * (size_t)n_probes * (size_t)n_freq, no = sizeof(double) * (size_t)n_freq;
+    double *ds = nullptr, *dw = nullptr;
+    struct Free {
+        double*& a;
+        double*& b;
+        ~Free() { hipFree(a); hipFree(b); }
+    } fr{ds, dw};
+    if (hipMalloc(&ds, ns) != hipSuccess || hipMalloc(&dw, no) != hipSuccess)
+        return fail(nullptr, MBF_ENOMEM, "device allocation for the spectral statistics failed");
+    HIPCHK(nullptr, hipMemcpy(ds, spec, ns, hipMemcpyHostToDevice));
+    HIPCHK(nullptr, hipMemcpy(dw, omega, no, hipMemcpyHostToDevice));
+    return spec_stats_device(nullptr, ds, n_probes, n_freq, dw, level, st, out);
+}
+
 int mbf_read_loss(mbf_handle* h, double* out) {
     if (!h || !out) return fail(h, MBF_EINVAL, "null argument");
     mbf::Ctl c{};
@@ -1819,6 +1887,16 @@ int mbf_batch_step_timed(mbf_batch* b, int64_t nsteps, double* kernel_ms, int64_
     kernel_ms[1] = t1;
     *launches = nsteps;
     return rc;
+}
+
+int mbf_batch_spectrum_stats(mbf_batch* b, double level, mbf_spec_stats* out) {
+    if (!b || !out) return bfail(b, MBF_EINVAL, "null argument");
+    for (size_t r = 0; r < b->m.size(); ++r) {
+        mbf_handle* h = b->m[r];
+        const int rc = mbf_spectrum_stats(h, level, out + r);
+        if (rc) return bfail(b, rc, "member " + std::to_string(r) + ": " + h->err);
+    }
+    return MBF_OK;
 }
 
 int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {

@@ -1,0 +1,159 @@
+// Spectral statistics of the emission spectra: the probe-summed power
+// spectrum, its peak, its standard deviation and a Gaussian fit around the
+// peak (the linewidth the Results section reads off the Maxwell-Bloch spectra
+// by a Gaussian fit, Fig. 5b; the width of the experimental spectra is their
+// standard deviation, Fig. 4).
+//
+//   S_k        = sum_p |F_{p,k}|^2                (probes summed in order)
+//   peak       = argmax_k S_k                     (lowest k among equal maxima)
+//   mean, std  = first moment and standard deviation of omega under S
+//   fit window = the run of bins around the peak with S_k >= level * S_peak
+//   fit        = weighted least-squares parabola ln(S_k / S_peak) = a + b x + c x^2
+//                over the window, weights (S_k / S_peak)^2, x = (omega_k - omega_peak) / s,
+//                s the mean bin spacing inside the window; a Gaussian has
+//                c = -1/(2 sigma_x^2), centre x0 = -b/(2c), amplitude S_peak exp(a - b^2/(4c)).
+#pragma once
+
+#include "mbf_kernels.hpp"
+
+namespace mbf {
+
+constexpr int kStatThreads = 256;
+
+// Sum over the workgroup in a fixed order, returned to every thread.
+__device__ __forceinline__ double stat_sum(double x, double* sh) {
+    const int t = (int)threadIdx.x;
+    x = wave_sum(x);
+    __syncthreads();                                  // earlier readers of sh are done
+    if ((t & 63) == 0) sh[t >> 6] = x;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kStatThreads / 64; ++w) r += sh[w];
+    return r;
+}
+
+// (value, bin) maximum with the lowest bin among equal values.
+__device__ __forceinline__ void stat_max(double& v, int& k, double v2, int k2) {
+    if (v2 > v || (v2 == v && k2 < k)) {
+        v = v2;
+        k = k2;
+    }
+}
+
+// One workgroup per spectrum: spec holds np x nf complex values (re, im
+// interleaved, probe-major), pw receives S (nf values), out the statistics.
+__global__ void __launch_bounds__(kStatThreads) k_spec_stats(const double* __restrict__ spec, int np, int nf,
+                                                            const double* __restrict__ omega, double level,
+                                                            double* __restrict__ pw, mbf_spec_stats* out) {
+    __shared__ double sh[kStatThreads / 64];
+    __shared__ double shv[kStatThreads / 64];
+    __shared__ int shk[kStatThreads / 64];
+    __shared__ int win[2];
+    const int t = (int)threadIdx.x;
+    // ---- power spectrum, total, peak
+    double tot = 0.0, best = -1.0;
+    int bk = nf;
+    for (int k = t; k < nf; k += kStatThreads) {
+        double s = 0.0;
+        for (int p = 0; p < np; ++p) {
+            const int64_t q = 2 * ((int64_t)p * nf + k);
+            const double re = spec[q], im = spec[q + 1];
+            s += re * re + im * im;
+        }
+        pw[k] = s;
+        tot += s;
+        stat_max(best, bk, s, k);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(best, o, 64);
+        const int k2 = __shfl_xor(bk, o, 64);
+        stat_max(best, bk, v2, k2);
+    }
+    if ((t & 63) == 0) {
+        shv[t >> 6] = best;
+        shk[t >> 6] = bk;
+    }
+    const double total = stat_sum(tot, sh);           // its barriers also publish shv, shk and pw
+    double peak = shv[0];
+    int kp = shk[0];
+    for (int w = 1; w < kStatThreads / 64; ++w) stat_max(peak, kp, shv[w], shk[w]);
+    // ---- moments of omega under S
+    double m1 = 0.0;
+    for (int k = t; k < nf; k += kStatThreads) m1 += pw[k] * omega[k];
+    const double mean = total > 0.0 ? stat_sum(m1, sh) / total : 0.0;
+    double m2 = 0.0;
+    for (int k = t; k < nf; k += kStatThreads) {
+        const double d = omega[k] - mean;
+        m2 += pw[k] * (d * d);
+    }
+    const double var = total > 0.0 ? stat_sum(m2, sh) / total : 0.0;
+    // ---- fit window: the run around the peak above level * peak
+    const double thr = level * peak;
+    if (t == 0) {
+        int lo = kp, hi = kp;
+        if (total > 0.0) {
+            while (lo > 0 && pw[lo - 1] >= thr) --lo;
+            while (hi < nf - 1 && pw[hi + 1] >= thr) ++hi;
+        }
+        win[0] = lo;
+        win[1] = hi;
+    }
+    __syncthreads();
+    const int lo = win[0], hi = win[1];
+    const bool can_fit = total > 0.0 && hi - lo >= 2 && omega[hi] != omega[lo];
+    const double wp = can_fit ? omega[kp] : 0.0;
+    const double s = can_fit ? (omega[hi] - omega[lo]) / (double)(hi - lo) : 1.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    if (can_fit) {
+        for (int k = lo + t; k <= hi; k += kStatThreads) {
+            const double x = (omega[k] - wp) / s;
+            const double u = pw[k] / peak;
+            const double w = u * u, y = log(u);
+            const double x2 = x * x;
+            a0 += w;
+            a1 += w * x;
+            a2 += w * x2;
+            a3 += w * (x2 * x);
+            a4 += w * (x2 * x2);
+            r0 += w * y;
+            r1 += w * (x * y);
+            r2 += w * (x2 * y);
+        }
+        a0 = stat_sum(a0, sh); a1 = stat_sum(a1, sh); a2 = stat_sum(a2, sh);
+        a3 = stat_sum(a3, sh); a4 = stat_sum(a4, sh);
+        r0 = stat_sum(r0, sh); r1 = stat_sum(r1, sh); r2 = stat_sum(r2, sh);
+    }
+    if (t != 0) return;
+    mbf_spec_stats o{};
+    o.total = total;
+    o.peak_bin = total > 0.0 ? kp : -1;
+    o.peak_omega = total > 0.0 ? omega[kp] : 0.0;
+    o.peak_value = total > 0.0 ? peak : 0.0;
+    o.mean_omega = mean;
+    o.std_omega = sqrt(var);
+    o.fit_lo = total > 0.0 ? lo : -1;
+    o.fit_hi = total > 0.0 ? hi : -1;
+    o.fit_ok = 0;
+    o.fit_center = o.fit_sigma = o.fit_amplitude = 0.0;
+    if (can_fit) {
+        // normal equations of the weighted parabola, by Cramer's rule
+        const double d = a0 * (a2 * a4 - a3 * a3) - a1 * (a1 * a4 - a2 * a3) + a2 * (a1 * a3 - a2 * a2);
+        const double da = r0 * (a2 * a4 - a3 * a3) - a1 * (r1 * a4 - a3 * r2) + a2 * (r1 * a3 - a2 * r2);
+        const double db = a0 * (r1 * a4 - a3 * r2) - r0 * (a1 * a4 - a2 * a3) + a2 * (a1 * r2 - r1 * a2);
+        const double dc = a0 * (a2 * r2 - r1 * a3) - a1 * (a1 * r2 - r1 * a2) + r0 * (a1 * a3 - a2 * a2);
+        if (d != 0.0) {
+            const double a = da / d, b = db / d, c = dc / d;
+            if (c < 0.0) {
+                o.fit_ok = 1;
+                o.fit_center = wp + s * (-b / (2.0 * c));
+                o.fit_sigma = fabs(s) * sqrt(-1.0 / (2.0 * c));
+                o.fit_amplitude = peak * exp(a - b * b / (4.0 * c));
+            }
+        }
+    }
+    *out = o;
+}
+
+}  // namespace mbf

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -318,3 +318,27 @@ def batch_pump_levels(count: int, n_th: float) -> List[float]:
     """Pump densities of the batched workload: level p = r mod 8 at
     0.5 * 8**(p/7) times threshold (8 log-spaced levels, 0.5x to 4x)."""
     return [0.5 * 8.0 ** ((r % 8) / 7.0) * n_th for r in range(count)]
+
+
+def synthetic_spectra(n_probes: int, n_freq: int, *, seed: int,
+                      lines: Sequence[Tuple[float, float, float]] = ((0.45, 0.03, 1.0),),
+                      noise: float = 0.02, lam_min: float = 450e-9,
+                      lam_max: float = 800e-9) -> Tuple[np.ndarray, np.ndarray]:
+    """Complex probe amplitudes F (n_probes, n_freq) on a uniform omega grid
+    between two wavelengths, shaped like running-DFT emission spectra: every
+    probe is a sum of lines (centre and width as fractions of the band,
+    amplitude) with Gaussian |F| profiles at random phases, plus complex
+    Gaussian noise of the given amplitude.  Returns (F, omega)."""
+    c = 299792458.0
+    w_lo, w_hi = 2.0 * math.pi * c / lam_max, 2.0 * math.pi * c / lam_min
+    omega = np.linspace(w_lo, w_hi, n_freq) if n_freq > 1 else np.array([0.5 * (w_lo + w_hi)])
+    g = _rng(seed, 7)
+    x = (omega - w_lo) / (w_hi - w_lo)
+    F = np.zeros((n_probes, n_freq), dtype=np.complex128)
+    for p in range(n_probes):
+        for (x0, wid, amp) in lines:
+            phase = g.uniform(0.0, 2.0 * math.pi)
+            scale = g.uniform(0.5, 1.5)
+            F[p] += amp * scale * np.exp(-0.5 * ((x - x0) / wid) ** 2) * np.exp(1j * phase)
+        F[p] += noise * (g.standard_normal(n_freq) + 1j * g.standard_normal(n_freq))
+    return F, omega

@@ -62,6 +62,14 @@ class mbf_tuning(C.Structure):
                 ("xcd_remap", C.c_int32), ("group_mb", C.c_int32)]
 
 
+class mbf_spec_stats(C.Structure):
+    _fields_ = [("total", C.c_double), ("peak_omega", C.c_double), ("peak_value", C.c_double),
+                ("mean_omega", C.c_double), ("std_omega", C.c_double), ("fit_center", C.c_double),
+                ("fit_sigma", C.c_double), ("fit_amplitude", C.c_double),
+                ("peak_bin", C.c_int32), ("fit_lo", C.c_int32), ("fit_hi", C.c_int32),
+                ("fit_ok", C.c_int32)]
+
+
 MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED = 0, 1
 _VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED}
 
@@ -122,6 +130,9 @@ def _load():
         "mbf_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
         "mbf_adjoint_run": (I, [P, I64, I, VP, I, dp, dp]),
         "mbf_batch_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
+        "mbf_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
+        "mbf_spectral_stats": (I, [VP, I, I, VP, D, I, VP, C.POINTER(mbf_spec_stats)]),
+        "mbf_batch_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -141,7 +152,8 @@ EXPORTED = [
     "mbf_batch_create", "mbf_batch_destroy", "mbf_batch_last_error", "mbf_batch_size",
     "mbf_batch_member", "mbf_batch_set_tuning", "mbf_batch_get_tuning", "mbf_batch_step",
     "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes", "mbf_autotune",
-    "mbf_batch_autotune", "mbf_adjoint_run",
+    "mbf_batch_autotune", "mbf_adjoint_run", "mbf_spectrum_stats", "mbf_spectral_stats",
+    "mbf_batch_spectrum_stats",
 ]
 
 
@@ -258,6 +270,37 @@ def mbf_read_spectrum(h: int, n_probes: int, n_freq: int) -> np.ndarray:
     out = np.zeros((n_probes, n_freq, 2))
     _check(lib.mbf_read_spectrum(h, out.ctypes.data_as(C.POINTER(C.c_double))), h)
     return out[..., 0] + 1j * out[..., 1]
+
+
+def _stats_dict(o: mbf_spec_stats) -> dict:
+    return {name: getattr(o, name) for name, _ in mbf_spec_stats._fields_}
+
+
+def mbf_spectrum_stats(h: int, level: float = 0.5) -> dict:
+    o = mbf_spec_stats()
+    _check(lib.mbf_spectrum_stats(h, float(level), C.byref(o)), h)
+    return _stats_dict(o)
+
+
+def mbf_spectral_stats(spec, omega, level: float = 0.5, stream: Optional[int] = None) -> dict:
+    """Statistics of caller amplitudes: spec is (n_probes, n_freq) complex128
+    (numpy) or (n_probes, n_freq, 2) float64 (numpy or a device tensor, re/im
+    interleaved); omega (n_freq,) float64 in the same memory."""
+    if isinstance(spec, np.ndarray) and np.iscomplexobj(spec):
+        spec = np.ascontiguousarray(np.stack([spec.real, spec.imag], axis=-1), dtype=np.float64)
+    if isinstance(spec, np.ndarray):
+        spec = np.ascontiguousarray(spec, dtype=np.float64)
+        omega = np.ascontiguousarray(omega, dtype=np.float64)
+    if tuple(spec.shape[-1:]) != (2,) or len(spec.shape) != 3 or omega.shape[0] != spec.shape[1]:
+        raise ValueError("spec must be (n_probes, n_freq, 2) and omega (n_freq,)")
+    ps, ks, _a = _ptr_kind(spec)
+    pw, kw, _b = _ptr_kind(omega)
+    if ks != kw:
+        raise ValueError("spec and omega must live in the same memory")
+    o = mbf_spec_stats()
+    _check(lib.mbf_spectral_stats(ps, spec.shape[0], spec.shape[1], pw, float(level), ks,
+                                  C.c_void_p(stream or 0), C.byref(o)))
+    return _stats_dict(o)
 
 
 def mbf_read_loss(h: int) -> float:
@@ -399,6 +442,13 @@ def mbf_batch_step_timed(b: int, n: int) -> Tuple[Tuple[float, float], int]:
     return (ms[0], ms[1]), cnt.value
 
 
+def mbf_batch_spectrum_stats(b: int, level: float = 0.5) -> list:
+    R = mbf_batch_size(b)
+    arr = (mbf_spec_stats * R)()
+    _bcheck(lib.mbf_batch_spectrum_stats(b, float(level), arr), b)
+    return [_stats_dict(o) for o in arr]
+
+
 def mbf_batch_step_bytes(b: int) -> Tuple[float, float, float]:
     x = (C.c_double * 3)()
     _bcheck(lib.mbf_batch_step_bytes(b, x), b)
@@ -506,6 +556,11 @@ class Sim:
     def loss(self):
         return mbf_read_loss(self.h)
 
+    def spectrum_stats(self, level=0.5):
+        """Peak, standard deviation and Gaussian fit of the probe-summed
+        power spectrum (dict of the mbf_spec_stats fields)."""
+        return mbf_spectrum_stats(self.h, level)
+
     def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=2, group_mb=0):
         mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)
 
@@ -570,6 +625,10 @@ class Batch:
 
     def step_bytes(self):
         return mbf_batch_step_bytes(self.b)
+
+    def spectrum_stats(self, level=0.5):
+        """spectrum_stats of every member, in member order."""
+        return mbf_batch_spectrum_stats(self.b, level)
 
     def close(self):
         if getattr(self, "b", None):

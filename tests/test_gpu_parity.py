@@ -400,6 +400,16 @@ def test_lasing_spectra_match_oracle():
         ks, ko = int(np.argmax(fs[p])), int(np.argmax(fo[p]))
         assert abs(ks - ko) <= 1, p
         assert width(fs[p], ks) == pytest.approx(width(fo[p], ko), rel=0.02), p
+    # the library's statistics of the probe-summed spectrum (Gaussian-fit
+    # linewidth, standard deviation) against the oracle's of its own spectrum
+    from oracle import spectra as OS
+    gs, os_ = sim.spectrum_stats(0.5), OS.spectral_stats(ora.spectrum(), om, 0.5)
+    print("lasing spectrum: GPU peak bin %d sigma %.4e, oracle peak bin %d sigma %.4e" % (
+        gs["peak_bin"], gs["fit_sigma"], os_["peak_bin"], os_["fit_sigma"]))
+    assert abs(gs["peak_bin"] - os_["peak_bin"]) <= 1
+    assert gs["fit_ok"] == os_["fit_ok"] == 1
+    assert gs["fit_sigma"] == pytest.approx(os_["fit_sigma"], rel=0.02)
+    assert gs["std_omega"] == pytest.approx(os_["std_omega"], rel=0.02)
 
 
 def test_c2_size_parity_linear_interval():
