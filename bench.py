@@ -372,6 +372,14 @@ def main():
         f"{kern_ms[0] / launches:.3f} + {kern_ms[1] / launches:.3f} ms; "
         f"{alg[0] / cells:.1f} alg. B/cell per step; kernel source {sha}")
 
+    if args.workload == "c5":
+        # the linewidth analysis of the run's spectra (once per run, not per step)
+        t0 = time.perf_counter()
+        stats = batch.spectrum_stats(0.5)
+        st_ms = (time.perf_counter() - t0) * 1e3
+        log(f"spectral statistics of {len(stats)} members ({batch[0]._np} probes x {batch[0]._nf} bins): "
+            f"{st_ms:.2f} ms wall; peak bins {[q['peak_bin'] for q in stats]}")
+
     if args.calib_copy:
         a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -257,10 +257,10 @@ int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out);
 
 /* The same statistics of caller data: spec[2 * n_probes * n_freq] (probe-
  * major, interleaved re, im) and omega[n_freq], both host or both device
- * memory per mem_kind (caller-owned, unchanged).  Runs on `stream` (NULL: the
- * null stream) in device memory it allocates and frees; returns when *out
- * holds the result.  n_probes >= 1, n_freq >= 1, 0 < level < 1 (MBF_EINVAL
- * otherwise). */
+ * memory per mem_kind (caller-owned, unchanged; a device spec must be 16-byte
+ * aligned).  Runs on `stream` (NULL: the null stream) in device memory it
+ * allocates and frees; returns when *out holds the result.  n_probes >= 1,
+ * n_freq >= 1, 0 < level < 1 (MBF_EINVAL otherwise). */
 int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
                        int mem_kind, void* stream, mbf_spec_stats* out);
 

@@ -1276,8 +1276,8 @@ int spec_stats_device(mbf_handle* h, const double* dspec, int np, int nf, const 
     if (hipMalloc(&pw, sizeof(double) * (size_t)nf) != hipSuccess ||
         hipMalloc(&dout, sizeof(mbf_spec_stats)) != hipSuccess)
         return fail(h, MBF_ENOMEM, "device allocation for the spectral statistics failed");
-    hipLaunchKernelGGL(mbf::k_spec_stats, dim3(1), dim3(mbf::kStatThreads), 0, st, dspec, np, nf, domega, level,
-                       pw, dout);
+    hipLaunchKernelGGL(mbf::k_spec_power, dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, st, dspec, np, nf, pw);
+    hipLaunchKernelGGL(mbf::k_spec_stats, dim3(1), dim3(mbf::kStatThreads), 0, st, pw, nf, domega, level, dout);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(out, dout, sizeof(mbf_spec_stats), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
@@ -1310,7 +1310,11 @@ int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const doubl
     if (!stat_level_ok(level)) return fail(nullptr, MBF_EINVAL, "level must lie in (0, 1)");
     if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
     hipStream_t st = (hipStream_t)stream;
-    if (mem_kind == MBF_MEM_DEVICE) return spec_stats_device(nullptr, spec, n_probes, n_freq, omega, level, st, out);
+    if (mem_kind == MBF_MEM_DEVICE) {
+        if (reinterpret_cast<uintptr_t>(spec) % 16 != 0)
+            return fail(nullptr, MBF_EINVAL, "device spec must be 16-byte aligned");
+        return spec_stats_device(nullptr, spec, n_probes, n_freq, omega, level, st, out);
+    }
     const size_t ns = sizeof(double) * 2 * (size_t)n_probes * (size_t)n_freq, no = sizeof(double) * (size_t)n_freq;
     double *ds = nullptr, *dw = nullptr;
     struct Free {

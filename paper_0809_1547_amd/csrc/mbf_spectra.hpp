@@ -41,27 +41,46 @@ __device__ __forceinline__ void stat_max(double& v, int& k, double v2, int k2) {
     }
 }
 
-// One workgroup per spectrum: spec holds np x nf complex values (re, im
-// interleaved, probe-major), pw receives S (nf values), out the statistics.
-__global__ void __launch_bounds__(kStatThreads) k_spec_stats(const double* __restrict__ spec, int np, int nf,
+// S_k = sum_p |F_{p,k}|^2, one thread per bin (a wave reads 64 consecutive
+// complex values of one probe at a time); spec holds np x nf complex values,
+// re and im interleaved, probe-major.  The probes are added in index order;
+// the loads of eight probes go out before their sums.
+__global__ void __launch_bounds__(64) k_spec_power(const double* __restrict__ spec, int np, int nf,
+                                                   double* __restrict__ pw) {
+    const int k = (int)(blockIdx.x * 64 + threadIdx.x);
+    if (k >= nf) return;
+    const double2* __restrict__ f = reinterpret_cast<const double2*>(spec);
+    double s = 0.0;
+    int p = 0;
+    for (; p + 8 <= np; p += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = f[(int64_t)(p + q) * nf + k];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q].x * v[q].x + v[q].y * v[q].y;
+    }
+    for (; p < np; ++p) {
+        const double2 v = f[(int64_t)p * nf + k];
+        s += v.x * v.x + v.y * v.y;
+    }
+    pw[k] = s;
+}
+
+// One workgroup per spectrum: pw holds S (nf values, from k_spec_power),
+// out receives the statistics.
+__global__ void __launch_bounds__(kStatThreads) k_spec_stats(const double* __restrict__ pw, int nf,
                                                             const double* __restrict__ omega, double level,
-                                                            double* __restrict__ pw, mbf_spec_stats* out) {
+                                                            mbf_spec_stats* out) {
     __shared__ double sh[kStatThreads / 64];
     __shared__ double shv[kStatThreads / 64];
     __shared__ int shk[kStatThreads / 64];
     __shared__ int win[2];
     const int t = (int)threadIdx.x;
-    // ---- power spectrum, total, peak
+    // ---- total, peak
     double tot = 0.0, best = -1.0;
     int bk = nf;
     for (int k = t; k < nf; k += kStatThreads) {
-        double s = 0.0;
-        for (int p = 0; p < np; ++p) {
-            const int64_t q = 2 * ((int64_t)p * nf + k);
-            const double re = spec[q], im = spec[q + 1];
-            s += re * re + im * im;
-        }
-        pw[k] = s;
+        const double s = pw[k];
         tot += s;
         stat_max(best, bk, s, k);
     }
@@ -75,7 +94,7 @@ __global__ void __launch_bounds__(kStatThreads) k_spec_stats(const double* __res
         shv[t >> 6] = best;
         shk[t >> 6] = bk;
     }
-    const double total = stat_sum(tot, sh);           // its barriers also publish shv, shk and pw
+    const double total = stat_sum(tot, sh);           // its barriers also publish shv and shk
     double peak = shv[0];
     int kp = shk[0];
     for (int w = 1; w < kStatThreads / 64; ++w) stat_max(peak, kp, shv[w], shk[w]);

@@ -143,18 +143,24 @@ def test_c4_adjoint_against_fp64_differences():
     import time
     eps, gain = I.voxelize(I.packing_for("c4", 96, 0))
     nsteps = 1000
-    sim = _c4_sim("fp32", eps, gain)
-    t0 = time.perf_counter()
-    L, g, gna = sim.adjoint_run(nsteps, K=50)
-    t_adj = time.perf_counter() - t0
-    sim.close()
+    # cost: the better of two runs each (a fresh handle per adjoint run, since
+    # the run must start from the pump)
+    t_adj = t_fwd = float("inf")
+    for _ in range(2):
+        sim = _c4_sim("fp32", eps, gain)
+        sim.sync()
+        t0 = time.perf_counter()
+        L, g, gna = sim.adjoint_run(nsteps, K=50)
+        t_adj = min(t_adj, time.perf_counter() - t0)
+        sim.close()
     sim = _c4_sim("fp32", eps, gain)
     sim.step(8)
-    sim.sync()
-    t0 = time.perf_counter()
-    sim.step(nsteps)
-    sim.sync()
-    t_fwd = time.perf_counter() - t0
+    for _ in range(2):
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(nsteps)
+        sim.sync()
+        t_fwd = min(t_fwd, time.perf_counter() - t0)
     sim.close()
     print(f"C4: forward {t_fwd * 1e3:.1f} ms, forward+adjoint {t_adj * 1e3:.1f} ms, "
           f"reverse sweep / forward = {(t_adj - t_fwd) / t_fwd:.2f}")
