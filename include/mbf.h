@@ -183,6 +183,16 @@ int mbf_set_pump(mbf_handle* h, double Na, int init);
 int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double amp,
                          double lambda_s, double tau_p, double t0);
 
+/* Continuous-wave soft source on E-site (comp; i,j,k), which must be
+ * interior: amp * (1 - exp(-(t/t_ramp)^2)) * sin(w_s t) with w_s = 2 pi c /
+ * lambda_s, added to E^{n+1} at t = (n+1) dt (Simulations section: the field
+ * distribution of a mode is found by CW excitation at its spectral peak; the
+ * Gaussian switch-on over t_ramp keeps the drive narrow-band).  It replaces
+ * any source of the handle (one source per handle); amp != 0, lambda_s > 0,
+ * t_ramp > 0 (MBF_EINVAL otherwise). */
+int mbf_add_cw_source(mbf_handle* h, int comp, int i, int j, int k, double amp, double lambda_s,
+                      double t_ramp);
+
 /* Running DFT monitor: F[p][w] += E_c(site_p)^{m} exp(+i omega_w m dt) for
  * every sample m (the Fourier sign of the Gross-Pitaevskii section).
  * sites[4*n_probes] rows (comp, i, j, k); omega[n_freq] in rad/s; samples are
@@ -219,6 +229,22 @@ int mbf_read_spectrum(mbf_handle* h, double* re_im);
 
 /* Loss-box integral. */
 int mbf_read_loss(mbf_handle* h, double* out);
+
+/* Energy density in a section of the sample (Simulations section: the
+ * energy density in the middle section under CW excitation, Fig. 1 inset,
+ * and in the lasing run, Fig. 2a).  mbf_set_plane_monitor(h, k) with
+ * 0 <= k < nz sums, every step n, u(i,j) = 1/2 [eps_r |E^n|^2 +
+ * |H^{n+1/2}|^2] over the cell's own E- and H-sites (i, j, k) into an FP64
+ * array of nx*ny values (x fastest), starting from zero now; k = -1 removes
+ * the monitor.  mbf_reset_plane_monitor zeroes the sums;
+ * mbf_read_plane_monitor synchronises and copies them to the host buffer
+ * out[nx*ny] (caller-owned) with *count the number of steps summed (divide
+ * for the time average).  mbf_set_pump zeroes the sums too; checkpoints and
+ * device snapshots carry them (an image saved with a monitor loads only into
+ * a handle monitoring the same plane).  MBF_ESTATE without a monitor. */
+int mbf_set_plane_monitor(mbf_handle* h, int k);
+int mbf_reset_plane_monitor(mbf_handle* h);
+int mbf_read_plane_monitor(mbf_handle* h, double* out, int64_t* count);
 
 /* ------------------------------------------------------ spectral statistics
  * Peak and width of an emission spectrum (Results section: the linewidth of
@@ -263,6 +289,20 @@ int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out);
  * n_freq >= 1, 0 < level < 1 (MBF_EINVAL otherwise). */
 int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
                        int mem_kind, void* stream, mbf_spec_stats* out);
+
+/* Spectral peaks (Simulations section: the spectrum after a wide-band pulse
+ * shows several peaks, the long-lived modes, Fig. 1).  Of the same S_k: the
+ * bins with S_k > 0, S_k >= min_rel * max_k S_k and S_{k-1} < S_k >= S_{k+1}
+ * (a band-edge bin compares with its one neighbour; a flat top counts once,
+ * at its first bin), by decreasing S_k (equal values: lower k first), at most
+ * max_peaks of them into the host buffer bins[max_peaks] (caller-owned),
+ * *n_found how many.  0 <= min_rel <= 1, 1 <= max_peaks <= 1024 (MBF_EINVAL
+ * otherwise).  mbf_spectrum_peaks works on a handle's spectra (MBF_ESTATE
+ * without probes), mbf_spectral_peaks on caller amplitudes as
+ * mbf_spectral_stats. */
+int mbf_spectrum_peaks(mbf_handle* h, double min_rel, int max_peaks, int32_t* bins, int* n_found);
+int mbf_spectral_peaks(const double* spec, int n_probes, int n_freq, double min_rel, int max_peaks, int mem_kind,
+                       void* stream, int32_t* bins, int* n_found);
 
 /* Copy one site array out of / into the device state (see field ids), in the
  * packed layout of (nx+1)*(ny+1)*(nz+1) values, x fastest; dst/src are host

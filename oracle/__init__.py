@@ -60,6 +60,11 @@ def lib():
                                      C.c_double, C.c_double, C.c_double]
         L.orc_source_value.restype = C.c_double
         L.orc_source_value.argtypes = [P, C.c_int64]
+        L.orc_set_cw_source.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                        C.c_double, C.c_double]
+        L.orc_set_plane_monitor.argtypes = [P, C.c_int]
+        L.orc_read_plane_monitor.restype = C.c_int64
+        L.orc_read_plane_monitor.argtypes = [P, dp]
         L.orc_set_probes.argtypes = [P, C.c_void_p, C.c_int, C.c_void_p, C.c_int]
         L.orc_set_loss_box.argtypes = [P] + [C.c_int] * 6
         L.orc_step.argtypes = [P, C.c_int64]
@@ -173,6 +178,22 @@ class Oracle:
 
     def source_value(self, n: int) -> float:
         return lib().orc_source_value(self._h, n)
+
+    def set_cw_source(self, comp, i, j, k, amp=1.0, lambda_s=586.5e-9, t_ramp=20e-15):
+        if lib().orc_set_cw_source(self._h, comp, i, j, k, amp, lambda_s, t_ramp) != 0:
+            raise ValueError("bad source")
+
+    def set_plane_monitor(self, k: int):
+        if lib().orc_set_plane_monitor(self._h, int(k)) != 0:
+            raise ValueError("bad plane")
+
+    def plane_monitor(self):
+        """(sums of the plane's energy density (ny, nx), steps summed)."""
+        out = np.empty((self.n[1], self.n[0]))
+        cnt = lib().orc_read_plane_monitor(self._h, _dp(out))
+        if cnt < 0:
+            raise ValueError("no plane monitor")
+        return out, int(cnt)
 
     def set_probes(self, sites: np.ndarray, omega: np.ndarray):
         sites = np.ascontiguousarray(sites, dtype=np.int32).reshape(-1, 4)

@@ -35,8 +35,11 @@ struct orc_sim {
     double* inv_eps;
     uint8_t* gain;
     int64_t step;
-    int src_on, src_comp, src_i, src_j, src_k;
+    int src_on, src_kind, src_comp, src_i, src_j, src_k;
     double src_amp, src_ws, src_tp, src_t0;
+    double* map;               /* energy density of plane map_k summed over steps */
+    int map_k;
+    int64_t map_count;
     int n_probes, n_freq;
     int32_t* probes;
     double* omega;
@@ -256,7 +259,7 @@ void orc_destroy(orc_sim* s) {
     for (int q = 0; q < 3; ++q) { free(s->Hn[q]); free(s->Eold[q]); }
     free(s->eps); free(s->inv_eps); free(s->gain); free(s->plane_sum);
     for (int a = 0; a < 3; ++a) { free(s->prof[a][0]); free(s->prof[a][1]); }
-    free(s->probes); free(s->omega); free(s->spec); free(s->hist);
+    free(s->probes); free(s->omega); free(s->spec); free(s->hist); free(s->map);
     free(s);
 }
 
@@ -282,6 +285,8 @@ static void reset_monitors(orc_sim* s) {
     s->hist_len = 0;
     s->loss = 0.0;
     if (s->spec) memset(s->spec, 0, sizeof(double) * 2 * (size_t)s->n_probes * s->n_freq);
+    if (s->map) memset(s->map, 0, sizeof(double) * (size_t)s->nx * s->ny);
+    s->map_count = 0;
 }
 
 int orc_set_pump(orc_sim* s, double Na_si, int init) {
@@ -332,6 +337,7 @@ int orc_set_source(orc_sim* s, int comp, int i, int j, int k, double amp,
                    double lambda_s, double tau_p, double t0) {
     if (comp < 0 || comp > 2 || !e_interior(s, comp, i, j, k)) return -1;
     s->src_on = 1;
+    s->src_kind = 0;
     s->src_comp = comp; s->src_i = i; s->src_j = j; s->src_k = k;
     s->src_amp = amp;
     s->src_ws = 2.0 * ORC_PI * ORC_C0 / lambda_s;
@@ -340,12 +346,65 @@ int orc_set_source(orc_sim* s, int comp, int i, int j, int k, double amp,
     return 0;
 }
 
-/* soft source added to E^{n+1} during step n, evaluated at t = (n+1) dt */
+int orc_set_cw_source(orc_sim* s, int comp, int i, int j, int k, double amp,
+                      double lambda_s, double t_ramp) {
+    if (comp < 0 || comp > 2 || !e_interior(s, comp, i, j, k) || !(t_ramp > 0.0)) return -1;
+    s->src_on = 1;
+    s->src_kind = 1;
+    s->src_comp = comp; s->src_i = i; s->src_j = j; s->src_k = k;
+    s->src_amp = amp;
+    s->src_ws = 2.0 * ORC_PI * ORC_C0 / lambda_s;
+    s->src_tp = t_ramp;
+    s->src_t0 = 0.0;
+    return 0;
+}
+
+/* soft source added to E^{n+1} during step n, evaluated at t = (n+1) dt:
+ * the Gaussian pulse, or the continuous wave with a Gaussian switch-on */
 double orc_source_value(const orc_sim* s, int64_t n) {
     if (!s->src_on) return 0.0;
+    if (s->src_kind == 1) {
+        double t = (double)(n + 1) * s->coef[ORC_C_DT];
+        double ramp = 1.0 - exp(-(t / s->src_tp) * (t / s->src_tp));
+        return rnd(s, s->src_amp * ramp * sin(s->src_ws * t));
+    }
     double t = (double)(n + 1) * s->coef[ORC_C_DT] - s->src_t0;
     double v = s->src_amp * sin(s->src_ws * t) * exp(-(t / s->src_tp) * (t / s->src_tp));
     return rnd(s, v);
+}
+
+int orc_set_plane_monitor(orc_sim* s, int k) {
+    if (k < -1 || k >= s->nz) return -1;
+    free(s->map);
+    s->map = NULL;
+    s->map_k = -1;
+    s->map_count = 0;
+    if (k < 0) return 0;
+    s->map = (double*)calloc((size_t)s->nx * s->ny, sizeof(double));
+    if (!s->map) return -1;
+    s->map_k = k;
+    return 0;
+}
+
+int64_t orc_read_plane_monitor(const orc_sim* s, double* out) {
+    if (!s->map) return -1;
+    memcpy(out, s->map, sizeof(double) * (size_t)s->nx * s->ny);
+    return s->map_count;
+}
+
+/* energy density 1/2 [eps |E^n|^2 + |H^{n+1/2}|^2] of the cells of plane
+ * map_k from their own sites (i, j, map_k), added to the sums */
+static void plane_monitor(orc_sim* s) {
+    if (!s->map) return;
+    const int k = s->map_k;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            size_t x = at(s, i, j, k);
+            double e2 = (s->f[0][x] * s->f[0][x] + s->f[1][x] * s->f[1][x]) + s->f[2][x] * s->f[2][x];
+            double h2 = (s->Hn[0][x] * s->Hn[0][x] + s->Hn[1][x] * s->Hn[1][x]) + s->Hn[2][x] * s->Hn[2][x];
+            s->map[(size_t)i + (size_t)s->nx * j] += 0.5 * (s->eps[cell_of(s, i, j, k)] * e2 + h2);
+        }
+    s->map_count++;
 }
 
 int orc_set_probes(orc_sim* s, const int32_t* sites, int n_probes, const double* omega,
@@ -635,6 +694,7 @@ int orc_step(orc_sim* s, int64_t nsteps) {
     for (int64_t t = 0; t < nsteps; ++t) {
         update_h(s);
         push_energy(s, energy(s));
+        plane_monitor(s);
         update_p(s);
         update_e(s);
         apply_mur(s);
@@ -683,7 +743,7 @@ static int forward_copy(const orc_sim* s, state_t X1) {
     memcpy(t->rates, s->rates, sizeof(s->rates));
     for (int q = 0; q < ORC_NFIELDS; ++q) memcpy(t->f[q], s->f[q], sizeof(double) * s->ntot);
     t->step = s->step;
-    t->src_on = s->src_on; t->src_comp = s->src_comp;
+    t->src_on = s->src_on; t->src_kind = s->src_kind; t->src_comp = s->src_comp;
     t->src_i = s->src_i; t->src_j = s->src_j; t->src_k = s->src_k;
     t->src_amp = s->src_amp; t->src_ws = s->src_ws; t->src_tp = s->src_tp; t->src_t0 = s->src_t0;
     orc_step(t, 1);

@@ -87,6 +87,13 @@ int      orc_set_pump(orc_sim* s, double Na, int init);
 int      orc_set_source(orc_sim* s, int comp, int i, int j, int k, double amp,
                         double lambda_s, double tau_p, double t0);
 double   orc_source_value(const orc_sim* s, int64_t n);
+/* continuous wave amp (1 - exp(-(t/t_ramp)^2)) sin(w_s t), replacing any source */
+int      orc_set_cw_source(orc_sim* s, int comp, int i, int j, int k, double amp,
+                           double lambda_s, double t_ramp);
+/* energy density of the cells of plane z = k summed over steps (k = -1: off);
+ * the read returns the number of steps summed (-1 without a monitor) */
+int      orc_set_plane_monitor(orc_sim* s, int k);
+int64_t  orc_read_plane_monitor(const orc_sim* s, double* out /* nx*ny */);
 int      orc_set_probes(orc_sim* s, const int32_t* sites, int n_probes,
                         const double* omega, int n_freq);
 int      orc_set_loss_box(orc_sim* s, int i0, int j0, int k0, int i1, int j1, int k1);

@@ -73,3 +73,22 @@ def spectral_stats(F: np.ndarray, omega: np.ndarray, level: float = 0.5) -> dict
                    fit_sigma=float(abs(s) * np.sqrt(-1.0 / (2.0 * c))),
                    fit_amplitude=float(peak * np.exp(a - b * b / (4.0 * c))))
     return out
+
+
+def spectral_peaks(F: np.ndarray, min_rel: float = 0.1, max_peaks: int = 16) -> list:
+    """Bins of the spectral peaks: S_k > 0, S_k >= min_rel * max S and
+    S_{k-1} < S_k >= S_{k+1} (a band-edge bin has one neighbour; a flat top
+    counts at its first bin), largest first (equal values: lower bin first),
+    at most max_peaks (the long-lived modes of a passive spectrum, Fig. 1)."""
+    S = power_spectrum(F)
+    K = S.shape[0]
+    thr = min_rel * float(np.max(S)) if K else 0.0
+    peaks = []
+    for k in range(K):
+        v = S[k]
+        left_ok = k == 0 or S[k - 1] < v
+        right_ok = k == K - 1 or v >= S[k + 1]
+        if v > 0.0 and v >= thr and left_ok and right_ok:
+            peaks.append(k)
+    peaks.sort(key=lambda k: (-S[k], k))
+    return peaks[:max_peaks]

@@ -72,8 +72,12 @@ struct mbf_handle {
     double* d_spec = nullptr;
     int64_t flushed = 0;
     // source
-    int src_on = 0, src_comp = 0, src_i = 0, src_j = 0, src_k = 0;
+    int src_on = 0, src_kind = 0, src_comp = 0, src_i = 0, src_j = 0, src_k = 0;
     double src_amp = 0, src_ws = 0, src_tp = 1, src_t0 = 0;
+    // plane energy-density monitor (map == nullptr: off)
+    double* map = nullptr;
+    int map_k = -1;
+    int64_t map_start = 0;    // step at which the sums were last zeroed
     // loss box
     int box_on = 0, box[6] = {};
     int mur_tasks = 0, mur_a[mbf::kMaxMurTasks] = {}, mur_side[mbf::kMaxMurTasks] = {},
@@ -212,6 +216,7 @@ mbf::SimView<T> view(mbf_handle* h) {
     v.src_on = h->src_on;
     v.src_comp = h->src_comp;
     v.src_i = h->src_i; v.src_j = h->src_j; v.src_k = h->src_k;
+    v.src_kind = h->src_kind;
     v.src_amp = h->src_amp; v.src_ws = h->src_ws; v.src_tp = h->src_tp; v.src_t0 = h->src_t0;
     v.dt = k.dt;
     v.box_on = h->box_on;
@@ -243,6 +248,8 @@ mbf::SimView<T> view(mbf_handle* h) {
     v.ring = reinterpret_cast<T*>(h->d_ring);
     v.omega = h->d_omega;
     v.spec = h->d_spec;
+    v.map = h->map;
+    v.map_k = h->map_k;
     return v;
 }
 
@@ -565,13 +572,17 @@ hipError_t copy_sites(const mbf_handle* h, void* dst, const void* src, bool to_d
 struct Snap {
     void* buf = nullptr;
     size_t bytes = 0;
-    int64_t step = 0, flushed = 0;
+    int64_t step = 0, flushed = 0, map_start = 0;
 };
+
+size_t map_bytes(const mbf_handle* h) {
+    return h->map ? sizeof(double) * (size_t)h->cfg.nx * h->cfg.ny : 0;
+}
 
 size_t snap_bytes(const mbf_handle* h) {
     return (size_t)h->nsite * h->esz * 12 + (size_t)h->glen * h->esz * 15 + sizeof(mbf::Ctl) +
            sizeof(double) * (size_t)h->hist_cap + sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq +
-           h->esz * (size_t)h->n_probes * h->decim;
+           h->esz * (size_t)h->n_probes * h->decim + map_bytes(h);
 }
 
 int snap_copy(mbf_handle* h, Snap& s, bool save) {
@@ -583,6 +594,7 @@ int snap_copy(mbf_handle* h, Snap& s, bool save) {
         {h->hist, sizeof(double) * (size_t)h->hist_cap},
         {h->d_spec, sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq},
         {h->d_ring, h->esz * (size_t)h->n_probes * h->decim},
+        {h->map, map_bytes(h)},
     };
     size_t off = 0;
     for (const Part& q : parts) {
@@ -595,9 +607,11 @@ int snap_copy(mbf_handle* h, Snap& s, bool save) {
     if (save) {
         s.step = h->step;
         s.flushed = h->flushed;
+        s.map_start = h->map_start;
     } else {
         h->step = s.step;
         h->flushed = s.flushed;
+        h->map_start = s.map_start;
     }
     return MBF_OK;
 }
@@ -804,7 +818,7 @@ void mbf_destroy(mbf_handle* h) {
     hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
     hipFree(h->mat); hipFree(h->lut);
     hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
-    hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items);
+    hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items); hipFree(h->map);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
 }
@@ -928,8 +942,10 @@ static int reset_monitors(mbf_handle* h) {
     HIPCHK(h, hipMemsetAsync(h->ctl, 0, sizeof(mbf::Ctl), h->stream));
     if (h->d_spec)
         HIPCHK(h, hipMemsetAsync(h->d_spec, 0, sizeof(double) * 2 * h->n_probes * h->n_freq, h->stream));
+    if (h->map) HIPCHK(h, hipMemsetAsync(h->map, 0, map_bytes(h), h->stream));
     h->flushed = 0;
     h->step = 0;
+    h->map_start = 0;
     return MBF_OK;
 }
 
@@ -990,6 +1006,7 @@ int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double am
     if (!std::isfinite(amp) || !finite_pos(lambda_s) || !finite_pos(tau_p) || !std::isfinite(t0))
         return fail(h, MBF_EINVAL, "bad source parameters");
     h->src_on = 1;
+    h->src_kind = 0;
     h->src_comp = comp; h->src_i = i; h->src_j = j; h->src_k = k;
     h->src_amp = amp;
     h->src_ws = 2.0 * kPi * kC0 / lambda_s;
@@ -997,6 +1014,67 @@ int mbf_add_point_source(mbf_handle* h, int comp, int i, int j, int k, double am
     h->src_t0 = t0;
     drop_graph(h);
     return init_source(h);
+}
+
+int mbf_add_cw_source(mbf_handle* h, int comp, int i, int j, int k, double amp, double lambda_s, double t_ramp) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    const mbf_config& c = h->cfg;
+    if (comp < 0 || comp > 2) return fail(h, MBF_EINVAL, "component must be 0, 1 or 2");
+    const int idx[3] = {i, j, k};
+    const int nd[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = (a == comp) ? 0 : 1;
+        if (idx[a] < lo || idx[a] >= nd[a]) return fail(h, MBF_EINVAL, "source must be an interior E-site");
+    }
+    if (!std::isfinite(amp) || amp == 0.0 || !finite_pos(lambda_s) || !finite_pos(t_ramp))
+        return fail(h, MBF_EINVAL, "bad source parameters");
+    h->src_on = 1;
+    h->src_kind = 1;
+    h->src_comp = comp; h->src_i = i; h->src_j = j; h->src_k = k;
+    h->src_amp = amp;
+    h->src_ws = 2.0 * kPi * kC0 / lambda_s;
+    h->src_tp = t_ramp;
+    h->src_t0 = 0.0;
+    drop_graph(h);
+    return init_source(h);
+}
+
+int mbf_set_plane_monitor(mbf_handle* h, int k) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    if (k < -1 || k >= h->cfg.nz) return fail(h, MBF_EINVAL, "plane index must be in [0, nz) or -1");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    if (k < 0) {
+        hipFree(h->map);
+        h->map = nullptr;
+        h->map_k = -1;
+        return MBF_OK;
+    }
+    if (!h->map && hipMalloc(&h->map, sizeof(double) * (size_t)h->cfg.nx * h->cfg.ny) != hipSuccess) {
+        h->map = nullptr;
+        return fail(h, MBF_ENOMEM, "plane monitor allocation failed");
+    }
+    h->map_k = k;
+    HIPCHK(h, hipMemsetAsync(h->map, 0, map_bytes(h), h->stream));
+    h->map_start = h->step;
+    return MBF_OK;
+}
+
+int mbf_reset_plane_monitor(mbf_handle* h) {
+    if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
+    if (!h->map) return fail(h, MBF_ESTATE, "no plane monitor set");
+    HIPCHK(h, hipMemsetAsync(h->map, 0, map_bytes(h), h->stream));
+    h->map_start = h->step;
+    return MBF_OK;
+}
+
+int mbf_read_plane_monitor(mbf_handle* h, double* out, int64_t* count) {
+    if (!h || !out || !count) return fail(h, MBF_EINVAL, "null argument");
+    if (!h->map) return fail(h, MBF_ESTATE, "no plane monitor set");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(out, h->map, map_bytes(h), hipMemcpyDeviceToHost));
+    *count = h->step - h->map_start;
+    return MBF_OK;
 }
 
 int mbf_set_probes(mbf_handle* h, const int32_t* sites, int n_probes, const double* omega,
@@ -1286,6 +1364,35 @@ int spec_stats_device(mbf_handle* h, const double* dspec, int np, int nf, const 
 
 bool stat_level_ok(double level) { return std::isfinite(level) && level > 0.0 && level < 1.0; }
 
+// Peaks of np x nf device amplitudes on stream st into host bins[max_peaks].
+int spec_peaks_device(mbf_handle* h, const double* dspec, int np, int nf, double min_rel, int max_peaks,
+                      hipStream_t st, int32_t* bins, int* n_found) {
+    double* pw = nullptr;
+    int32_t* dout = nullptr;
+    struct Free {
+        double*& pw;
+        int32_t*& dout;
+        ~Free() { hipFree(pw); hipFree(dout); }
+    } fr{pw, dout};
+    if (hipMalloc(&pw, sizeof(double) * (size_t)nf) != hipSuccess ||
+        hipMalloc(&dout, sizeof(int32_t) * (size_t)(max_peaks + 1)) != hipSuccess)
+        return fail(h, MBF_ENOMEM, "device allocation for the spectral peaks failed");
+    hipLaunchKernelGGL(mbf::k_spec_power, dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, st, dspec, np, nf, pw);
+    hipLaunchKernelGGL(mbf::k_spec_peaks, dim3(1), dim3(mbf::kStatThreads), 0, st, pw, nf, min_rel, max_peaks,
+                       dout + 1, dout);
+    HIPCHK(h, hipGetLastError());
+    std::vector<int32_t> host((size_t)max_peaks + 1);
+    HIPCHK(h, hipMemcpyAsync(host.data(), dout, sizeof(int32_t) * host.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    *n_found = host[0];
+    for (int q = 0; q < host[0]; ++q) bins[q] = host[(size_t)q + 1];
+    return MBF_OK;
+}
+
+bool peak_args_ok(double min_rel, int max_peaks) {
+    return std::isfinite(min_rel) && min_rel >= 0.0 && min_rel <= 1.0 && max_peaks >= 1 && max_peaks <= 1024;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1301,6 +1408,44 @@ int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out) {
         h->flushed = h->step;
     }
     return spec_stats_device(h, h->d_spec, h->n_probes, h->n_freq, h->d_omega, level, h->stream, out);
+}
+
+int mbf_spectrum_peaks(mbf_handle* h, double min_rel, int max_peaks, int32_t* bins, int* n_found) {
+    if (!h || !bins || !n_found) return fail(h, MBF_EINVAL, "null argument");
+    if (!peak_args_ok(min_rel, max_peaks)) return fail(h, MBF_EINVAL, "min_rel in [0, 1], max_peaks in [1, 1024]");
+    if (h->n_probes == 0 || h->n_freq == 0) return fail(h, MBF_ESTATE, "no probes or frequencies set");
+    const int64_t pending = h->step - h->flushed;
+    if (pending > 0) {
+        int rc = dispatch_dft(h, (int)pending);
+        if (rc) return rc;
+        h->flushed = h->step;
+    }
+    return spec_peaks_device(h, h->d_spec, h->n_probes, h->n_freq, min_rel, max_peaks, h->stream, bins, n_found);
+}
+
+int mbf_spectral_peaks(const double* spec, int n_probes, int n_freq, double min_rel, int max_peaks, int mem_kind,
+                       void* stream, int32_t* bins, int* n_found) {
+    if (!spec || !bins || !n_found) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n_probes < 1 || n_freq < 1) return fail(nullptr, MBF_EINVAL, "n_probes and n_freq must be >= 1");
+    if (!peak_args_ok(min_rel, max_peaks))
+        return fail(nullptr, MBF_EINVAL, "min_rel in [0, 1], max_peaks in [1, 1024]");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    hipStream_t st = (hipStream_t)stream;
+    if (mem_kind == MBF_MEM_DEVICE) {
+        if (reinterpret_cast<uintptr_t>(spec) % 16 != 0)
+            return fail(nullptr, MBF_EINVAL, "device spec must be 16-byte aligned");
+        return spec_peaks_device(nullptr, spec, n_probes, n_freq, min_rel, max_peaks, st, bins, n_found);
+    }
+    const size_t ns = sizeof(double) * 2 * (size_t)n_probes * (size_t)n_freq;
+    double* ds = nullptr;
+    struct Free {
+        double*& a;
+        ~Free() { hipFree(a); }
+    } fr{ds};
+    if (hipMalloc(&ds, ns) != hipSuccess)
+        return fail(nullptr, MBF_ENOMEM, "device allocation for the spectral peaks failed");
+    HIPCHK(nullptr, hipMemcpy(ds, spec, ns, hipMemcpyHostToDevice));
+    return spec_peaks_device(nullptr, ds, n_probes, n_freq, min_rel, max_peaks, st, bins, n_found);
 }
 
 int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
@@ -1405,19 +1550,20 @@ struct StateHeader {
     uint64_t magic;
     int32_t nx, ny, nz, precision;
     int64_t step;
-    int32_t n_probes, n_freq, decim, pad;
+    int32_t n_probes, n_freq, decim, map_k;
     int64_t flushed;
+    int64_t map_start;
     double Na_si;
     mbf::Ctl ctl;
 };
-constexpr uint64_t kMagic = 0x3146424D5F54534Bull;
+constexpr uint64_t kMagic = 0x3246424D5F54534Bull;
 }  // namespace
 
 int mbf_state_size(const mbf_handle* h, size_t* out) {
     if (!h || !out) return fail(nullptr, MBF_EINVAL, "null argument");
     *out = sizeof(StateHeader) + (size_t)MBF_NFIELDS * h->nexch * h->esz +
            sizeof(double) * 2 * (size_t)h->n_probes * h->n_freq + h->esz * (size_t)h->n_probes * h->decim +
-           sizeof(uint64_t);
+           map_bytes(h) + sizeof(uint64_t);
     return MBF_OK;
 }
 
@@ -1434,6 +1580,8 @@ int mbf_save_state(mbf_handle* h, void* buf, size_t n) {
     hd.step = h->step;
     hd.n_probes = h->n_probes; hd.n_freq = h->n_freq; hd.decim = h->decim;
     hd.flushed = h->flushed;
+    hd.map_k = h->map ? h->map_k : -1;
+    hd.map_start = h->map_start;
     hd.Na_si = h->Na_si;
     HIPCHK(h, hipMemcpy(&hd.ctl, h->ctl, sizeof(mbf::Ctl), hipMemcpyDeviceToHost));
     std::memcpy(p, &hd, sizeof(hd));
@@ -1463,6 +1611,10 @@ int mbf_save_state(mbf_handle* h, void* buf, size_t n) {
         HIPCHK(h, hipMemcpy(p + off, h->d_ring, rb, hipMemcpyDeviceToHost));
         off += rb;
     }
+    if (h->map) {
+        HIPCHK(h, hipMemcpy(p + off, h->map, map_bytes(h), hipMemcpyDeviceToHost));
+        off += map_bytes(h);
+    }
     const uint64_t cs = fnv1a(p, off);
     std::memcpy(p + off, &cs, sizeof(cs));
     return MBF_OK;
@@ -1478,7 +1630,7 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
     std::memcpy(&hd, p, sizeof(hd));
     if (hd.magic != kMagic || hd.nx != h->cfg.nx || hd.ny != h->cfg.ny || hd.nz != h->cfg.nz ||
         hd.precision != h->cfg.precision || hd.n_probes != h->n_probes || hd.n_freq != h->n_freq ||
-        hd.decim != h->decim)
+        hd.decim != h->decim || hd.map_k != (h->map ? h->map_k : -1))
         return fail(h, MBF_EINVAL, "state image does not match this handle");
     const size_t body = need - sizeof(uint64_t);
     uint64_t cs;
@@ -1516,6 +1668,11 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n) {
         const size_t rb = h->esz * (size_t)h->n_probes * h->decim;
         HIPCHK(h, hipMemcpy(h->d_ring, p + off, rb, hipMemcpyHostToDevice));
         off += rb;
+    }
+    if (h->map) {
+        HIPCHK(h, hipMemcpy(h->map, p + off, map_bytes(h), hipMemcpyHostToDevice));
+        off += map_bytes(h);
+        h->map_start = hd.map_start;
     }
     HIPCHK(h, hipMemcpy(h->ctl, &hd.ctl, sizeof(mbf::Ctl), hipMemcpyHostToDevice));
     h->step = hd.step;
@@ -2032,6 +2189,11 @@ struct AdjBuffers {
 // The soft-source value added during step n, as the forward computes it.
 double host_source_value(const mbf_handle* h, int64_t n) {
     if (!h->src_on) return 0.0;
+    if (h->src_kind == 1) {
+        const double t = (double)(n + 1) * h->co.dt;
+        const double q = t / h->src_tp;
+        return h->src_amp * (1.0 - std::exp(-q * q)) * std::sin(h->src_ws * t);
+    }
     const double t = (double)(n + 1) * h->co.dt - h->src_t0;
     const double q = t / h->src_tp;
     return h->src_amp * std::sin(h->src_ws * t) * std::exp(-q * q);

@@ -65,8 +65,9 @@ struct SimView {
     int noise;
     int frozen_pop;
     uint32_t seed_lo, seed_hi, realization;
-    // soft source
-    int src_on, src_comp, src_i, src_j, src_k;
+    // soft source: src_kind 0 is the Gaussian pulse (src_tp its width, src_t0
+    // its centre), 1 the continuous wave switched on over src_tp
+    int src_on, src_kind, src_comp, src_i, src_j, src_k;
     double src_amp, src_ws, src_tp, src_t0, dt;
     // loss box
     int box_on, box[6];
@@ -93,6 +94,10 @@ struct SimView {
     T* ring;                  // n_probes x decim samples
     const double* omega;
     double* spec;             // n_probes x n_freq x 2
+    // energy density of the cells of plane z = map_k summed over steps
+    // (nx x ny, x fastest; map == nullptr: off)
+    double* map;
+    int map_k;
 };
 
 // ------------------------------------------------------------------ Philox
@@ -280,6 +285,11 @@ __device__ __forceinline__ T h_update(T h, T S, T curl, T a) {
 
 template <typename T>
 __device__ __forceinline__ T source_value(const SimView<T>& v, int64_t n) {
+    if (v.src_kind == 1) {
+        const double t = (double)(n + 1) * v.dt;
+        const double q = t / v.src_tp;
+        return (T)(v.src_amp * (1.0 - exp(-q * q)) * sin(v.src_ws * t));
+    }
     const double t = (double)(n + 1) * v.dt - v.src_t0;
     const double q = t / v.src_tp;
     return (T)(v.src_amp * sin(v.src_ws * t) * exp(-q * q));
@@ -326,6 +336,18 @@ __device__ __forceinline__ void batch_item(const uint32_t* __restrict__ items, i
     const uint32_t e = items[blockIdx.x];
     r = (int)(e >> 24);
     w = (int)(e & 0xFFFFFFu);
+}
+
+// Energy density of cell (i, j) of the monitored plane from the cell's own
+// sites, 1/2 [eps_r |E^n|^2 + |H^{n+1/2}|^2], added to its FP64 sum (one lane
+// owns each cell of the plane).
+template <typename T>
+__device__ __forceinline__ void plane_energy(const SimView<T>& v, int i, int j, T eps, T ex, T ey, T ez,
+                                             T hx, T hy, T hz) {
+    const double e2 = ((double)ex * (double)ex + (double)ey * (double)ey) + (double)ez * (double)ez;
+    const double h2 = ((double)hx * (double)hx + (double)hy * (double)hy) + (double)hz * (double)hz;
+    const uint32_t c = (uint32_t)i + (uint32_t)v.nx * (uint32_t)j;
+    sto(v.map, c, gld(v.map + c) + 0.5 * ((double)eps * e2 + h2));
 }
 
 // ---------------------------------------------------------------- row a1
@@ -401,6 +423,7 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             sto(f.hn[1], x, nhy);
             sto(f.hn[2], x, nhz);
             const T eps = gld(v.lut_eps + P.m);
+            if (v.map != nullptr && k == v.map_k) plane_energy(v, i, j, eps, ex, ey, ez, nhx, nhy, nhz);
             T acc = (T)0;
             if (j >= 1 && k >= 1) acc += eps * ex * ex;
             if (i >= 1 && k >= 1) acc += eps * ey * ey;
@@ -721,6 +744,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 sto(f.hn[1], x, nhy);
                 sto(f.hn[2], x, nhz);
                 const T eps = gld(v.lut_eps + m);
+                if (v.map != nullptr && k == v.map_k) plane_energy(v, i, j, eps, ex, ey, ez, nhx, nhy, nhz);
                 T acc = (T)0;
                 if (j >= 1 && k >= 1) acc += eps * ex * ex;
                 if (i >= 1 && k >= 1) acc += eps * ey * ey;

@@ -175,4 +175,67 @@ __global__ void __launch_bounds__(kStatThreads) k_spec_stats(const double* __res
     *out = o;
 }
 
+// Peaks of S (the long-lived modes of a passive spectrum, Fig. 1): bins with
+// S_k > 0, S_k >= min_rel * max S, S_{k-1} < S_k >= S_{k+1} (an edge bin
+// compares with its one neighbour; a flat top counts once, at its first bin),
+// listed by decreasing S_k (equal values: lower k first), at most max_peaks.
+// One workgroup; round r takes the largest candidate below the previous one
+// in that order.
+__global__ void __launch_bounds__(kStatThreads) k_spec_peaks(const double* __restrict__ pw, int nf, double min_rel,
+                                                            int max_peaks, int32_t* __restrict__ bins,
+                                                            int32_t* __restrict__ count) {
+    __shared__ double sh[kStatThreads / 64];
+    __shared__ double shv[kStatThreads / 64];
+    __shared__ int shk[kStatThreads / 64];
+    const int t = (int)threadIdx.x;
+    double top = -1.0;
+    int tk = nf;
+    for (int k = t; k < nf; k += kStatThreads) stat_max(top, tk, pw[k], k);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(top, o, 64);
+        const int k2 = __shfl_xor(tk, o, 64);
+        stat_max(top, tk, v2, k2);
+    }
+    if ((t & 63) == 0) shv[t >> 6] = top;
+    (void)stat_sum(0.0, sh);                          // barrier: shv published
+    double smax = shv[0];
+    for (int w = 1; w < kStatThreads / 64; ++w) smax = fmax(smax, shv[w]);
+    const double thr = min_rel * smax;
+    double pv = INFINITY;                             // previous pick (value, bin)
+    int pk = -1;
+    int found = 0;
+    for (int r = 0; r < max_peaks; ++r) {
+        double best = -1.0;
+        int bk = nf;
+        for (int k = t; k < nf; k += kStatThreads) {
+            const double v = pw[k];
+            const bool is_peak = v > 0.0 && v >= thr && (k == 0 || pw[k - 1] < v) && (k == nf - 1 || v >= pw[k + 1]);
+            const bool below = v < pv || (v == pv && k > pk);
+            if (is_peak && below) stat_max(best, bk, v, k);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(best, o, 64);
+            const int k2 = __shfl_xor(bk, o, 64);
+            stat_max(best, bk, v2, k2);
+        }
+        __syncthreads();                              // readers of the previous round are done
+        if ((t & 63) == 0) {
+            shv[t >> 6] = best;
+            shk[t >> 6] = bk;
+        }
+        __syncthreads();
+        best = shv[0];
+        bk = shk[0];
+        for (int w = 1; w < kStatThreads / 64; ++w) stat_max(best, bk, shv[w], shk[w]);
+        if (best < 0.0) break;                        // uniform: no candidate left
+        if (t == 0) bins[r] = bk;
+        pv = best;
+        pk = bk;
+        found = r + 1;
+    }
+    if (t == 0) *count = found;
+}
+
 }  // namespace mbf

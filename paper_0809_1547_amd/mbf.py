@@ -133,6 +133,12 @@ def _load():
         "mbf_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
         "mbf_spectral_stats": (I, [VP, I, I, VP, D, I, VP, C.POINTER(mbf_spec_stats)]),
         "mbf_batch_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
+        "mbf_spectrum_peaks": (I, [P, D, I, VP, C.POINTER(C.c_int)]),
+        "mbf_spectral_peaks": (I, [VP, I, I, D, I, I, VP, VP, C.POINTER(C.c_int)]),
+        "mbf_add_cw_source": (I, [P, I, I, I, I, D, D, D]),
+        "mbf_set_plane_monitor": (I, [P, I]),
+        "mbf_reset_plane_monitor": (I, [P]),
+        "mbf_read_plane_monitor": (I, [P, dp, C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -153,7 +159,8 @@ EXPORTED = [
     "mbf_batch_member", "mbf_batch_set_tuning", "mbf_batch_get_tuning", "mbf_batch_step",
     "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes", "mbf_autotune",
     "mbf_batch_autotune", "mbf_adjoint_run", "mbf_spectrum_stats", "mbf_spectral_stats",
-    "mbf_batch_spectrum_stats",
+    "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
+    "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor",
 ]
 
 
@@ -301,6 +308,48 @@ def mbf_spectral_stats(spec, omega, level: float = 0.5, stream: Optional[int] = 
     _check(lib.mbf_spectral_stats(ps, spec.shape[0], spec.shape[1], pw, float(level), ks,
                                   C.c_void_p(stream or 0), C.byref(o)))
     return _stats_dict(o)
+
+
+def mbf_spectrum_peaks(h: int, min_rel: float = 0.1, max_peaks: int = 16) -> list:
+    bins = np.zeros(max_peaks, dtype=np.int32)
+    cnt = C.c_int()
+    _check(lib.mbf_spectrum_peaks(h, float(min_rel), int(max_peaks), bins.ctypes.data, C.byref(cnt)), h)
+    return [int(b) for b in bins[:cnt.value]]
+
+
+def mbf_spectral_peaks(spec, min_rel: float = 0.1, max_peaks: int = 16, stream: Optional[int] = None) -> list:
+    """Peaks of caller amplitudes (layouts as mbf_spectral_stats)."""
+    if isinstance(spec, np.ndarray) and np.iscomplexobj(spec):
+        spec = np.ascontiguousarray(np.stack([spec.real, spec.imag], axis=-1), dtype=np.float64)
+    if isinstance(spec, np.ndarray):
+        spec = np.ascontiguousarray(spec, dtype=np.float64)
+    if len(spec.shape) != 3 or spec.shape[-1] != 2:
+        raise ValueError("spec must be (n_probes, n_freq, 2)")
+    ps, ks, _a = _ptr_kind(spec)
+    bins = np.zeros(max_peaks, dtype=np.int32)
+    cnt = C.c_int()
+    _check(lib.mbf_spectral_peaks(ps, spec.shape[0], spec.shape[1], float(min_rel), int(max_peaks), ks,
+                                  C.c_void_p(stream or 0), bins.ctypes.data, C.byref(cnt)))
+    return [int(b) for b in bins[:cnt.value]]
+
+
+def mbf_add_cw_source(h, comp, i, j, k, amp=1.0, lambda_s=586.5e-9, t_ramp=20e-15):
+    _check(lib.mbf_add_cw_source(h, comp, i, j, k, amp, lambda_s, t_ramp), h)
+
+
+def mbf_set_plane_monitor(h: int, k: int) -> None:
+    _check(lib.mbf_set_plane_monitor(h, int(k)), h)
+
+
+def mbf_reset_plane_monitor(h: int) -> None:
+    _check(lib.mbf_reset_plane_monitor(h), h)
+
+
+def mbf_read_plane_monitor(h: int, nx: int, ny: int) -> Tuple[np.ndarray, int]:
+    out = np.zeros((ny, nx))
+    cnt = C.c_int64()
+    _check(lib.mbf_read_plane_monitor(h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)), h)
+    return out, cnt.value
 
 
 def mbf_read_loss(h: int) -> float:
@@ -560,6 +609,23 @@ class Sim:
         """Peak, standard deviation and Gaussian fit of the probe-summed
         power spectrum (dict of the mbf_spec_stats fields)."""
         return mbf_spectrum_stats(self.h, level)
+
+    def spectrum_peaks(self, min_rel=0.1, max_peaks=16):
+        """Bins of the peaks of the probe-summed power spectrum, largest first."""
+        return mbf_spectrum_peaks(self.h, min_rel, max_peaks)
+
+    def set_cw_source(self, comp, i, j, k, amp=1.0, lambda_s=586.5e-9, t_ramp=20e-15):
+        mbf_add_cw_source(self.h, comp, i, j, k, amp, lambda_s, t_ramp)
+
+    def set_plane_monitor(self, k):
+        mbf_set_plane_monitor(self.h, k)
+
+    def reset_plane_monitor(self):
+        mbf_reset_plane_monitor(self.h)
+
+    def plane_monitor(self):
+        """(sums of the energy density of the monitored plane (ny, nx), steps)."""
+        return mbf_read_plane_monitor(self.h, self.cfg.nx, self.cfg.ny)
 
     def set_tuning(self, variant="two_pass", tile_y=4, zseg=0, xcd_remap=2, group_mb=0):
         mbf_set_tuning(self.h, _VARIANTS[variant], tile_y, zseg, xcd_remap, group_mb)

@@ -133,3 +133,33 @@ def test_fit_weights_are_the_squared_spectrum():
     X = np.stack([np.ones_like(x), x, x * x])
     assert np.max(np.abs(X @ (u * u * r))) < 1e-10
     assert np.max(np.abs(X @ (u * r))) > 1e-4
+
+
+def test_peaks_hand_worked():
+    # local maxima 1 (value 5), 4 (9), 7 (plateau 6, 6: first bin), edge 9 (7)
+    Sk = [1.0, 5.0, 2.0, 3.0, 9.0, 4.0, 1.0, 6.0, 6.0, 7.0]
+    F = one_probe(Sk)
+    assert S.spectral_peaks(F, 0.0, 10) == [4, 9, 7, 1]
+    assert S.spectral_peaks(F, 0.0, 2) == [4, 9]
+    assert S.spectral_peaks(F, 0.6, 10) == [4, 9, 7]          # 5 < 0.6 * 9
+    # the rule is local: the first bin of a flat run counts when nothing
+    # higher follows right away (the run [3, 3] at the band edge), a falling
+    # band edge counts, a flat run after a rise counts at its first bin only
+    assert S.spectral_peaks(one_probe([3.0, 3.0, 5.0, 1.0]), 0.0, 5) == [2, 0]
+    assert S.spectral_peaks(one_probe([8.0, 3.0, 3.0, 1.0]), 0.0, 5) == [0]
+    assert S.spectral_peaks(one_probe([1.0, 4.0, 4.0, 4.0, 2.0]), 0.0, 5) == [1]
+    assert S.spectral_peaks(np.zeros((2, 6), dtype=np.complex128), 0.0, 5) == []
+
+
+def test_peaks_of_separated_lines():
+    # three Gaussian lines of distinct heights on a quiet floor: one peak each,
+    # in order of height, at the sample nearest each centre
+    om = np.linspace(0.0, 1.0, 1001)
+    lines = [(0.21, 0.01, 2.0), (0.55, 0.02, 5.0), (0.80, 0.005, 1.0)]
+    Sk = sum(gaussian(om, A, mu, sg) for (mu, sg, A) in lines)
+    got = S.spectral_peaks(one_probe(Sk), 0.05, 8)
+    want = [int(np.argmin(np.abs(om - mu))) for (mu, _, _) in sorted(lines, key=lambda l: -l[2])]
+    assert got == want
+    # equal heights: lower bin first
+    Sk = gaussian(om, 1.0, 0.3, 0.01) + gaussian(om, 1.0, 0.7, 0.01)
+    assert S.spectral_peaks(one_probe(Sk), 0.5, 8) == [300, 700]
