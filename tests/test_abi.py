@@ -57,6 +57,19 @@ def test_create_rejects_bad_configs_before_allocating(field, value, code):
     assert e.value.code == code
 
 
+@pytest.mark.parametrize("n,precision", [((16, 65535, 16), "fp32"), ((16, 16, 70000), "fp32"),
+                                         ((1100, 1100, 1100), "fp32"), ((820, 820, 820), "fp64")])
+def test_create_rejects_grids_beyond_the_limits(n, precision):
+    # 16-bit grid rows/planes of the launch and 32-bit site offsets: ny, nz <
+    # 65535 and one site array below 4 GiB, checked before any allocation
+    from paper_0809_1547_amd import mbf
+    c = mbf.mbf_config_default(*n)
+    c.precision = mbf.MBF_FP64 if precision == "fp64" else mbf.MBF_FP32
+    with pytest.raises(mbf.MbfError) as e:
+        mbf.mbf_create(c)
+    assert e.value.code == mbf.MBF_EINVAL
+
+
 def test_create_bad_boundary():
     from paper_0809_1547_amd import mbf
     c = mbf.mbf_config_default(8, 8, 8)
