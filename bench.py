@@ -65,7 +65,7 @@ def parse():
                     help="write the calibrated HBM traffic summary of --kernel from two rocprofv3 "
                          "--pmc runs (FETCH_SIZE, WRITE_SIZE, each with --calib-copy) and exit")
     ap.add_argument("--kernel", default="k_curl_e_batch")
-    ap.add_argument("--tuning", default="two_pass/4/4/2",
+    ap.add_argument("--tuning", default="two_pass/4/2/2",
                     help="variant/tile_y/zseg/xcd_remap the counter runs used")
     return ap.parse_args()
 
@@ -332,6 +332,9 @@ def main():
         log(f"autotuned: {tuning}")
     else:
         batch, cells, config, extra = c5_batch(args, I, mbf, stream)
+        # the schedule a sweep picks at this size: two passes, tiles of 64 x 4
+        # columns over 2-plane segments, layers dealt to the XCDs in turn
+        batch.set_tuning("two_pass", tile_y=4, zseg=2, xcd_remap=2)
         tuning = batch.tuning()
     config["tuning"] = tuning
     batch.step(args.warmup)
