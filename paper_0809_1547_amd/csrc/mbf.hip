@@ -96,6 +96,7 @@ struct mbf_handle {
     void* tap = nullptr;      // trajectory recording buffer of the adjoint (nullptr: off)
     int64_t tap_stride = 0;   // values per trajectory slot
     int64_t tap_base = 0;     // host copy of ctl->tap_base
+    int64_t adj_n_host = 0;   // host copy of ctl->adj_n
     // device copy of the view, geometry and work table the step kernels read
     void* d_view = nullptr;
     mbf::Geom* d_geom = nullptr;
@@ -1556,7 +1557,7 @@ struct StateHeader {
     double Na_si;
     mbf::Ctl ctl;
 };
-constexpr uint64_t kMagic = 0x3246424D5F54534Bull;
+constexpr uint64_t kMagic = 0x3346424D5F54534Bull;
 }  // namespace
 
 int mbf_state_size(const mbf_handle* h, size_t* out) {
@@ -2170,12 +2171,16 @@ namespace {
 struct AdjBuffers {
     std::vector<Snap> ckpt;
     Snap end;
-    void* traj = nullptr;       // K+1 slots of (E dense x3, P compact x3, N1 x3, N2 x3) + one P slot
-    void* adj = nullptr;        // et x3, hb x3 (dense), lp x3, lq x3, ln x9 (compact)
+    void* traj = nullptr;       // K+1 slots of (E dense x3, dP compact x3, N1 - N2 compact x3)
+    void* adj = nullptr;        // u x3, hb x3 (dense), lp x3, lq x3, ln x9 (compact)
     double* g_eps = nullptr;
     double* g_na = nullptr;
     double* g_pop = nullptr;
+    hipGraphExec_t rev = nullptr;   // K reverse steps, captured once
+    void* dview = nullptr;          // the run's view, read by the reverse-step kernels
     ~AdjBuffers() {
+        if (rev) hipGraphExecDestroy(rev);
+        if (dview) hipFree(dview);
         for (Snap& q : ckpt) snap_free(q);
         snap_free(end);
         if (traj) hipFree(traj);
@@ -2185,19 +2190,6 @@ struct AdjBuffers {
         if (g_pop) hipFree(g_pop);
     }
 };
-
-// The soft-source value added during step n, as the forward computes it.
-double host_source_value(const mbf_handle* h, int64_t n) {
-    if (!h->src_on) return 0.0;
-    if (h->src_kind == 1) {
-        const double t = (double)(n + 1) * h->co.dt;
-        const double q = t / h->src_tp;
-        return h->src_amp * (1.0 - std::exp(-q * q)) * std::sin(h->src_ws * t);
-    }
-    const double t = (double)(n + 1) * h->co.dt - h->src_t0;
-    const double q = t / h->src_tp;
-    return h->src_amp * std::sin(h->src_ws * t) * std::exp(-q * q);
-}
 
 // Turn trajectory recording on (buffer) or off (nullptr); slot 0 is the state
 // at step `base`.
@@ -2299,14 +2291,26 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     v.seed_lo = (uint32_t)(c.seed & 0xFFFFFFFFull);
     v.seed_hi = (uint32_t)(c.seed >> 32);
     v.realization = c.realization;
-    v.src_on = h->src_on; v.src_comp = h->src_comp;
+    v.src_on = h->src_on; v.src_kind = h->src_kind; v.src_comp = h->src_comp;
     v.src_i = h->src_i; v.src_j = h->src_j; v.src_k = h->src_k;
+    v.src_amp = h->src_amp; v.src_ws = h->src_ws; v.src_tp = h->src_tp; v.src_t0 = h->src_t0;
+    v.dt = h->co.dt;
     for (int q = 0; q < 6; ++q) v.box[q] = h->box[q];
-    char* traj = (char*)B.traj;
-    auto sE = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot) + (size_t)cc * h->nsite; };
-    auto sdP = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot + E3 * esz) + (size_t)cc * h->glen; };
-    auto sdN = [&](int64_t q, int cc) { return (T*)(traj + (size_t)q * slot + (E3 + C3) * esz) + (size_t)cc * h->glen; };
+    v.traj = (const T*)B.traj;
+    v.slot = (int64_t)(slot / esz);
+    v.tap_e = h->nsite;
+    v.tap_c = h->glen;
+    v.ctl = h->ctl;
+    if (hipMalloc(&B.dview, sizeof(v)) != hipSuccess) return fail(h, MBF_ENOMEM, "device allocation for the adjoint failed");
+    HIPCHK(h, hipMemcpy(B.dview, &v, sizeof(v), hipMemcpyHostToDevice));
+    const mbf::AdjView<T>* dv = reinterpret_cast<const mbf::AdjView<T>*>(B.dview);
     const dim3 gblk((unsigned)gm.nblk), tb(64, 4);
+    // one reverse step: the H part, the E part, then step n - 1
+    auto reverse_step = [&]() {
+        hipLaunchKernelGGL((mbf::k_adj_h<T, 4>), gblk, tb, 0, h->stream, dv, gm);
+        hipLaunchKernelGGL((mbf::k_adj_e<T, 4>), gblk, tb, 0, h->stream, dv, gm);
+        hipLaunchKernelGGL(mbf::k_adj_next, dim3(1), dim3(64), 0, h->stream, h->ctl);
+    };
     for (int64_t sg = nseg - 1; sg >= 0 && !rc; --sg) {
         const int64_t n0 = sg * K, kp = std::min<int64_t>(K, nsteps - n0);
         if (sg != nseg - 1) {                          // recompute and record the segment
@@ -2314,24 +2318,31 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
             if (!rc) rc = set_tap<T>(h, B.traj, n0);
             if (!rc) rc = run_steps(h, kp, nullptr);
             if (rc) break;
-        } else {                                       // etot = 2 E^N in the box
-            for (int q = 0; q < 3; ++q) v.E1[q] = sE(kp, q);
+        }
+        // the reverse sweep starts at step n0 + kp - 1 (slot kp - 1 of the
+        // segment, whose slot 0 is step n0 = ctl->tap_base)
+        h->adj_n_host = n0 + kp - 1;
+        HIPCHK(h, hipMemcpyAsync(&h->ctl->adj_n, &h->adj_n_host, sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+        if (sg == nseg - 1)                           // etot = 2 E^N in the box
             hipLaunchKernelGGL(mbf::k_adj_seed<T>, dim3((unsigned)((c.nx + 64) / 64), (unsigned)(c.ny + 1), (unsigned)(c.nz + 1)),
                                dim3(64), 0, h->stream, v);
-        }
-        for (int64_t n = n0 + kp - 1; n >= n0; --n) {
-            const int64_t q = n - n0;
-            for (int cc = 0; cc < 3; ++cc) {
-                v.E0[cc] = sE(q, cc);
-                v.E1[cc] = sE(q + 1, cc);
-                v.dP0[cc] = sdP(q, cc);
-                v.dP1[cc] = sdP(q + 1, cc);
-                v.dN[cc] = sdN(q, cc);
+        if (kp == K) {                                 // a whole segment: the captured sequence
+            if (!B.rev) {
+                hipGraph_t g = nullptr;
+                HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+                for (int q = 0; q < K; ++q) reverse_step();
+                const hipError_t e = hipStreamEndCapture(h->stream, &g);
+                if (e != hipSuccess) return fail(h, MBF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+                const hipError_t ei = hipGraphInstantiate(&B.rev, g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    B.rev = nullptr;
+                    return fail(h, MBF_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+                }
             }
-            v.n = n;
-            v.src = (T)host_source_value(h, n);
-            hipLaunchKernelGGL((mbf::k_adj_h<T, 4>), gblk, tb, 0, h->stream, v, gm);
-            hipLaunchKernelGGL((mbf::k_adj_e<T, 4>), gblk, tb, 0, h->stream, v, gm);
+            HIPCHK(h, hipGraphLaunch(B.rev, h->stream));
+        } else {
+            for (int64_t q = 0; q < kp; ++q) reverse_step();
         }
         if (hipGetLastError() != hipSuccess) rc = fail(h, MBF_EHIP, "adjoint kernel launch failed");
     }

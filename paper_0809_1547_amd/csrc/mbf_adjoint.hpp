@@ -27,12 +27,13 @@ namespace mbf {
 
 template <typename T>
 struct AdjView {
-    // forward trajectory around the step n being reversed
-    const T* E0[3];      // E^n (dense)
-    const T* E1[3];      // E^{n+1}
-    const T* dP0[3];     // P^n - P^{n-1} (compact)
-    const T* dP1[3];     // P^{n+1} - P^n
-    const T* dN[3];      // N1^n - N2^n
+    // forward trajectory: slot q = m - ctl->tap_base of `slot` values holds
+    // E^m (3 x tap_e dense), P^m - P^{m-1} (3 x tap_c compact) and N1^m - N2^m
+    // (3 x tap_c compact); the step being reversed is n = ctl->adj_n, so one
+    // captured sequence of reverse steps serves every segment
+    const T* traj;
+    int64_t slot, tap_e, tap_c;
+    Ctl* ctl;
     // adjoint state, updated in place
     T* u[3];             // in: cb ie etot of E^{n+1}; out: of E^n (for step n-1); zero off the interior
     T* hb[3];            // htot of the previous reverse step on entry, of this one on exit
@@ -55,11 +56,33 @@ struct AdjView {
     T ck_esp;            // d c_F / d(N_a/N_ref) = ck E_sp (0 without noise)
     int noise;
     uint32_t seed_lo, seed_hi, realization;
-    int64_t n;           // index of the step being reversed
-    T src;               // soft-source value of step n (at its site)
-    int src_on, src_comp, src_i, src_j, src_k;
+    // soft source of the forward run (its value at step n is formed again)
+    int src_on, src_kind, src_comp, src_i, src_j, src_k;
+    double src_amp, src_ws, src_tp, src_t0, dt;
     int box[6];
 };
+
+// Trajectory slots of steps n and n+1 for the step n = ctl->adj_n.
+template <typename T>
+struct AdjSlot {
+    const T* s0;
+    const T* s1;
+    int64_t n;
+};
+
+template <typename T>
+__device__ __forceinline__ AdjSlot<T> adj_slot(const AdjView<T>& v) {
+    AdjSlot<T> a;
+    a.n = gld(&v.ctl->adj_n);
+    a.s0 = v.traj + (a.n - gld(&v.ctl->tap_base)) * v.slot;
+    a.s1 = a.s0 + v.slot;
+    return a;
+}
+
+// The reverse sweep moves to step n - 1 (one thread, after the step's kernels).
+__global__ void __launch_bounds__(64) k_adj_next(Ctl* ctl) {
+    if (threadIdx.x == 0) ctl->adj_n = ctl->adj_n - 1;
+}
 
 template <typename T>
 __device__ __forceinline__ T adj_loss_e(const AdjView<T>& v, int c, int i, int j, int k) {
@@ -81,8 +104,12 @@ __device__ __forceinline__ bool e_in(const AdjView<T>& v, int c, int i, int j, i
 
 
 // H part: htot = da htot_prev + S curl+(u) on the H-sites of [0,n)^3.
+// The view of a run lives in device memory and is read through a no-alias
+// pointer (constant over the run), so its fields stay out of the kernel
+// arguments and scalar registers.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_adj_h(AdjView<T> v, Geom gm) {
+__global__ void __launch_bounds__(64 * TY) k_adj_h(const AdjView<T>* __restrict__ vp, Geom gm) {
+    const AdjView<T>& v = *vp;
     int bx, by, bz;
     decode_item(gm, xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap), bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
@@ -129,8 +156,8 @@ struct AdjPlane {
 // are not used); the y-1 and x-1 neighbours only exist for j >= 1 and i >= 1
 // (the offsets would wrap below zero otherwise).
 template <typename T>
-__device__ __forceinline__ void adj_load_plane(AdjPlane<T>& p, const AdjView<T>& v, uint32_t x, uint32_t cell,
-                                               uint32_t gi, bool g, int i, int j, int k) {
+__device__ __forceinline__ void adj_load_plane(AdjPlane<T>& p, const AdjView<T>& v, const AdjSlot<T>& a, uint32_t x,
+                                               uint32_t cell, uint32_t gi, bool g, int i, int j, int k) {
     const uint32_t sx = (uint32_t)v.sx;
     p.hx = ldo(v.hb[0], x); p.hy = ldo(v.hb[1], x); p.hz = ldo(v.hb[2], x);
     p.hz_y = j >= 1 ? ldo(v.hb[2], x - sx) : (T)0;
@@ -140,17 +167,17 @@ __device__ __forceinline__ void adj_load_plane(AdjPlane<T>& p, const AdjView<T>&
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         p.u[c] = ldo(v.u[c], x);
-        p.E[c] = ldo(v.E0[c], x);
-        p.En[c] = ldo(v.E1[c], x);
+        p.E[c] = ldo(a.s0 + c * v.tap_e, x);
+        p.En[c] = ldo(a.s1 + c * v.tap_e, x);
         const bool gs = g && e_in(v, c, i, j, k);
-        p.dPf[c] = gs ? ldo(v.dP1[c], gi) : (T)0;
-        p.dN[c] = gs ? ldo(v.dN[c], gi) : (T)0;
+        p.dPf[c] = gs ? ldo(a.s1 + 3 * v.tap_e + c * v.tap_c, gi) : (T)0;
+        p.dN[c] = gs ? ldo(a.s0 + 3 * v.tap_e + (3 + c) * v.tap_c, gi) : (T)0;
         p.n1[c] = gs ? ldo(v.ln[0][c], gi) : (T)0;
         p.n2[c] = gs ? ldo(v.ln[1][c], gi) : (T)0;
         p.n3[c] = gs ? ldo(v.ln[2][c], gi) : (T)0;
         p.lp[c] = gs ? ldo(v.lp[c], gi) : (T)0;
         p.lq[c] = gs ? ldo(v.lq[c], gi) : (T)0;
-        p.dPp[c] = gs ? ldo(v.dP0[c], gi) : (T)0;
+        p.dPp[c] = gs ? ldo(a.s0 + 3 * v.tap_e + c * v.tap_c, gi) : (T)0;
     }
     p.ge = gld(v.g_eps + cell);
 }
@@ -167,7 +194,8 @@ __device__ __forceinline__ T adj_db(const AdjView<T>& v, int c, int i, int j, in
 // wave owns one row and marches along z (htot of Hx, Hy at k-1 stays in
 // registers); a plane's loads all go out before its arithmetic and stores.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
+__global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict__ vp, Geom gm) {
+    const AdjView<T>& v = *vp;
     __shared__ double sh[TY];
     const int w = xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap);
     int bx, by, bz;
@@ -175,6 +203,8 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    const AdjSlot<T> a = adj_slot(v);
+    const T src = v.src_on ? (T)source_at(v, a.n) : (T)0;   // the forward's value at step n
     double gna = 0.0;
     if (j < v.ny) {
         const bool act = i < v.nx;
@@ -193,7 +223,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
         }
         for (int k = kz0; k < kz1; ++k, x += sxy, cell += pcell) {
             AdjPlane<T> P;
-            adj_load_plane(P, v, x, cell, gi, act && m >= kGainId, i, j, k);
+            adj_load_plane(P, v, a, x, cell, gi, act && m >= kGainId, i, j, k);
             uint32_t gi_n = 0;
             uint8_t m_nn = 0;
             if (k + 1 < kz1) {
@@ -208,7 +238,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
                 const T ie = gld(v.lut_inv_eps + m);
                 double geps = 0.0;
                 T xi[3] = {(T)0, (T)0, (T)0};
-                if (g && v.noise) noise3(v, cell, (uint32_t)v.n, xi);
+                if (g && v.noise) noise3(v, cell, (uint32_t)a.n, xi);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (!e_in(v, c, i, j, k)) continue;
@@ -250,10 +280,10 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(AdjView<T> v, Geom gm) {
                         dP_prev = P.dPp[c];
                     }
                     // E^{n+1} = ca E^n + cb ie (S curl- H' - dP) + src: its eps derivative
-                    const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? v.src : (T)0;
+                    const T s = (v.src_on && c == v.src_comp && i == v.src_i && j == v.src_j && k == v.src_k) ? src : (T)0;
                     geps += (double)et * (double)((En - ca * E) - s) * (double)(-ie);
                     // loss term of E^n and the work term of step n-1
-                    if (v.n >= 1) {
+                    if (a.n >= 1) {
                         if (i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5])
                             lam += (T)2 * E;
                         lam += Wh_prev * v.beta * (T)0.5 * dP_prev;
@@ -281,6 +311,7 @@ __global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
     if (i > v.nx) return;
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
     const bool inb = i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5];
+    const AdjSlot<T> a = adj_slot(v);                 // n = N - 1: slot N holds E^N
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         T u = (T)0;
@@ -288,7 +319,7 @@ __global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
             const T ie = gld(v.lut_inv_eps + ldo(v.mat, x));
             T cb = (T)1;
             if (v.has_layer) cb = recip((T)1 + adj_loss_e(v, c, i, j, k));
-            u = cb * ie * ((T)2 * ldo(v.E1[c], x));
+            u = cb * ie * ((T)2 * ldo(a.s1 + c * v.tap_e, x));
         }
         sto(v.u[c], x, u);
     }

@@ -39,6 +39,7 @@ struct Ctl {                  // per-simulation control block (device memory)
     int32_t pad;
     double src_val;           // soft-source value added during the current step
     int64_t tap_base;         // step of trajectory slot 0 while a trajectory is recorded
+    int64_t adj_n;            // step the reverse sweep is taking back
 };
 
 template <typename T>
@@ -283,16 +284,21 @@ __device__ __forceinline__ T h_update(T h, T S, T curl, T a) {
     return ca * h - cb * (S * curl);
 }
 
-template <typename T>
-__device__ __forceinline__ T source_value(const SimView<T>& v, int64_t n) {
+template <typename V>
+__device__ __forceinline__ double source_at(const V& v, int64_t n) {
     if (v.src_kind == 1) {
         const double t = (double)(n + 1) * v.dt;
         const double q = t / v.src_tp;
-        return (T)(v.src_amp * (1.0 - exp(-q * q)) * sin(v.src_ws * t));
+        return v.src_amp * (1.0 - exp(-q * q)) * sin(v.src_ws * t);
     }
     const double t = (double)(n + 1) * v.dt - v.src_t0;
     const double q = t / v.src_tp;
-    return (T)(v.src_amp * sin(v.src_ws * t) * exp(-q * q));
+    return v.src_amp * sin(v.src_ws * t) * exp(-q * q);
+}
+
+template <typename T>
+__device__ __forceinline__ T source_value(const SimView<T>& v, int64_t n) {
+    return (T)source_at(v, n);
 }
 
 // Work decomposition of the step kernels: tiles of 64 x TY columns cut into
