@@ -398,6 +398,35 @@ int mbf_load_state(mbf_handle* h, const void* buf, size_t n);
 int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_kind, double* grad_Na,
                     double* loss);
 
+/* -------------------------------------------- Gross-Pitaevskii / ST law
+ * The theory of the Gross-Pitaevskii section: the oscillation condition of
+ * the random laser in dimensionless form (Eq. g5),
+ *     -phi'' + tau^2 phi + phi^3 = E phi,
+ * whose positive bound state exists for E > 1, with E = (p - 1)/(kappa
+ * sqrt(p)) (Eq. ee, p the pump relative to the high-Q loss) and the
+ * threshold E = 1 at p_th = 1 + kappa^2/2 + kappa sqrt(4 + kappa^2)/2.
+ * mbf_gp_solve solves it for n_E eigenvalues at once (one workgroup each) on
+ * M interior points tau_i = -L + (i+1) h, h = 2L/(M+1), phi(+-L) = 0,
+ * second differences: a semi-implicit gradient flow from the near-threshold
+ * Gaussian (E < 3) or the Thomas-Fermi profile, then Newton steps to an update
+ * below 1e-13 of max phi.  For each E it returns phi (M values), the spectrum
+ * S_k = phit(nu_k)^2 with phit(nu) = (h/2pi) sum_i phi_i cos(nu tau_i), nu_k =
+ * k dnu (n_nu values), and 7 statistics: N = h sum phi^2, the spectral waist
+ * w = sigma_nu/(2 pi) (sigma_nu^2 the second moment of the even spectrum; a
+ * Gaussian exp(-nu^2/(8 pi^2 w^2)) has waist w; w -> 1/(2 sqrt(2) pi) at
+ * threshold), the peak S(0), max phi, the largest residual of the discrete
+ * equation, the Newton steps taken and a converged flag (1/0).  In real units
+ * (Eq. s1 and below) W = w sqrt(kappa) / (p^{1/4} t_g), S_peak = t_g^2 S(0) /
+ * gamma_S.  E[n_E], phi[n_E*M], spec[n_E*n_nu], stats[n_E*7]: all host or
+ * all device memory per mem_kind, caller-owned; runs on `stream` and returns
+ * when the results are in place.  1 <= n_E <= 65535, 3 <= M <= 1023, L > 0,
+ * n_nu >= 1, dnu > 0, every E > 1 (MBF_EINVAL otherwise). */
+int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu, int mem_kind, void* stream,
+                 double* phi, double* spec, double* stats);
+/* E(p) of Eq. ee and the threshold pump p_th (E = 1). */
+double mbf_gp_eigenvalue(double p, double kappa);
+double mbf_gp_threshold(double kappa);
+
 /* ---------------------------------------------------------------- batches
  * Many realizations advanced together (Simulations section: the emission is
  * studied over several sphere packings and pump levels N_a).  A batch owns R

@@ -21,6 +21,7 @@
 #include "mbf_kernels.hpp"
 #include "mbf_adjoint.hpp"
 #include "mbf_spectra.hpp"
+#include "mbf_gp.hpp"
 
 namespace {
 
@@ -1474,6 +1475,51 @@ int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const doubl
     HIPCHK(nullptr, hipMemcpy(dw, omega, no, hipMemcpyHostToDevice));
     return spec_stats_device(nullptr, ds, n_probes, n_freq, dw, level, st, out);
 }
+
+int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu, int mem_kind, void* stream,
+                 double* phi, double* spec, double* stats) {
+    if (!E || !phi || !spec || !stats) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n_E < 1 || n_E > 65535 || M < 3 || M > mbf::kGpMaxM || !finite_pos(L) || n_nu < 1 || !finite_pos(dnu))
+        return fail(nullptr, MBF_EINVAL, "need 1 <= n_E <= 65535, 3 <= M <= 1023, L > 0, n_nu >= 1, dnu > 0");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    std::vector<double> eh((size_t)n_E);
+    if (mem_kind == MBF_MEM_HOST) std::memcpy(eh.data(), E, sizeof(double) * (size_t)n_E);
+    else HIPCHK(nullptr, hipMemcpy(eh.data(), E, sizeof(double) * (size_t)n_E, hipMemcpyDeviceToHost));
+    for (double x : eh)
+        if (!(std::isfinite(x) && x > 1.0)) return fail(nullptr, MBF_EINVAL, "every E must be finite and > 1");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nphi = (size_t)n_E * M, nspec = (size_t)n_E * n_nu, nst = (size_t)n_E * mbf::kGpStats;
+    double *dE = nullptr, *dphi = nullptr, *dspec = nullptr, *dst = nullptr;
+    struct Free {
+        double** p[4];
+        bool own;
+        ~Free() { if (own) for (double** q : p) hipFree(*q); }
+    } fr{{&dE, &dphi, &dspec, &dst}, mem_kind == MBF_MEM_HOST};
+    if (mem_kind == MBF_MEM_HOST) {
+        if (hipMalloc(&dE, sizeof(double) * (size_t)n_E) != hipSuccess ||
+            hipMalloc(&dphi, sizeof(double) * nphi) != hipSuccess ||
+            hipMalloc(&dspec, sizeof(double) * nspec) != hipSuccess ||
+            hipMalloc(&dst, sizeof(double) * nst) != hipSuccess)
+            return fail(nullptr, MBF_ENOMEM, "device allocation for the Gross-Pitaevskii solver failed");
+        HIPCHK(nullptr, hipMemcpy(dE, E, sizeof(double) * (size_t)n_E, hipMemcpyHostToDevice));
+    } else {
+        dE = const_cast<double*>(E); dphi = phi; dspec = spec; dst = stats;
+    }
+    mbf::GpArgs g{dE, M, L, n_nu, dnu, 400, 60, dphi, dspec, dst};
+    hipLaunchKernelGGL(mbf::k_gp_solve, dim3((unsigned)n_E), dim3(mbf::kGpThreads), 0, st, g);
+    HIPCHK(nullptr, hipGetLastError());
+    if (mem_kind == MBF_MEM_HOST) {
+        HIPCHK(nullptr, hipMemcpyAsync(phi, dphi, sizeof(double) * nphi, hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipMemcpyAsync(spec, dspec, sizeof(double) * nspec, hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipMemcpyAsync(stats, dst, sizeof(double) * nst, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+    return MBF_OK;
+}
+
+double mbf_gp_eigenvalue(double p, double kappa) { return (p - 1.0) / (kappa * std::sqrt(p)); }
+
+double mbf_gp_threshold(double kappa) { return 1.0 + 0.5 * kappa * kappa + 0.5 * kappa * std::sqrt(4.0 + kappa * kappa); }
 
 int mbf_read_loss(mbf_handle* h, double* out) {
     if (!h || !out) return fail(h, MBF_EINVAL, "null argument");

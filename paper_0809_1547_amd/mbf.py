@@ -139,6 +139,9 @@ def _load():
         "mbf_set_plane_monitor": (I, [P, I]),
         "mbf_reset_plane_monitor": (I, [P]),
         "mbf_read_plane_monitor": (I, [P, dp, C.POINTER(C.c_int64)]),
+        "mbf_gp_solve": (I, [VP, I, I, D, I, D, I, VP, VP, VP, VP]),
+        "mbf_gp_eigenvalue": (D, [D, D]),
+        "mbf_gp_threshold": (D, [D]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -160,7 +163,8 @@ EXPORTED = [
     "mbf_batch_sync", "mbf_batch_step_timed", "mbf_batch_step_bytes", "mbf_autotune",
     "mbf_batch_autotune", "mbf_adjoint_run", "mbf_spectrum_stats", "mbf_spectral_stats",
     "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
-    "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor",
+    "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor", "mbf_gp_solve",
+    "mbf_gp_eigenvalue", "mbf_gp_threshold",
 ]
 
 
@@ -350,6 +354,36 @@ def mbf_read_plane_monitor(h: int, nx: int, ny: int) -> Tuple[np.ndarray, int]:
     cnt = C.c_int64()
     _check(lib.mbf_read_plane_monitor(h, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)), h)
     return out, cnt.value
+
+
+GP_STATS = ("N", "w", "peak", "phi_max", "residual", "newton_steps", "converged")
+
+
+def mbf_gp_solve(E, M: int = 1023, L: float = 12.0, n_nu: int = 512, dnu: float = 0.02,
+                 stream: Optional[int] = None) -> dict:
+    """Bound states of -phi'' + tau^2 phi + phi^3 = E phi for every E (> 1):
+    {"phi": (n_E, M), "spec": (n_E, n_nu), "tau": (M,), "nu": (n_nu,), and
+    one (n_E,) array per statistic of GP_STATS}."""
+    E = np.ascontiguousarray(np.atleast_1d(E), dtype=np.float64)
+    nE = E.shape[0]
+    phi = np.zeros((nE, M))
+    spec = np.zeros((nE, n_nu))
+    st = np.zeros((nE, len(GP_STATS)))
+    _check(lib.mbf_gp_solve(E.ctypes.data, nE, int(M), float(L), int(n_nu), float(dnu), MBF_MEM_HOST,
+                            C.c_void_p(stream or 0), phi.ctypes.data, spec.ctypes.data, st.ctypes.data))
+    h = 2.0 * L / (M + 1)
+    out = {"phi": phi, "spec": spec, "tau": -L + h * np.arange(1, M + 1), "nu": dnu * np.arange(n_nu)}
+    for q, name in enumerate(GP_STATS):
+        out[name] = st[:, q]
+    return out
+
+
+def mbf_gp_eigenvalue(p: float, kappa: float) -> float:
+    return lib.mbf_gp_eigenvalue(float(p), float(kappa))
+
+
+def mbf_gp_threshold(kappa: float) -> float:
+    return lib.mbf_gp_threshold(float(kappa))
 
 
 def mbf_read_loss(h: int) -> float:
