@@ -97,7 +97,6 @@ struct mbf_handle {
     void* tap = nullptr;      // trajectory recording buffer of the adjoint (nullptr: off)
     int64_t tap_stride = 0;   // values per trajectory slot
     int64_t tap_base = 0;     // host copy of ctl->tap_base
-    int64_t adj_n_host = 0;   // host copy of ctl->adj_n
     // device copy of the view, geometry and work table the step kernels read
     void* d_view = nullptr;
     mbf::Geom* d_geom = nullptr;
@@ -1603,7 +1602,7 @@ struct StateHeader {
     double Na_si;
     mbf::Ctl ctl;
 };
-constexpr uint64_t kMagic = 0x3346424D5F54534Bull;
+constexpr uint64_t kMagic = 0x3446424D5F54534Bull;
 }  // namespace
 
 int mbf_state_size(const mbf_handle* h, size_t* out) {
@@ -2351,11 +2350,10 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     HIPCHK(h, hipMemcpy(B.dview, &v, sizeof(v), hipMemcpyHostToDevice));
     const mbf::AdjView<T>* dv = reinterpret_cast<const mbf::AdjView<T>*>(B.dview);
     const dim3 gblk((unsigned)gm.nblk), tb(64, 4);
-    // one reverse step: the H part, the E part, then step n - 1
-    auto reverse_step = [&]() {
+    // the reverse step of slot q of a segment (step tap_base + q)
+    auto reverse_step = [&](int q) {
         hipLaunchKernelGGL((mbf::k_adj_h<T, 4>), gblk, tb, 0, h->stream, dv, gm);
-        hipLaunchKernelGGL((mbf::k_adj_e<T, 4>), gblk, tb, 0, h->stream, dv, gm);
-        hipLaunchKernelGGL(mbf::k_adj_next, dim3(1), dim3(64), 0, h->stream, h->ctl);
+        hipLaunchKernelGGL((mbf::k_adj_e<T, 4>), gblk, tb, 0, h->stream, dv, gm, q);
     };
     for (int64_t sg = nseg - 1; sg >= 0 && !rc; --sg) {
         const int64_t n0 = sg * K, kp = std::min<int64_t>(K, nsteps - n0);
@@ -2365,18 +2363,17 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
             if (!rc) rc = run_steps(h, kp, nullptr);
             if (rc) break;
         }
-        // the reverse sweep starts at step n0 + kp - 1 (slot kp - 1 of the
-        // segment, whose slot 0 is step n0 = ctl->tap_base)
-        h->adj_n_host = n0 + kp - 1;
-        HIPCHK(h, hipMemcpyAsync(&h->ctl->adj_n, &h->adj_n_host, sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+        // the reverse steps of the segment take back steps n0 + kp - 1 down to
+        // n0 (slots kp - 1 .. 0 of the segment, whose slot 0 is step n0 =
+        // ctl->tap_base)
         if (sg == nseg - 1)                           // etot = 2 E^N in the box
             hipLaunchKernelGGL(mbf::k_adj_seed<T>, dim3((unsigned)((c.nx + 64) / 64), (unsigned)(c.ny + 1), (unsigned)(c.nz + 1)),
-                               dim3(64), 0, h->stream, v);
+                               dim3(64), 0, h->stream, v, (int)kp - 1);
         if (kp == K) {                                 // a whole segment: the captured sequence
             if (!B.rev) {
                 hipGraph_t g = nullptr;
                 HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
-                for (int q = 0; q < K; ++q) reverse_step();
+                for (int q = K - 1; q >= 0; --q) reverse_step(q);
                 const hipError_t e = hipStreamEndCapture(h->stream, &g);
                 if (e != hipSuccess) return fail(h, MBF_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
                 const hipError_t ei = hipGraphInstantiate(&B.rev, g, nullptr, nullptr, 0);
@@ -2388,7 +2385,7 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
             }
             HIPCHK(h, hipGraphLaunch(B.rev, h->stream));
         } else {
-            for (int64_t q = 0; q < kp; ++q) reverse_step();
+            for (int q = (int)kp - 1; q >= 0; --q) reverse_step(q);
         }
         if (hipGetLastError() != hipSuccess) rc = fail(h, MBF_EHIP, "adjoint kernel launch failed");
     }

@@ -29,8 +29,9 @@ template <typename T>
 struct AdjView {
     // forward trajectory: slot q = m - ctl->tap_base of `slot` values holds
     // E^m (3 x tap_e dense), P^m - P^{m-1} (3 x tap_c compact) and N1^m - N2^m
-    // (3 x tap_c compact); the step being reversed is n = ctl->adj_n, so one
-    // captured sequence of reverse steps serves every segment
+    // (3 x tap_c compact); a reverse step is told its slot q and takes back
+    // step n = ctl->tap_base + q, so one captured sequence of reverse steps
+    // serves every segment
     const T* traj;
     int64_t slot, tap_e, tap_c;
     Ctl* ctl;
@@ -62,7 +63,7 @@ struct AdjView {
     int box[6];
 };
 
-// Trajectory slots of steps n and n+1 for the step n = ctl->adj_n.
+// Trajectory slots q and q+1 (steps n and n+1, n = ctl->tap_base + q).
 template <typename T>
 struct AdjSlot {
     const T* s0;
@@ -71,17 +72,12 @@ struct AdjSlot {
 };
 
 template <typename T>
-__device__ __forceinline__ AdjSlot<T> adj_slot(const AdjView<T>& v) {
+__device__ __forceinline__ AdjSlot<T> adj_slot(const AdjView<T>& v, int q) {
     AdjSlot<T> a;
-    a.n = gld(&v.ctl->adj_n);
-    a.s0 = v.traj + (a.n - gld(&v.ctl->tap_base)) * v.slot;
+    a.n = gld(&v.ctl->tap_base) + q;
+    a.s0 = v.traj + (int64_t)q * v.slot;
     a.s1 = a.s0 + v.slot;
     return a;
-}
-
-// The reverse sweep moves to step n - 1 (one thread, after the step's kernels).
-__global__ void __launch_bounds__(64) k_adj_next(Ctl* ctl) {
-    if (threadIdx.x == 0) ctl->adj_n = ctl->adj_n - 1;
 }
 
 template <typename T>
@@ -194,7 +190,7 @@ __device__ __forceinline__ T adj_db(const AdjView<T>& v, int c, int i, int j, in
 // wave owns one row and marches along z (htot of Hx, Hy at k-1 stays in
 // registers); a plane's loads all go out before its arithmetic and stores.
 template <typename T, int TY>
-__global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict__ vp, Geom gm) {
+__global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict__ vp, Geom gm, int q) {
     const AdjView<T>& v = *vp;
     __shared__ double sh[TY];
     const int w = xcd_work_item((int)blockIdx.x, gm.nblk, gm.xcd_remap);
@@ -203,7 +199,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict_
     const int i = bx * 64 + threadIdx.x;
     const int j = by * TY + threadIdx.y;
     const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
-    const AdjSlot<T> a = adj_slot(v);
+    const AdjSlot<T> a = adj_slot(v, q);
     const T src = v.src_on ? (T)source_at(v, a.n) : (T)0;   // the forward's value at step n
     double gna = 0.0;
     if (j < v.ny) {
@@ -306,12 +302,12 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict_
 // Start of the reverse sweep: etot = 2 E^N on the interior sites of the box
 // (u = cb ie etot; zero elsewhere); the other adjoint arrays start at zero.
 template <typename T>
-__global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v) {
+__global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v, int q) {
     const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
     if (i > v.nx) return;
     const uint32_t x = (uint32_t)i + (uint32_t)v.sx * (uint32_t)j + (uint32_t)v.sxy * (uint32_t)k;
     const bool inb = i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] && k >= v.box[2] && k < v.box[5];
-    const AdjSlot<T> a = adj_slot(v);                 // n = N - 1: slot N holds E^N
+    const AdjSlot<T> a = adj_slot(v, q);              // q = N - 1 - tap_base: slot q+1 holds E^N
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         T u = (T)0;

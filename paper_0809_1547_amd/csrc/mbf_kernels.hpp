@@ -39,7 +39,6 @@ struct Ctl {                  // per-simulation control block (device memory)
     int32_t pad;
     double src_val;           // soft-source value added during the current step
     int64_t tap_base;         // step of trajectory slot 0 while a trajectory is recorded
-    int64_t adj_n;            // step the reverse sweep is taking back
 };
 
 template <typename T>
