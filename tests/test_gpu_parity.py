@@ -321,6 +321,41 @@ def test_nonfinite_energy_is_reported():
     assert err.value.code == mbf.MBF_ENONFINITE
 
 
+def test_state_errors_and_limits():
+    # stepping before material and pump, a 32-bit step index that would wrap,
+    # sources off the interior, probes and loss boxes outside the grid
+    mbf = _mbf()
+    sim = mbf.Sim((10, 9, 8))
+    with pytest.raises(mbf.MbfError) as err:
+        sim.step(1)
+    assert err.value.code == mbf.MBF_ESTATE
+    eps, gain = I.homogeneous((10, 9, 8), 1.0, 1)
+    sim.set_material(eps, gain)
+    sim.set_pump(2e24)
+    for n in (-1, 1 << 32):
+        with pytest.raises(mbf.MbfError) as err:
+            sim.step(n)
+        assert err.value.code == mbf.MBF_EINVAL
+    for src in ((0, 10, 4, 4), (1, 0, 4, 4), (2, 4, 4, 8), (3, 4, 4, 4)):
+        with pytest.raises(mbf.MbfError):
+            sim.set_source(*src)
+        with pytest.raises(mbf.MbfError):
+            sim.set_cw_source(*src)
+    with pytest.raises(mbf.MbfError):
+        sim.set_probes(np.array([[0, 11, 1, 1]]), np.array([1e15]))
+    with pytest.raises(mbf.MbfError):
+        sim.set_loss_box((0, 0, 0), (11, 9, 8))
+    for k in (-2, 8):
+        with pytest.raises(mbf.MbfError):
+            sim.set_plane_monitor(k)
+    with pytest.raises(mbf.MbfError) as err:
+        sim.plane_monitor()
+    assert err.value.code == mbf.MBF_ESTATE
+    assert sim.step_index == 0                     # nothing above advanced the run
+    sim.step(3)
+    assert sim.step_index == 3
+
+
 def test_device_memory_roundtrip_through_torch():
     import torch
     mbf = _mbf()
