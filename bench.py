@@ -376,12 +376,22 @@ def main():
         f"{alg[0] / cells:.1f} alg. B/cell per step; kernel source {sha}")
 
     if args.workload == "c5":
-        # the linewidth analysis of the run's spectra (once per run, not per step)
+        # the linewidth analysis of the run's spectra (once per run, not per
+        # step); with --steps 78675 --warmup 0 this is the whole 3 ps run
         t0 = time.perf_counter()
         stats = batch.spectrum_stats(0.5)
         st_ms = (time.perf_counter() - t0) * 1e3
         log(f"spectral statistics of {len(stats)} members ({batch[0]._np} probes x {batch[0]._nf} bins): "
-            f"{st_ms:.2f} ms wall; peak bins {[q['peak_bin'] for q in stats]}")
+            f"{st_ms:.2f} ms wall")
+        c0 = 299792458.0
+        for r, q in enumerate(stats):
+            if q["peak_bin"] < 0:
+                continue
+            lam = 2.0 * math.pi * c0 / q["peak_omega"]
+            to_nm = lam * lam / (2.0 * math.pi * c0) * 1e9      # d(lambda)/d(omega) at the peak
+            log(f"  N_a = {NA_LEVELS[r % len(NA_LEVELS)]:.2e}: W = {batch[r].energy()[0]:.3e}, peak "
+                f"{lam * 1e9:.1f} nm, std {q['std_omega'] * to_nm:.1f} nm, Gaussian-fit sigma "
+                f"{q['fit_sigma'] * to_nm:.2f} nm")
 
     if args.calib_copy:
         a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
