@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+DENSE_BYTES_PER_CU = 157.0      # 21 FP32 values read, 18 written, material byte
 NA_LEVELS = [1e24, 2e24, 3.5e24, 5e24, 7e24]
 RUN_STEPS_3PS = 78675          # 3 ps at dt = 3.81315e-17 s
 
@@ -441,6 +442,9 @@ def main():
             "avg_launch_ms": avg_kern_s * 1e3,
             "step_alg_bytes": alg[0],
             "step_kernels_ms": [kern_ms[0] / launches, kern_ms[1] / launches],
+            # cell-updates/s priced at the dense 157 B per cell-update (every
+            # cell with three gain sites), over the same peak
+            "effective_frac_157B": value * DENSE_BYTES_PER_CU / (HBM_PEAK_GBS * 1e9),
         },
         "cpu_baseline": cpu,
     }
