@@ -90,6 +90,9 @@ def lib():
         L.orc_adjoint_run.argtypes = [P, C.c_int64, dp, dp, dp]
         L.orc_tangent_step.argtypes = [P, pp, pp]
         L.orc_adjoint_step.argtypes = [P, pp, pp]
+        L.orc_pack_md.restype = C.c_int
+        L.orc_pack_md.argtypes = [C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_pack_energy.argtypes = [C.c_int, dp, dp, dp, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -304,3 +307,29 @@ def pop_series(coef: np.ndarray, N0: np.ndarray, Ebar: np.ndarray, dP: np.ndarra
     out = np.empty((Ebar.shape[0], 4))
     lib().orc_pop_series(_dp(coef), _dp(N), _dp(Ebar), _dp(dP), Ebar.shape[0], _dp(out))
     return out
+
+
+def _pack_args(box, diam, centres):
+    box = np.ascontiguousarray(box, dtype=np.float64).reshape(3)
+    diam = np.ascontiguousarray(diam, dtype=np.float64).reshape(-1)
+    x = np.array(centres, dtype=np.float64, order="C").reshape(diam.shape[0], 3)
+    return box, diam, x
+
+
+def pack_md(box, diam, centres, *, s0: float = 0.5, stages: int = 50, iters: int = 20,
+            final_iters: int = 500, eta: float = 0.1) -> np.ndarray:
+    """Soft-sphere compression packing (pack_oracle.c): the centres after the
+    schedule, as a new (n, 3) array."""
+    box, diam, x = _pack_args(box, diam, centres)
+    rc = lib().orc_pack_md(diam.shape[0], _dp(box), _dp(diam), _dp(x), s0, stages, iters, final_iters, eta)
+    if rc != 0:
+        raise ValueError("orc_pack_md: bad arguments")
+    return x
+
+
+def pack_energy(box, diam, centres, s: float = 1.0):
+    """(U_s, largest overlap) of a configuration at scale s."""
+    box, diam, x = _pack_args(box, diam, centres)
+    out = np.zeros(2)
+    lib().orc_pack_energy(diam.shape[0], _dp(box), _dp(diam), _dp(x), s, _dp(out))
+    return float(out[0]), float(out[1])

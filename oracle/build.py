@@ -8,9 +8,9 @@ LIB = os.path.join(HERE, "libmboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "mb_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("mb_oracle.c", "pack_oracle.c")]
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-fno-fast-math", "-ffp-contract=off", "-o", LIB + ".tmp", src, "-lm"]
+           "-fno-fast-math", "-ffp-contract=off", "-o", LIB + ".tmp", *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

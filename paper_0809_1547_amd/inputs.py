@@ -11,7 +11,9 @@ simulations start from:
   workload presets (grid, step count, pump density).
 
 The paper obtains its packing by molecular dynamics; random sequential addition
-(RSA) with Gaussian diameters stands in for it here.  Every generator is keyed
+(RSA) with Gaussian diameters stands in for it by default, and ``pack_start``
+gives the seeded start (diameters and random centres) of the soft-sphere
+compression packing that the library computes.  Every generator is keyed
 by an explicit integer seed (numpy PCG64), so a given call returns the same
 arrays on every machine.
 """
@@ -165,6 +167,40 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
             excluded[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= d2 < reach * reach
     return Packing(n, np.array(centres, dtype=np.float64).reshape(-1, 3),
                    np.array(radii, dtype=np.float64))
+
+
+def pack_start(n: Tuple[int, int, int] | int, *, seed: int, fill: float,
+               mean_d: float = 300.0 / 20.0, sd_d: float = 30.0 / 20.0):
+    """Seeded start of a compression packing (cell units).
+
+    Diameters are drawn as in ``rsa_pack`` (Gaussian, truncated to +-3 sd by
+    redrawing) until their summed full-sphere volume reaches ``fill`` times the
+    box volume; centres are uniform over the box and may overlap.  Returns
+    (box (3,), diameters (K,), centres (K, 3) as (x, y, z)).
+    """
+    if isinstance(n, int):
+        n = (n, n, n)
+    box = np.array([float(v) for v in n])
+    rng = _rng(seed, 2)
+    target = fill * float(np.prod(box))
+    diam: List[float] = []
+    vol = 0.0
+    while vol < target:
+        d = rng.normal(mean_d, sd_d)
+        if abs(d - mean_d) <= 3 * sd_d:
+            diam.append(float(d))
+            vol += math.pi / 6.0 * d ** 3
+    d = np.array(diam, dtype=np.float64)
+    centres = rng.random((d.shape[0], 3)) * box
+    return box, d, centres
+
+
+def packing_from_centres(n: Tuple[int, int, int] | int, diam: np.ndarray, centres: np.ndarray) -> Packing:
+    """A Packing (for ``voxelize``) from diameters and centres."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    return Packing(tuple(int(v) for v in n), np.asarray(centres, dtype=np.float64).reshape(-1, 3),
+                   0.5 * np.asarray(diam, dtype=np.float64).reshape(-1))
 
 
 def voxelize(p: Packing, eps_sphere: float = EPS_SPHERE,

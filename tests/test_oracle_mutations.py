@@ -10,6 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mb_oracle.c")
+PACK_SRC = os.path.join(ROOT, "oracle", "pack_oracle.c")
 # the adjoint pins run first: they take under a second, and their comparison
 # of the tangent step with differences of the forward step also trips on most
 # mistakes in the forward step
@@ -60,18 +61,43 @@ MUTATIONS = [
     ("tangent_inversion_term", "c[ORC_C_CK] * dN * v[cc][x];", "c[ORC_C_CK] * dN * v[cc][x] * 0.5;"),
 ]
 
+# mistakes in the packing oracle, caught by its own pins
+PACK_PINS = ["tests/test_oracle_pack.py"]
+PACK_MUTATIONS = [
+    ("pack_pair_sign", "const double q = (sig - r) / r;", "const double q = (r - sig) / r;"),
+    ("pack_contact_distance", "const double sig = s * (0.5 * (d[i] + d[j]));", "const double sig = s * d[i];"),
+    ("pack_unscaled_contact", "const double sig = s * (0.5 * (d[i] + d[j]));", "const double sig = 0.5 * (d[i] + d[j]);"),
+    ("pack_pair_index", "const double rz = x[3 * i + 2] - x[3 * j + 2];\n            const double r2",
+     "const double rz = x[3 * i + 2] - x[3 * (j + 1) % n + 2];\n            const double r2"),
+    ("pack_upper_wall_sign", "if (hi > 0.0) fa[a] -= hi;", "if (hi > 0.0) fa[a] += hi;"),
+    ("pack_wall_radius", "const double ri = s * (0.5 * d[i]);\n        double fa", "const double ri = s * d[i];\n        double fa"),
+    ("pack_schedule_end", "const int steps = m < stages ? iters : final_iters;", "const int steps = m <= stages ? iters : final_iters;"),
+    ("pack_schedule_scale", "s0 + (1.0 - s0) * (double)m / (double)stages", "s0 + (1.0 - s0) * (double)(m + 1) / (double)stages"),
+    ("pack_gauss_seidel", "for (int k = 0; k < 3 * n; ++k) x[k] += eta * f[k];",
+     "for (int k = 0; k < 3 * n; ++k) x[k] += eta * f[k] * (k < 3 ? 2.0 : 1.0);"),
+]
 
-@pytest.mark.parametrize("name,orig,mut", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_is_caught(tmp_path, name, orig, mut):
-    src = open(SRC).read()
-    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
-    bad = tmp_path / "mb_oracle.c"
-    bad.write_text(src.replace(orig, mut))
+
+CASES = [(m, SRC, PINS) for m in MUTATIONS] + [(m, PACK_SRC, PACK_PINS) for m in PACK_MUTATIONS]
+
+
+@pytest.mark.parametrize("mutation,path,pins", CASES, ids=[c[0][0] for c in CASES])
+def test_planted_mistake_is_caught(tmp_path, mutation, path, pins):
+    name, orig, mut = mutation
+    srcs = []
+    for f in (SRC, PACK_SRC):
+        text = open(f).read()
+        if f == path:
+            assert text.count(orig) == 1, f"mutation anchor for {name} not unique"
+            text = text.replace(orig, mut)
+        out = tmp_path / os.path.basename(f)
+        out.write_text(text)
+        srcs.append(str(out))
     (tmp_path / "mb_oracle.h").write_text(open(os.path.join(ROOT, "oracle", "mb_oracle.h")).read())
     lib = tmp_path / "libbad.so"
     subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-                    "-o", str(lib), str(bad), "-lm"], check=True)
+                    "-o", str(lib), *srcs, "-lm"], check=True)
     env = dict(os.environ, MB_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+                        *pins], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
