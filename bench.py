@@ -53,9 +53,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--n", type=int, default=320, help="cells per side")
     ap.add_argument("--batch", type=int, default=5)
-    ap.add_argument("--workload", choices=["c5", "c3"], default="c5",
+    ap.add_argument("--workload", choices=["c5", "c3", "pack"], default="c5",
                     help="c5: 320^3 batch of pump levels (default); c3: 64 small realizations "
-                         "of uneven size, batched against one at a time")
+                         "of uneven size, batched against one at a time; pack: the soft-sphere "
+                         "compression packing of the 320^3 sample")
+    ap.add_argument("--pack-runs", type=int, default=5, help="timed packings of --workload pack")
+    ap.add_argument("--packing", choices=["rsa", "md"], default="rsa",
+                    help="c5 sample: random sequential addition (default) or the library's "
+                         "soft-sphere compression packing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
@@ -195,10 +200,11 @@ def traffic_from_profiles(kernel, workload, tuning, kernel_sha):
 
 
 def kernel_source_sha():
+    """Hash of the source that defines the step kernels (their launch shape is
+    the tuning, recorded beside it)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("mbf_kernels.hpp", "mbf.hip"):
-        h.update(open(os.path.join(ROOT, "paper_0809_1547_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_0809_1547_amd", "csrc", "mbf_kernels.hpp"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -232,7 +238,14 @@ def c5_batch(args, I, mbf, stream):
     """The paper-scale workload: a batch of pump levels on one 320^3 packing."""
     n = args.n
     t0 = time.perf_counter()
-    pk = I.rsa_pack(n, seed=0, fill=0.4)
+    if args.packing == "md":
+        # the soft-sphere compression packing, computed by the library
+        box, d, x = I.pack_start(n, seed=0, fill=0.4)
+        x, _, ov = mbf.mbf_pack_md(box, d, x, stream=stream.cuda_stream, **PACK_SCHEDULE)
+        pk = I.packing_from_centres(n, d, x)
+        log(f"compression packing: largest overlap {ov:.2e} cells")
+    else:
+        pk = I.rsa_pack(n, seed=0, fill=0.4)
     eps, gain = I.voxelize(pk)
     log(f"packing: {pk.count} spheres, voxel fill {1 - gain.mean():.3f} ({time.perf_counter() - t0:.1f} s)")
     probes = I.select_probes(eps, gain, 256, seed=0)
@@ -248,7 +261,8 @@ def c5_batch(args, I, mbf, stream):
     log(f"set-up of {args.batch} x {n}^3 done ({time.perf_counter() - t0:.1f} s), {len(om)} DFT bins")
     config = {
         "workload": f"paper-scale realization {n}^3 x batch of {args.batch} pump levels "
-                    f"(RSA spheres d=300nm n=2.9 fill 0.4, gain in voids, ground start, "
+                    f"({'compression-packed' if args.packing == 'md' else 'RSA'} spheres d=300nm n=2.9 "
+                    f"fill 0.4, gain in voids, ground start, "
                     f"noise, 256 probes x {len(om)} DFT bins, absorbing walls)",
         "cells_per_realization": n ** 3,
         "batch": args.batch,
@@ -307,6 +321,59 @@ def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream):
     return sum(N ** 3 for N in sizes) * steps / dt
 
 
+PACK_SCHEDULE = dict(s0=0.5, stages=100, iters=20, final_iters=1000, eta=0.15)
+
+
+def pack_bench(args, I, mbf, stream):
+    """The 320^3 sample (6.4 um box, 0.4 fill of 300 nm +- 10% spheres)
+    packed by soft-sphere compression on the GPU, inputs resident in device
+    memory; the oracle (all pairs, FP64) timed on a few steps of the same
+    input."""
+    import torch
+    n = args.n
+    box, d, x = I.pack_start(n, seed=11, fill=0.4)
+    steps = PACK_SCHEDULE["stages"] * PACK_SCHEDULE["iters"] + PACK_SCHEDULE["final_iters"]
+    log(f"packing: {len(d)} spheres in {n}^3, {steps} steps per packing")
+    dt = torch.tensor(d, device="cuda")
+    x0 = torch.tensor(x, device="cuda")
+    xt = x0.clone()
+    sid = stream.cuda_stream
+    mbf.mbf_pack_md(box, dt, xt, stream=sid, **PACK_SCHEDULE)          # warm-up
+    times = []
+    for _ in range(args.pack_runs):
+        xt.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, U, ov = mbf.mbf_pack_md(box, dt, xt, stream=sid, **PACK_SCHEDULE)
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    value = len(d) * steps / best
+    log(f"packing: best {best * 1e3:.1f} ms of {args.pack_runs} ({np.mean(times) * 1e3:.1f} mean), "
+        f"{best / steps * 1e6:.2f} us per step; U = {U:.3e}, largest overlap {ov:.3e}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.pack_md(box, d, x, stages=0, final_iters=1)                # page in
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0) and k < 200:
+            O.pack_md(box, d, x, stages=0, final_iters=1)
+            k += 1
+        el = time.perf_counter() - t0
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": len(d) * k / el, "unit": "sphere-steps/s", "cores": cores, "kind": "oracle",
+               "sample": f"{k} steps of the same {len(d)} spheres (all pairs, FP64, {cores} OpenMP threads)"}
+        log(f"cpu baseline: {cpu}")
+    out = {"metric": "sphere-steps/s", "value": value, "unit": "sphere-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": 1, "ms_per_step": best / steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"soft-sphere compression packing, {n}^3 box, fill 0.4, 300 nm +- 10% "
+                                  f"spheres ({len(d)}), schedule {PACK_SCHEDULE}",
+                      "spheres": len(d), "ms_per_packing": best * 1e3, "energy": U, "max_overlap": ov},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_profile:
@@ -327,6 +394,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.workload == "pack":
+        pack_bench(args, I, mbf, stream)
+        return
     if args.workload == "c3":
         batch, cells, config, extra = c3_batch(args, I, mbf, stream)
         tuning = batch.autotune(budget_ms=6000)

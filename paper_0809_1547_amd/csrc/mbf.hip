@@ -22,6 +22,7 @@
 #include "mbf_adjoint.hpp"
 #include "mbf_spectra.hpp"
 #include "mbf_gp.hpp"
+#include "mbf_pack.hpp"
 
 namespace {
 
@@ -653,6 +654,22 @@ uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t hsh = 1469598103934665603ull
 }  // namespace
 
 // ======================================================================= ABI
+
+// Device buffers of one call, freed when it returns.
+struct DevScratch {
+    std::vector<void*> p;
+    ~DevScratch() {
+        for (void* q : p) hipFree(q);
+    }
+    template <typename T>
+    bool get(T** out, size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, sizeof(T) * count) != hipSuccess) return false;
+        p.push_back(q);
+        *out = (T*)q;
+        return true;
+    }
+};
 
 extern "C" {
 
@@ -1519,6 +1536,115 @@ int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu
 double mbf_gp_eigenvalue(double p, double kappa) { return (p - 1.0) / (kappa * std::sqrt(p)); }
 
 double mbf_gp_threshold(double kappa) { return 1.0 + 0.5 * kappa * kappa + 0.5 * kappa * std::sqrt(4.0 + kappa * kappa); }
+
+int mbf_pack_md(int n, const double* box, const double* diam, double* centres, const mbf_pack_params* prm,
+                int mem_kind, void* stream, double* energy, double* max_overlap) {
+    if (!box || !prm || !energy || !max_overlap || (n > 0 && (!diam || !centres)))
+        return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n < 0 || n > MBF_PACK_MAX_SPHERES) return fail(nullptr, MBF_EINVAL, "need 0 <= n <= 2^26 spheres");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    if (!finite_pos(box[0]) || !finite_pos(box[1]) || !finite_pos(box[2]))
+        return fail(nullptr, MBF_EINVAL, "box edges must be finite and > 0");
+    if (!(std::isfinite(prm->s0) && prm->s0 > 0.0 && prm->s0 <= 1.0) || prm->stages < 0 || prm->iters < 0 ||
+        prm->final_iters < 0 || !finite_pos(prm->eta))
+        return fail(nullptr, MBF_EINVAL, "need 0 < s0 <= 1, stages, iters, final_iters >= 0 and eta > 0");
+    if (n == 0) {
+        *energy = 0.0;
+        *max_overlap = 0.0;
+        return MBF_OK;
+    }
+    const size_t nn = (size_t)n;
+    std::vector<double> dh(nn), xh(3 * nn);
+    if (mem_kind == MBF_MEM_HOST) {
+        std::memcpy(dh.data(), diam, sizeof(double) * nn);
+        std::memcpy(xh.data(), centres, sizeof(double) * 3 * nn);
+    } else {
+        HIPCHK(nullptr, hipMemcpy(dh.data(), diam, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        HIPCHK(nullptr, hipMemcpy(xh.data(), centres, sizeof(double) * 3 * nn, hipMemcpyDeviceToHost));
+    }
+    double dmax = 0.0;
+    for (double d : dh) {
+        if (!finite_pos(d)) return fail(nullptr, MBF_EINVAL, "every diameter must be finite and > 0");
+        dmax = std::max(dmax, d);
+    }
+    for (double v : xh)
+        if (!std::isfinite(v)) return fail(nullptr, MBF_EINVAL, "every centre coordinate must be finite");
+    // cells at least as wide as the largest diameter (the longest contact)
+    mbf::PackGrid gr{};
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double q = std::floor(box[a] / dmax);
+        if (q > (double)mbf::kPackMaxCells) return fail(nullptr, MBF_EINVAL, "box too large for its spheres (over 2^24 cells)");
+        int g = std::max(1, (int)q);
+        while (g > 1 && box[a] / (double)g < dmax) --g;
+        gr.g[a] = g;
+        gr.w[a] = box[a] / (double)g;
+        gr.box[a] = box[a];
+        ncell *= g;
+    }
+    if (ncell > mbf::kPackMaxCells) return fail(nullptr, MBF_EINVAL, "box too large for its spheres (over 2^24 cells)");
+    gr.ncell = (int)ncell;
+    hipStream_t st = (hipStream_t)stream;
+    DevScratch mem;
+    double4* P[2] = {nullptr, nullptr};
+    int *cnt = nullptr, *lst = nullptr, *flag = nullptr;
+    double *dd = nullptr, *dx = nullptr, *e = nullptr, *mo = nullptr, *out = nullptr;
+    const size_t nc = (size_t)ncell, ncap = nc * mbf::kPackCap;
+    if (!mem.get(&P[0], nn) || !mem.get(&P[1], nn) || !mem.get(&cnt, 2 * nc) || !mem.get(&lst, 2 * ncap) ||
+        !mem.get(&flag, 1) || !mem.get(&e, nn) || !mem.get(&mo, nn) || !mem.get(&out, 2))
+        return fail(nullptr, MBF_ENOMEM, "device allocation for the packing failed");
+    if (mem_kind == MBF_MEM_HOST) {
+        if (!mem.get(&dd, nn) || !mem.get(&dx, 3 * nn))
+            return fail(nullptr, MBF_ENOMEM, "device allocation for the packing failed");
+        HIPCHK(nullptr, hipMemcpyAsync(dd, dh.data(), sizeof(double) * nn, hipMemcpyHostToDevice, st));
+        HIPCHK(nullptr, hipMemcpyAsync(dx, xh.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice, st));
+    } else {
+        dd = const_cast<double*>(diam);
+        dx = centres;
+    }
+    // two cell tables (counts + lists): a step reads one and bins into the other
+    int* ct[2] = {cnt, cnt + nc};
+    int* lt[2] = {lst, lst + ncap};
+    const unsigned b256 = (unsigned)((nn + 255) / 256);
+    const unsigned bstep = (unsigned)((nn + mbf::kPackThreads / mbf::kPackLanes - 1) / (mbf::kPackThreads / mbf::kPackLanes));
+    const unsigned bcell = (unsigned)((nc + 255) / 256);
+    hipLaunchKernelGGL(mbf::k_pack_load, dim3(b256), dim3(256), 0, st, dx, dd, n, P[0], cnt, 2 * gr.ncell);
+    hipLaunchKernelGGL(mbf::k_pack_clear_flag, dim3(1), dim3(64), 0, st, flag);
+    hipLaunchKernelGGL(mbf::k_pack_bin, dim3(b256), dim3(256), 0, st, P[0], n, gr, ct[0], lt[0], flag);
+    hipLaunchKernelGGL(mbf::k_pack_sort, dim3(bcell), dim3(256), 0, st, ct[0], lt[0], gr.ncell, ct[1]);
+    HIPCHK(nullptr, hipGetLastError());
+    int cur = 0, par = 0;
+    for (int m = 0; m <= prm->stages; ++m) {
+        const double s = prm->stages > 0 ? prm->s0 + (1.0 - prm->s0) * (double)m / (double)prm->stages : 1.0;
+        const int steps = m < prm->stages ? prm->iters : prm->final_iters;
+        for (int t = 0; t < steps; ++t) {
+            hipLaunchKernelGGL(mbf::k_pack_step, dim3(bstep), dim3(mbf::kPackThreads), 0, st, P[cur], P[cur ^ 1], n,
+                               gr, ct[par], lt[par], s, prm->eta, ct[par ^ 1], lt[par ^ 1], flag);
+            hipLaunchKernelGGL(mbf::k_pack_sort, dim3(bcell), dim3(256), 0, st, ct[par ^ 1], lt[par ^ 1], gr.ncell,
+                               ct[par]);
+            cur ^= 1;
+            par ^= 1;
+        }
+        HIPCHK(nullptr, hipGetLastError());
+    }
+    hipLaunchKernelGGL(mbf::k_pack_measure, dim3(b256), dim3(256), 0, st, P[cur], n, gr, ct[par], lt[par], e, mo);
+    hipLaunchKernelGGL(mbf::k_pack_reduce, dim3(1), dim3(256), 0, st, e, mo, n, out);
+    hipLaunchKernelGGL(mbf::k_pack_store, dim3(b256), dim3(256), 0, st, P[cur], n, dx);
+    HIPCHK(nullptr, hipGetLastError());
+    double res[2];
+    int fl = 0;
+    HIPCHK(nullptr, hipMemcpyAsync(res, out, sizeof(res), hipMemcpyDeviceToHost, st));
+    HIPCHK(nullptr, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (mem_kind == MBF_MEM_HOST)
+        HIPCHK(nullptr, hipMemcpyAsync(centres, dx, sizeof(double) * 3 * nn, hipMemcpyDeviceToHost, st));
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+    if (fl) return fail(nullptr, MBF_ESTATE, "more than 32 centres fell into one cell: the packing is too dense for its cells");
+    *energy = res[0];
+    *max_overlap = res[1];
+    if (!std::isfinite(res[0]) || !std::isfinite(res[1]))
+        return fail(nullptr, MBF_ENONFINITE, "the packing diverged (eta too large for the contacts)");
+    return MBF_OK;
+}
 
 int mbf_read_loss(mbf_handle* h, double* out) {
     if (!h || !out) return fail(h, MBF_EINVAL, "null argument");

@@ -62,6 +62,11 @@ class mbf_tuning(C.Structure):
                 ("xcd_remap", C.c_int32), ("group_mb", C.c_int32)]
 
 
+class mbf_pack_params(C.Structure):
+    _fields_ = [("s0", C.c_double), ("stages", C.c_int32), ("iters", C.c_int32),
+                ("final_iters", C.c_int32), ("pad", C.c_int32), ("eta", C.c_double)]
+
+
 class mbf_spec_stats(C.Structure):
     _fields_ = [("total", C.c_double), ("peak_omega", C.c_double), ("peak_value", C.c_double),
                 ("mean_omega", C.c_double), ("std_omega", C.c_double), ("fit_center", C.c_double),
@@ -142,6 +147,7 @@ def _load():
         "mbf_gp_solve": (I, [VP, I, I, D, I, D, I, VP, VP, VP, VP]),
         "mbf_gp_eigenvalue": (D, [D, D]),
         "mbf_gp_threshold": (D, [D]),
+        "mbf_pack_md": (I, [I, dp, VP, VP, C.POINTER(mbf_pack_params), I, VP, dp, dp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -164,7 +170,7 @@ EXPORTED = [
     "mbf_batch_autotune", "mbf_adjoint_run", "mbf_spectrum_stats", "mbf_spectral_stats",
     "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
     "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor", "mbf_gp_solve",
-    "mbf_gp_eigenvalue", "mbf_gp_threshold",
+    "mbf_gp_eigenvalue", "mbf_gp_threshold", "mbf_pack_md",
 ]
 
 
@@ -376,6 +382,34 @@ def mbf_gp_solve(E, M: int = 1023, L: float = 12.0, n_nu: int = 512, dnu: float 
     for q, name in enumerate(GP_STATS):
         out[name] = st[:, q]
     return out
+
+
+def mbf_pack_md(box, diam, centres, *, s0: float = 0.5, stages: int = 100, iters: int = 20,
+                final_iters: int = 1000, eta: float = 0.15, stream: Optional[int] = None):
+    """Soft-sphere compression packing of n spheres in the box.  diam (n,) and
+    centres (n, 3): numpy arrays (the packed centres come back as a new array)
+    or device tensors (float64, contiguous; centres are packed in place).
+    Returns (centres, energy U_1, largest overlap)."""
+    prm = mbf_pack_params(float(s0), int(stages), int(iters), int(final_iters), 0, float(eta))
+    b = (C.c_double * 3)(*[float(v) for v in np.asarray(box, dtype=np.float64).reshape(3)])
+    if isinstance(diam, np.ndarray) or not getattr(diam, "is_cuda", False):
+        diam = np.ascontiguousarray(np.asarray(diam, dtype=np.float64).reshape(-1))
+        centres = np.array(np.asarray(centres, dtype=np.float64).reshape(-1, 3), order="C")
+        n = diam.shape[0]
+        if centres.shape[0] != n:
+            raise ValueError("centres must be (n, 3) for n diameters")
+        pd, pc, kind = diam.ctypes.data, centres.ctypes.data, MBF_MEM_HOST
+    else:
+        import torch
+        if diam.dtype != torch.float64 or centres.dtype != torch.float64 or not centres.is_cuda:
+            raise ValueError("device diameters and centres must both be float64 device tensors")
+        if not (diam.is_contiguous() and centres.is_contiguous()) or tuple(centres.shape) != (diam.shape[0], 3):
+            raise ValueError("centres must be a contiguous (n, 3) tensor for n contiguous diameters")
+        n = diam.shape[0]
+        pd, pc, kind = diam.data_ptr(), centres.data_ptr(), MBF_MEM_DEVICE
+    e, m = C.c_double(), C.c_double()
+    _check(lib.mbf_pack_md(int(n), b, pd, pc, C.byref(prm), kind, C.c_void_p(stream or 0), C.byref(e), C.byref(m)))
+    return centres, e.value, m.value
 
 
 def mbf_gp_eigenvalue(p: float, kappa: float) -> float:
