@@ -857,8 +857,10 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
     std::vector<float> eps(ncell);
     std::vector<uint8_t> g(ncell);
     if (mem_kind == MBF_MEM_DEVICE) {
-        HIPCHK(h, hipMemcpy(eps.data(), eps_r, ncell * sizeof(float), hipMemcpyDeviceToHost));
-        HIPCHK(h, hipMemcpy(g.data(), gain, ncell, hipMemcpyDeviceToHost));
+        // read on the handle's stream: ordered after the caller's work there
+        HIPCHK(h, hipMemcpyAsync(eps.data(), eps_r, ncell * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(g.data(), gain, ncell, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
     } else if (mem_kind == MBF_MEM_HOST) {
         std::memcpy(eps.data(), eps_r, ncell * sizeof(float));
         std::memcpy(g.data(), gain, ncell);
@@ -1498,12 +1500,16 @@ int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu
     if (n_E < 1 || n_E > 65535 || M < 3 || M > mbf::kGpMaxM || !finite_pos(L) || n_nu < 1 || !finite_pos(dnu))
         return fail(nullptr, MBF_EINVAL, "need 1 <= n_E <= 65535, 3 <= M <= 1023, L > 0, n_nu >= 1, dnu > 0");
     if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    hipStream_t st = (hipStream_t)stream;
     std::vector<double> eh((size_t)n_E);
-    if (mem_kind == MBF_MEM_HOST) std::memcpy(eh.data(), E, sizeof(double) * (size_t)n_E);
-    else HIPCHK(nullptr, hipMemcpy(eh.data(), E, sizeof(double) * (size_t)n_E, hipMemcpyDeviceToHost));
+    if (mem_kind == MBF_MEM_HOST) {
+        std::memcpy(eh.data(), E, sizeof(double) * (size_t)n_E);
+    } else {
+        HIPCHK(nullptr, hipMemcpyAsync(eh.data(), E, sizeof(double) * (size_t)n_E, hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipStreamSynchronize(st));
+    }
     for (double x : eh)
         if (!(std::isfinite(x) && x > 1.0)) return fail(nullptr, MBF_EINVAL, "every E must be finite and > 1");
-    hipStream_t st = (hipStream_t)stream;
     const size_t nphi = (size_t)n_E * M, nspec = (size_t)n_E * n_nu, nst = (size_t)n_E * mbf::kGpStats;
     double *dE = nullptr, *dphi = nullptr, *dspec = nullptr, *dst = nullptr;
     struct Free {
@@ -1559,8 +1565,11 @@ int mbf_pack_md(int n, const double* box, const double* diam, double* centres, c
         std::memcpy(dh.data(), diam, sizeof(double) * nn);
         std::memcpy(xh.data(), centres, sizeof(double) * 3 * nn);
     } else {
-        HIPCHK(nullptr, hipMemcpy(dh.data(), diam, sizeof(double) * nn, hipMemcpyDeviceToHost));
-        HIPCHK(nullptr, hipMemcpy(xh.data(), centres, sizeof(double) * 3 * nn, hipMemcpyDeviceToHost));
+        // read on the caller's stream: ordered after its work there
+        HIPCHK(nullptr, hipMemcpyAsync(dh.data(), diam, sizeof(double) * nn, hipMemcpyDeviceToHost, (hipStream_t)stream));
+        HIPCHK(nullptr, hipMemcpyAsync(xh.data(), centres, sizeof(double) * 3 * nn, hipMemcpyDeviceToHost,
+                                       (hipStream_t)stream));
+        HIPCHK(nullptr, hipStreamSynchronize((hipStream_t)stream));
     }
     double dmax = 0.0;
     for (double d : dh) {
