@@ -53,10 +53,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--n", type=int, default=320, help="cells per side")
     ap.add_argument("--batch", type=int, default=5)
-    ap.add_argument("--workload", choices=["c5", "c3", "pack"], default="c5",
+    ap.add_argument("--workload", choices=["c5", "c3", "pack", "gp"], default="c5",
                     help="c5: 320^3 batch of pump levels (default); c3: 64 small realizations "
                          "of uneven size, batched against one at a time; pack: the soft-sphere "
-                         "compression packing of the 320^3 sample")
+                         "compression packing of the 320^3 sample; gp: Gross-Pitaevskii bound "
+                         "states of a 256-point pump sweep")
     ap.add_argument("--pack-runs", type=int, default=5, help="timed packings of --workload pack")
     ap.add_argument("--packing", choices=["rsa", "md"], default="rsa",
                     help="c5 sample: random sequential addition (default) or the library's "
@@ -374,6 +375,50 @@ def pack_bench(args, I, mbf, stream):
     print(json.dumps(out), flush=True)
 
 
+GP_M, GP_L, GP_NU, GP_DNU = 1023, 14.0, 512, 0.02
+
+
+def gp_bench(args, mbf, stream):
+    """Bound states of the Gross-Pitaevskii equation for a pump sweep: 256
+    eigenvalues from just above threshold to E = 30 (log-spaced in E - 1),
+    1023 points on [-14, 14], 512 spectrum points; the oracle (continuation
+    and Newton in FP64 numpy) timed on a sample of the same eigenvalues."""
+    E = 1.0 + np.logspace(-3, math.log10(29.0), 256)
+    sid = stream.cuda_stream
+    mbf.mbf_gp_solve(E, M=GP_M, L=GP_L, n_nu=GP_NU, dnu=GP_DNU, stream=sid)       # warm-up
+    times = []
+    for _ in range(args.pack_runs):
+        t0 = time.perf_counter()
+        g = mbf.mbf_gp_solve(E, M=GP_M, L=GP_L, n_nu=GP_NU, dnu=GP_DNU, stream=sid)
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    ok = int(np.sum(g["converged"]))
+    log(f"gp: {len(E)} bound states in {best * 1e3:.2f} ms (best of {args.pack_runs}), {ok} converged, "
+        f"Newton steps {int(np.min(g['newton_steps']))}-{int(np.max(g['newton_steps']))}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import gp as OG
+        t0 = time.perf_counter()
+        k = 0
+        for e in E[::16]:
+            OG.gp_solve(float(e), GP_M, GP_L, GP_NU, GP_DNU)
+            k += 1
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": k / el, "unit": "bound states/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} of the 256 eigenvalues (every 16th), continuation and Newton in FP64 numpy"}
+        log(f"cpu baseline: {cpu}")
+    out = {"metric": "bound states/s", "value": len(E) / best, "unit": "bound states/s", "n_gpus": 1,
+           "steps": len(E), "warmup": 1, "ms_per_step": best / len(E) * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"Gross-Pitaevskii bound states, {len(E)} eigenvalues 1.001-30, "
+                                  f"M = {GP_M}, L = {GP_L}, {GP_NU} spectrum points",
+                      "ms_per_sweep": best * 1e3, "converged": ok},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_profile:
@@ -396,6 +441,9 @@ def main():
     stream = torch.cuda.Stream()
     if args.workload == "pack":
         pack_bench(args, I, mbf, stream)
+        return
+    if args.workload == "gp":
+        gp_bench(args, mbf, stream)
         return
     if args.workload == "c3":
         batch, cells, config, extra = c3_batch(args, I, mbf, stream)
