@@ -519,6 +519,23 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # what a plain streaming copy reaches on this device (reads 1 GiB, writes
+    # 1 GiB; best of 10, events on torch's stream where the add runs)
+    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.add(a, 1.0, out=b)
+    best_copy = float("inf")
+    for _ in range(10):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        torch.add(a, 1.0, out=b)
+        c1.record()
+        c1.synchronize()
+        best_copy = min(best_copy, c0.elapsed_time(c1) / 1e3)
+    copy_gbs = 2.0 * CALIB_BYTES / best_copy / 1e9
+    del a, b
+    log(f"plain copy: {copy_gbs:.0f} GB/s (the dominant kernel reaches {achieved / copy_gbs:.1%} of it)")
+
     cpu = None
     extra_out = {}
     if args.workload == "c3":
@@ -563,6 +580,7 @@ def main():
             # cell-updates/s priced at the dense 157 B per cell-update (every
             # cell with three gain sites), over the same peak
             "effective_frac_157B": value * DENSE_BYTES_PER_CU / (HBM_PEAK_GBS * 1e9),
+            "measured_copy_GBs": copy_gbs,
         },
         "cpu_baseline": cpu,
     }
