@@ -313,7 +313,7 @@ int mbf_spectral_peaks(const double* spec, int n_probes, int n_freq, double min_
 int mbf_read_field(mbf_handle* h, int field_id, void* dst, int mem_kind);
 int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 
-/* Kernel schedule.  Both variants give bitwise identical fields; they differ
+/* Kernel schedule.  All variants give bitwise identical fields; they differ
  * in how the step is cut into kernels.  Workgroups cover 64 x tile_y columns
  * over zseg planes (zseg = 0: 4).  xcd_remap chooses which XCD runs which
  * workgroup (the hardware deals launch-order workgroups to the 8 XCDs in
@@ -323,6 +323,12 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  * planes together.  tile_y must be 2, 4, 8 or 16.
  *   MBF_VARIANT_TWO_PASS (default: tile_y 4, zseg 4, xcd_remap 2): a1 in one kernel,
  *     a2-a5 in a second.
+ *   MBF_VARIANT_TWO_PASS_SPLIT: the same two passes; the second prefetches
+ *     only the dense fields of the next plane and loads the Bloch state at the
+ *     start of each plane, and the first writes H with streaming (non-
+ *     temporal) stores: fewer registers, more waves, faster on grids that
+ *     fill the device and exceed its caches (a batch of 320^3 realizations),
+ *     slower on small ones.
  *   MBF_VARIANT_FUSED: rows a1-a5 in one z-marching kernel in which every
  *     wave owns a row and forms again the few H^{n+1/2} values of the
  *     neighbouring row, column and plane that it needs (no LDS, no barrier).
@@ -333,6 +339,7 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  * Results do not depend on it. */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
+#define MBF_VARIANT_TWO_PASS_SPLIT 2
 typedef struct mbf_tuning {
     int32_t variant;
     int32_t tile_y;
@@ -343,7 +350,7 @@ typedef struct mbf_tuning {
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t);
 int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
 
-/* Time candidate schedules (both variants, tile_y 2/4/8, zseg 2/4/8; the
+/* Time candidate schedules (every variant, tile_y 2/4/8, zseg 2/4/8; the
  * default first) on the handle's own grid for about budget_ms (at least one
  * candidate), keep the fastest and report it in *chosen (may be NULL).  The
  * simulation state is saved to device memory before the trials and restored

@@ -312,6 +312,38 @@ void dispatch_order(std::vector<uint32_t>& items, int i0, int i1, const std::vec
     std::copy(out.begin(), out.end(), items.begin() + i0);
 }
 
+// The two passes of a step at tile height ty (evm recorded between them);
+// SPLIT: the split E pass and streaming H stores.
+template <typename T, bool SPLIT>
+hipError_t launch_two_pass(hipStream_t st, int ty, const mbf::SimView<T>* vw, const mbf::Geom* gw, const uint32_t* it,
+                           int ni, int rm, hipEvent_t evm) {
+    const dim3 g((unsigned)ni);
+    hipError_t e = hipSuccess;
+    switch (ty) {
+        case 2:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2, SPLIT>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2, SPLIT>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
+            break;
+        case 4:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4, SPLIT>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4, SPLIT>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
+            break;
+        case 16:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16, SPLIT>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16, SPLIT>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
+            break;
+        default:
+            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8, SPLIT>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
+            if (evm) e = hipEventRecord(evm, st);
+            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8, SPLIT>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
+            break;
+    }
+    return e;
+}
+
 // The field kernels of one step (both passes, or the fused pass) over the
 // work table it[0..ni) of the views vw and geometries gw; evm (optional) is
 // recorded between the two passes.
@@ -331,29 +363,8 @@ hipError_t launch_fields(hipStream_t st, const mbf_tuning& tun, const mbf::SimVi
         if (evm) e = hipEventRecord(evm, st);
         return e;
     }
-    switch (tun.tile_y) {
-        case 2:
-            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
-            if (evm) e = hipEventRecord(evm, st);
-            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm);
-            break;
-        case 4:
-            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
-            if (evm) e = hipEventRecord(evm, st);
-            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm);
-            break;
-        case 16:
-            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
-            if (evm) e = hipEventRecord(evm, st);
-            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm);
-            break;
-        default:
-            hipLaunchKernelGGL((mbf::k_curl_h_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
-            if (evm) e = hipEventRecord(evm, st);
-            hipLaunchKernelGGL((mbf::k_curl_e_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm);
-            break;
-    }
-    return e;
+    if (tun.variant == MBF_VARIANT_TWO_PASS_SPLIT) return launch_two_pass<T, true>(st, tun.tile_y, vw, gw, it, ni, rm, evm);
+    return launch_two_pass<T, false>(st, tun.tile_y, vw, gw, it, ni, rm, evm);
 }
 
 // A handle steps through the same kernels as a batch, as a batch of one: its
@@ -636,7 +647,7 @@ void snap_free(Snap& s) {
 std::vector<mbf_tuning> tuning_candidates() {
     std::vector<mbf_tuning> c;
     c.push_back({MBF_VARIANT_TWO_PASS, 4, 4, 2, 0});
-    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED})
+    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED})
         for (int ty : {2, 4, 8})
             for (int zs : {2, 4, 8})
                 if (!(var == MBF_VARIANT_TWO_PASS && ty == 4 && zs == 4)) c.push_back({var, ty, zs, 2, 0});
@@ -1251,7 +1262,7 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes) {
 
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
     if (!h || !t) return fail(h, MBF_EINVAL, "null argument");
-    if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS)
+    if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS && t->variant != MBF_VARIANT_TWO_PASS_SPLIT)
         return fail(h, MBF_EINVAL, "unknown variant");
     if (t->tile_y != 2 && t->tile_y != 4 && t->tile_y != 8 && t->tile_y != 16)
         return fail(h, MBF_EINVAL, "tile_y must be 2, 4, 8 or 16");

@@ -201,6 +201,12 @@ __device__ __forceinline__ void sto(T* base, uint32_t off, T val) {
     MBF_GLOBAL char* b = (MBF_GLOBAL char*)base;
     *(MBF_GLOBAL T*)(b + off * (uint32_t)sizeof(T)) = val;
 }
+// Streaming store (non-temporal: the line is not kept in the caches).
+template <typename T>
+__device__ __forceinline__ void sto_nt(T* base, uint32_t off, T val) {
+    MBF_GLOBAL char* b = (MBF_GLOBAL char*)base;
+    __builtin_nontemporal_store(val, (MBF_GLOBAL T*)(b + off * (uint32_t)sizeof(T)));
+}
 template <typename T>
 __device__ __forceinline__ T gld(const T* p) {
     return *(const MBF_GLOBAL T*)p;
@@ -383,7 +389,9 @@ __device__ __forceinline__ void load_hplane(HPlane<T>& p, const Fields<T>& f, co
     p.m = ldo(mat, x);
 }
 
-template <typename T, int TY>
+// NT: H^{n+1/2} leaves by streaming stores (for grids far larger than the
+// caches, where the E pass reads it back from HBM anyway).
+template <typename T, int TY, bool NT>
 __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
     int bx, by, bz;
@@ -424,9 +432,15 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             const T nhx = h_update(hx, v.S, cx, ax);
             const T nhy = h_update(hy, v.S, cy, ay);
             const T nhz = h_update(hz, v.S, cz, az);
-            sto(f.hn[0], x, nhx);
-            sto(f.hn[1], x, nhy);
-            sto(f.hn[2], x, nhz);
+            if constexpr (NT) {
+                sto_nt(f.hn[0], x, nhx);
+                sto_nt(f.hn[1], x, nhy);
+                sto_nt(f.hn[2], x, nhz);
+            } else {
+                sto(f.hn[0], x, nhx);
+                sto(f.hn[1], x, nhy);
+                sto(f.hn[2], x, nhz);
+            }
             const T eps = gld(v.lut_eps + P.m);
             if (v.map != nullptr && k == v.map_k) plane_energy(v, i, j, eps, ex, ey, ez, nhx, nhy, nhz);
             T acc = (T)0;
@@ -448,13 +462,13 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
 
 // The tables are separate no-alias read-only arguments, so the compiler may
 // keep the member's view in scalar registers across the kernel's stores.
-template <typename T, int TY>
+template <typename T, int TY, bool NT>
 __global__ void __launch_bounds__(64 * TY) k_curl_h_batch(const SimView<T>* __restrict__ views,
                                                 const Geom* __restrict__ geoms,
                                                 const uint32_t* __restrict__ items, int nitems, int remap) {
     int r, w;
     batch_item(items, nitems, remap, r, w);
-    curl_h_body<T, TY>(views[r], geoms[r], w);
+    curl_h_body<T, TY, NT>(views[r], geoms[r], w);
 }
 
 // ---------------------------------------------------- rows a2, a3, a4, a5
@@ -553,14 +567,11 @@ struct EPlane {
     T ex, ey, ez, hx, hy, hz, hzy, hzx, hyx, hxy;
 };
 
+// The dense part of a plane (E and H of the cell, H at y-1 and x-1).
 // Neighbours at y-1 only for j >= 1 and at x-1 only for i >= 1 (the offsets
 // would wrap below zero otherwise).
 template <typename T>
-__device__ __forceinline__ void load_plane(EPlane<T>& p, const Fields<T>& f, uint32_t x, uint32_t sx,
-                                           uint32_t gi, bool g, bool inx, bool iny, bool inz, int i, int j) {
-    p.b0 = bloch_load(f, 0, gi, g && inx);
-    p.b1 = bloch_load(f, 1, gi, g && iny);
-    p.b2 = bloch_load(f, 2, gi, g && inz);
+__device__ __forceinline__ void load_dense(EPlane<T>& p, const Fields<T>& f, uint32_t x, uint32_t sx, int i, int j) {
     p.hx = ldo(f.hn[0], x); p.hy = ldo(f.hn[1], x); p.hz = ldo(f.hn[2], x);
     p.hzy = j >= 1 ? ldo(f.hn[2], x - sx) : (T)0;
     p.hxy = j >= 1 ? ldo(f.hn[0], x - sx) : (T)0;
@@ -569,7 +580,24 @@ __device__ __forceinline__ void load_plane(EPlane<T>& p, const Fields<T>& f, uin
     p.ex = ldo(f.e[0], x); p.ey = ldo(f.e[1], x); p.ez = ldo(f.e[2], x);
 }
 
-template <typename T, int TY>
+// A whole plane: the Bloch state of its three sites and the dense part.
+template <typename T>
+__device__ __forceinline__ void load_plane(EPlane<T>& p, const Fields<T>& f, uint32_t x, uint32_t sx,
+                                           uint32_t gi, bool g, bool inx, bool iny, bool inz, int i, int j) {
+    p.b0 = bloch_load(f, 0, gi, g && inx);
+    p.b1 = bloch_load(f, 1, gi, g && iny);
+    p.b2 = bloch_load(f, 2, gi, g && inz);
+    load_dense(p, f, x, sx, i, j);
+}
+
+// SPLIT selects what goes out one plane ahead: the whole next plane (false),
+// or only its dense part, the Bloch state being loaded at the start of its
+// own plane (true).  The whole plane keeps 90 VGPRs (5 waves per SIMD) and
+// hides the Bloch loads behind a plane of work, which pays on small grids
+// that leave most of the chip idle; the split keeps 76 (6 waves) and streams
+// faster where the work fills the chip (a 320^3 batch; there the first pass
+// also writes H with streaming stores, NT).
+template <typename T, int TY, bool SPLIT>
 __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
     int bx, by, bz;
@@ -592,17 +620,25 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
         T hxm = kz0 >= 1 ? ldo(f.hn[0], x - sxy) : (T)0;
         T hym = kz0 >= 1 ? ldo(f.hn[1], x - sxy) : (T)0;
         EPlane<T> P, Q;
-        load_plane(P, f, x, sx, gi, m >= kGainId, j >= 1 && kz0 >= 1, iny0 && kz0 >= 1, inz0, i, j);
+        if constexpr (SPLIT) load_dense(P, f, x, sx, i, j);
+        else load_plane(P, f, x, sx, gi, m >= kGainId, j >= 1 && kz0 >= 1, iny0 && kz0 >= 1, inz0, i, j);
         for (int k = kz0; k < kz1; ++k, x += sxy) {
             // software pipelining: the next plane's loads (its compact index
             // from the material byte read one plane earlier) go out before this
-            // plane's arithmetic and stores, so two planes are in flight per wave
+            // plane's arithmetic and stores, so two planes are in flight per
+            // wave; with SPLIT the plane's own Bloch state goes out first
+            if constexpr (SPLIT) {
+                P.b0 = bloch_load(f, 0, gi, m >= kGainId && j >= 1 && k >= 1);
+                P.b1 = bloch_load(f, 1, gi, m >= kGainId && iny0 && k >= 1);
+                P.b2 = bloch_load(f, 2, gi, m >= kGainId && inz0);
+            }
             uint32_t gi_n = 0;
             uint8_t m_nn = 0;
             if (k + 1 < kz1) {
                 gi_n = gain_index(v, bx, j, k + 1, m_n >= kGainId, true);
                 if (k + 2 < kz1) m_nn = ldo(v.mat, x + 2u * sxy);
-                load_plane(Q, f, x + sxy, sx, gi_n, m_n >= kGainId, j >= 1, iny0, inz0, i, j);
+                if constexpr (SPLIT) load_dense(Q, f, x + sxy, sx, i, j);
+                else load_plane(Q, f, x + sxy, sx, gi_n, m_n >= kGainId, j >= 1, iny0, inz0, i, j);
             }
             const bool g = m >= kGainId;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
@@ -658,13 +694,13 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
 
 // The tables are separate no-alias read-only arguments, so the compiler may
 // keep the member's view in scalar registers across the kernel's stores.
-template <typename T, int TY>
+template <typename T, int TY, bool SPLIT>
 __global__ void __launch_bounds__(64 * TY) k_curl_e_batch(const SimView<T>* __restrict__ views,
                                                 const Geom* __restrict__ geoms,
                                                 const uint32_t* __restrict__ items, int nitems, int remap) {
     int r, w;
     batch_item(items, nitems, remap, r, w);
-    curl_e_body<T, TY>(views[r], geoms[r], w);
+    curl_e_body<T, TY, SPLIT>(views[r], geoms[r], w);
 }
 
 // ------------------------------------------------ fused step (a1 to a5)

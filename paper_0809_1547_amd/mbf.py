@@ -75,8 +75,9 @@ class mbf_spec_stats(C.Structure):
                 ("fit_ok", C.c_int32)]
 
 
-MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED = 0, 1
-_VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED}
+MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED, MBF_VARIANT_TWO_PASS_SPLIT = 0, 1, 2
+_VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED,
+             "two_pass_split": MBF_VARIANT_TWO_PASS_SPLIT}
 
 
 def _load():
