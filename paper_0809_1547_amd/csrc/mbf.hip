@@ -884,12 +884,18 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
     std::vector<uint8_t> cell_id(ncell);
     std::vector<float> lut_eps(mbf::kMaxMat, 1.0f);
     int next_id[2] = {0, mbf::kGainId};
+    uint32_t last_bits = 0;
+    int last_g = -1, last_id = 0;       // neighbouring cells mostly share a material
     for (size_t q = 0; q < ncell; ++q) {
         const float e = eps[q];
         if (!(std::isfinite(e) && e > 0.0f)) return fail(h, MBF_EINVAL, "eps_r must be finite and > 0");
         uint32_t bits;
         std::memcpy(&bits, &e, 4);
         const uint8_t gq = g[q] ? 1 : 0;
+        if (bits == last_bits && gq == last_g) {
+            cell_id[q] = (uint8_t)last_id;
+            continue;
+        }
         const auto key = std::make_pair(bits, gq);
         auto it = ids.find(key);
         int id;
@@ -903,6 +909,9 @@ int mbf_set_material(mbf_handle* h, const float* eps_r, const uint8_t* gain, int
             id = it->second;
         }
         cell_id[q] = (uint8_t)id;
+        last_bits = bits;
+        last_g = gq;
+        last_id = id;
     }
     // site bytes on the extended range: the cell (i, j, k) clamped to n-1
     std::vector<uint8_t> site((size_t)h->nsite);

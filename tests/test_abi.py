@@ -58,10 +58,14 @@ def test_create_rejects_bad_configs_before_allocating(field, value, code):
 
 
 @pytest.mark.parametrize("n,precision", [((16, 65535, 16), "fp32"), ((16, 16, 70000), "fp32"),
-                                         ((1100, 1100, 1100), "fp32"), ((820, 820, 820), "fp64")])
+                                         ((1100, 1100, 1100), "fp32"), ((820, 820, 820), "fp64"),
+                                         ((1023, 1023, 1023), "fp32")])
 def test_create_rejects_grids_beyond_the_limits(n, precision):
     # 16-bit grid rows/planes of the launch and 32-bit site offsets: ny, nz <
     # 65535 and one site array below 4 GiB, checked before any allocation
+    # (1023^3 is the first cube past it: 1024^3 sites of 4 bytes; 1023 x 1023
+    # x 1022, one plane less, is the largest accepted grid and is stepped in
+    # tests/test_gpu_maxsize.py)
     from paper_0809_1547_amd import mbf
     c = mbf.mbf_config_default(*n)
     c.precision = mbf.MBF_FP64 if precision == "fp64" else mbf.MBF_FP32
