@@ -143,3 +143,30 @@ def test_paper_scale_packing():
     vf = float(np.mean(eps > 1.0))
     print(f"  voxel fill {vf:.4f}")
     assert vf >= 0.39
+
+
+def test_large_box_packing():
+    # a 1000^3 box (20 um) at fill 0.4: about 220,000 spheres, 51^3 cells.
+    # Two steps against the oracle element by element (all pairs: 4.8e10
+    # pair terms per step); the whole compression by its properties, the
+    # largest overlap checked over every pair closer than the largest
+    # diameter (a k-d tree on the test side) and run-to-run identity
+    from scipy.spatial import cKDTree
+    mbf = _mbf()
+    box, d, x = I.pack_start(1000, seed=12, fill=0.4)
+    print(f"1000^3: {len(d)} spheres", flush=True)
+    short = dict(s0=1.0, stages=0, iters=0, final_iters=2, eta=0.15)
+    got, _, _ = mbf.mbf_pack_md(box, d, x, **short)
+    want = O.pack_md(box, d, x, **short)
+    assert np.max(np.abs(got - want)) <= TOL_X * 1000.0
+    print("1000^3: two steps match; full compression", flush=True)
+    full, U, ov = mbf.mbf_pack_md(box, d, x, **SCHED)
+    again, U2, ov2 = mbf.mbf_pack_md(box, d, x, **SCHED)
+    assert np.array_equal(full, again) and U == U2 and ov == ov2
+    pairs = cKDTree(full).query_pairs(r=float(np.max(d)), output_type="ndarray")
+    r = np.sqrt(np.sum((full[pairs[:, 0]] - full[pairs[:, 1]]) ** 2, axis=1))
+    ovp = float(np.max(0.5 * (d[pairs[:, 0]] + d[pairs[:, 1]]) - r))
+    rad = 0.5 * d[:, None]
+    bo = max(ovp, float(np.max(rad - full)), float(np.max(full + rad - box)))
+    print(f"  U = {U:.3e}, largest overlap {ov:.3e} (k-d tree {bo:.3e})")
+    assert ov <= 1e-3 * 15.0 and abs(bo - ov) <= 1e-9 * 15.0
