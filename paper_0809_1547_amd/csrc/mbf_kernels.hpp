@@ -958,12 +958,18 @@ constexpr int kEndThreads = 1024;
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* sh) {
     const int t = threadIdx.x;
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int q = t; q < n; q += 8 * kEndThreads) {
+    // accumulator r adds p[t + r K], p[t + (r + 8) K], ... in that order (K
+    // threads); 32 loads go out per round.  Past the end they read as +0,
+    // which changes no sum: an accumulator starts at +0 and so is never -0.
+    for (int q = t; q < n; q += 32 * kEndThreads) {
+        double v[32];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int e = q + r * kEndThreads;
-            if (e < n) a[r] += p[e];
+        for (int s = 0; s < 32; ++s) {
+            const int e = q + s * kEndThreads;
+            v[s] = e < n ? p[e] : 0.0;
         }
+#pragma unroll
+        for (int s = 0; s < 32; ++s) a[s & 7] += v[s];
     }
     double x = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     x = wave_sum(x);
