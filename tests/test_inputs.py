@@ -70,3 +70,18 @@ def test_dft_grid_resolution():
     df = np.diff(w) / (2 * math.pi)
     assert np.allclose(df, 1 / (5000 * 3.81315e-17))
     assert 50 <= len(w) <= 60
+
+
+def test_pack_start_draws():
+    # seeded; the count is the first at which the whole-sphere volume reaches
+    # the target; diameters within +-3 sd; centres inside the box
+    box, d, x = I.pack_start((40, 36, 32), seed=3, fill=0.4, mean_d=6.0, sd_d=0.6)
+    b2, d2, x2 = I.pack_start((40, 36, 32), seed=3, fill=0.4, mean_d=6.0, sd_d=0.6)
+    assert np.array_equal(d, d2) and np.array_equal(x, x2) and np.array_equal(box, [40.0, 36.0, 32.0])
+    vol = math.pi / 6 * np.cumsum(d ** 3)
+    assert vol[-1] >= 0.4 * np.prod(box) > vol[-2]
+    assert np.all(np.abs(d - 6.0) <= 1.8) and x.shape == (len(d), 3)
+    assert np.all(x >= 0.0) and np.all(x < box)
+    assert not np.array_equal(x, I.pack_start((40, 36, 32), seed=4, fill=0.4, mean_d=6.0, sd_d=0.6)[2])
+    pk = I.packing_from_centres((40, 36, 32), d, x)
+    assert pk.count == len(d) and np.array_equal(pk.radii, 0.5 * d)
