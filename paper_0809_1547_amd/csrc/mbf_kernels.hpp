@@ -619,6 +619,15 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
         uint8_t m_n = (kz0 + 1 < kz1) ? ldo(v.mat, x + sxy) : (uint8_t)0;
         T hxm = kz0 >= 1 ? ldo(f.hn[0], x - sxy) : (T)0;
         T hym = kz0 >= 1 ? ldo(f.hn[1], x - sxy) : (T)0;
+        // the layer's x and y profile values of this column and row stay
+        // fixed along the march in z (loss_e, summed in the same order)
+        T px0 = (T)0, px1 = (T)0, py0 = (T)0, py1 = (T)0;
+        if (v.has_layer) {
+            px0 = gld(v.prof[0][0] + i);
+            px1 = gld(v.prof[0][1] + i);
+            py0 = gld(v.prof[1][0] + j);
+            py1 = gld(v.prof[1][1] + j);
+        }
         EPlane<T> P, Q;
         if constexpr (SPLIT) load_dense(P, f, x, sx, i, j);
         else load_plane(P, f, x, sx, gi, m >= kGainId, j >= 1 && kz0 >= 1, iny0 && kz0 >= 1, inz0, i, j);
@@ -650,27 +659,31 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             }
             T s0, s1, s2;
             source3(v, i, j, k, n, s0, s1, s2);
+            T la0 = (T)0, la1 = (T)0, la2 = (T)0;
+            if (v.has_layer) {
+                const T pz0 = gld(v.prof[2][0] + k), pz1 = gld(v.prof[2][1] + k);
+                la0 = (px1 + py0) + pz0;
+                la1 = (px0 + py1) + pz0;
+                la2 = (px0 + py0) + pz1;
+            }
             T acc = (T)0;
             {
                 const T curl = inx ? (P.hz - P.hzy) - (P.hy - hym) : (T)0;
-                const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0,
-                                        v.has_layer ? loss_e(v, 0, i, j, k) : (T)0, tslot);
+                const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0, la0, tslot);
                 sto(f.en[0], x, en);
                 if (tslot) sto(tslot, x, en);
                 if (inx) acc += en * en;
             }
             {
                 const T curl = iny ? (P.hx - hxm) - (P.hz - P.hzx) : (T)0;
-                const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1,
-                                        v.has_layer ? loss_e(v, 1, i, j, k) : (T)0, tslot);
+                const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1, la1, tslot);
                 sto(f.en[1], x, en);
                 if (tslot) sto(tslot + v.tap_e, x, en);
                 if (iny) acc += en * en;
             }
             {
                 const T curl = inz ? (P.hy - P.hyx) - (P.hx - P.hxy) : (T)0;
-                const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2,
-                                        v.has_layer ? loss_e(v, 2, i, j, k) : (T)0, tslot);
+                const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2, la2, tslot);
                 sto(f.en[2], x, en);
                 if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                 if (inz) acc += en * en;
