@@ -600,6 +600,11 @@ __device__ __forceinline__ void load_plane(EPlane<T>& p, const Fields<T>& f, uin
 template <typename T, int TY, bool SPLIT>
 __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
+    // the member's 1/eps_r table in LDS: one gather per plane fewer on the
+    // vector memory path
+    __shared__ T s_ie[kMaxMat];
+    for (int q = (int)(threadIdx.x + 64 * threadIdx.y); q < kMaxMat; q += 64 * TY) s_ie[q] = gld(v.lut_inv_eps + q);
+    __syncthreads();
     int bx, by, bz;
     decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
@@ -651,7 +656,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             }
             const bool g = m >= kGainId;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
-            const T ie = gld(v.lut_inv_eps + m);
+            const T ie = s_ie[m];
             T xi[3] = {(T)0, (T)0, (T)0};
             if (g && v.noise && (inx || iny || inz)) {
                 const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
