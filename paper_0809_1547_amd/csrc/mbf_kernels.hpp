@@ -735,6 +735,14 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e_batch(const SimView<T>* __re
 template <typename T, int TY>
 __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom& gm, int w) {
     __shared__ double sh[TY];
+    // the member's eps_r and 1/eps_r tables in LDS: two gathers per plane
+    // fewer on the vector memory path
+    __shared__ T s_ie[kMaxMat], s_eps[kMaxMat];
+    for (int q = (int)(threadIdx.x + 64 * threadIdx.y); q < kMaxMat; q += 64 * TY) {
+        s_ie[q] = gld(v.lut_inv_eps + q);
+        s_eps[q] = gld(v.lut_eps + q);
+    }
+    __syncthreads();
     int bx, by, bz;
     decode_item(gm, w, bx, by, bz);
     const int i = bx * 64 + threadIdx.x;
@@ -802,7 +810,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 sto(f.hn[0], x, nhx);
                 sto(f.hn[1], x, nhy);
                 sto(f.hn[2], x, nhz);
-                const T eps = gld(v.lut_eps + m);
+                const T eps = s_eps[m];
                 if (v.map != nullptr && k == v.map_k) plane_energy(v, i, j, eps, ex, ey, ez, nhx, nhy, nhz);
                 T acc = (T)0;
                 if (j >= 1 && k >= 1) acc += eps * ex * ex;
@@ -837,7 +845,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             }
             // ---- a2-a5 on the own row
             if (act) {
-                const T ie = gld(v.lut_inv_eps + m);
+                const T ie = s_ie[m];
                 T xi[3] = {(T)0, (T)0, (T)0};
                 if (g && v.noise && (inx || iny || inz)) {
                     const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
