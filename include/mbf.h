@@ -315,14 +315,14 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 
 /* Kernel schedule.  All variants give bitwise identical fields; they differ
  * in how the step is cut into kernels.  Workgroups cover 64 x tile_y columns
- * over zseg planes (zseg = 0: 4).  xcd_remap chooses which XCD runs which
+ * over zseg planes (zseg = 0: 2 for MBF_VARIANT_TWO_PASS_SPLIT, 4 for the
+ * others).  xcd_remap chooses which XCD runs which
  * workgroup (the hardware deals launch-order workgroups to the 8 XCDs in
  * turn): 0 launch order; 1 each XCD a contiguous range of (x tile, y tile,
  * z segment) work items; 2 (default) whole z-segment layers dealt to the XCDs
  * in turn, so neighbouring tiles share an L2 and the XCDs stream one window of
  * planes together.  tile_y must be 2, 4, 8 or 16.
- *   MBF_VARIANT_TWO_PASS (default: tile_y 4, zseg 4, xcd_remap 2): a1 in one kernel,
- *     a2-a5 in a second.
+ *   MBF_VARIANT_TWO_PASS: a1 in one kernel, a2-a5 in a second.
  *   MBF_VARIANT_TWO_PASS_SPLIT: the same two passes; the second prefetches
  *     only the dense fields of the next plane and loads the Bloch state at the
  *     start of each plane, and the first writes H with streaming (non-
@@ -331,12 +331,16 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  *     slower on small ones.
  *   MBF_VARIANT_FUSED: rows a1-a5 in one z-marching kernel in which every
  *     wave owns a row and forms again the few H^{n+1/2} values of the
- *     neighbouring row, column and plane that it needs (no LDS, no barrier).
+ *     neighbouring row, column and plane that it needs (waves exchange no
+ *     field values).
  * group_mb (batches only; >= 0): consecutive members whose device state adds
  * up to at most group_mb MiB form a group, and a graph-replayed chunk of
  * steps runs group by group, so that a group's state can stay in the
  * device's last-level cache over the chunk; 0 puts all members in one group.
- * Results do not depend on it. */
+ * Results do not depend on it.
+ * Default schedule (also the autotuner's first candidate): tile_y 4, zseg 0,
+ * xcd_remap 2, group_mb 0, MBF_VARIANT_TWO_PASS_SPLIT for a grid of at least
+ * 4 Mi cells (for a batch: its largest member), MBF_VARIANT_TWO_PASS below. */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 #define MBF_VARIANT_TWO_PASS_SPLIT 2

@@ -723,8 +723,9 @@ __global__ void __launch_bounds__(64 * TY) k_curl_e_batch(const SimView<T>* __re
 
 // ------------------------------------------------ fused step (a1 to a5)
 // Each wave owns one row (64 sites along x) of a 64 x TY tile and marches
-// along z over a segment [z0, z1) of planes; the waves never wait for each
-// other (no LDS, no barrier).  Per plane k a wave forms H^{n+1/2}(k) on its own
+// along z over a segment [z0, z1) of planes; after one barrier (the material
+// tables into LDS) the waves never wait for each other and exchange no field
+// values.  Per plane k a wave forms H^{n+1/2}(k) on its own
 // row and stores it, forms again the two components of row j-1 that its E
 // update needs (Hx, Hz), takes Hy and Hz at x-1 from the next lower lane (lane
 // 0 forms them again at the tile edge), and then updates E, P and the
