@@ -184,3 +184,21 @@ def test_member_schedule_change_does_not_break_batched_steps():
             assert np.array_equal(batch[r].field(f), solo.field(f)), (r, f)
         solo.close()
     batch.close()
+
+
+def test_default_schedule_follows_grid_size():
+    # the split two-pass variant over 2-plane segments from 4 Mi cells on,
+    # the whole-plane two-pass variant over 4-plane segments below (the
+    # tuning reads back the segment length in effect); a batch goes by its
+    # largest member
+    mbf = _mbf()
+    for n, want, zs in (((96, 96, 96), "two_pass", 4), ((160, 160, 163), "two_pass", 4),
+                        ((160, 160, 164), "two_pass_split", 2), ((320, 320, 320), "two_pass_split", 2)):
+        s = mbf.Sim(n)
+        t = s.tuning()
+        assert (t["variant"], t["tile_y"], t["zseg"], t["xcd_remap"]) == (want, 4, zs, 2), (n, t)
+        s.close()
+    b = mbf.Batch([mbf.make_config(m) for m in ((48, 48, 48), (160, 160, 164), (64, 64, 64))])
+    assert b.tuning()["variant"] == "two_pass_split" and all(b[r].tuning()["variant"] == "two_pass_split"
+                                                               for r in range(3))
+    b.close()
