@@ -1,6 +1,7 @@
-"""GPU: the largest grid the library accepts (one FP32 site array just below
-4 GiB: 1023 x 1023 x 1022 cells, 1.07e9 sites per array, about 52 GB of field
-state), stepped through the C ABI.  A localized field in the far corner
+"""GPU: the largest grids the library accepts (one site array just below
+4 GiB: 1023 x 1023 x 1022 cells in FP32, 1.07e9 sites per array, and 1023 x
+1023 x 510 in FP64; about 52 GB of field state either way), stepped through
+the C ABI.  A localized field in the far corner
 (where the 32-bit byte offsets are largest) spreads by at most one cell per
 step, so its whole light cone, walls included, is reproduced by the oracle on
 an 80^3 grid holding the same corner: the two are compared element by element
@@ -13,41 +14,42 @@ from paper_0809_1547_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-N = (1023, 1023, 1022)
 SUB = 80                 # the oracle's grid: the last SUB cells of each axis
 STEPS = 20
-TOL32 = 1e-5
 
 
-def test_largest_grid_far_corner_matches_oracle():
+@pytest.mark.parametrize("N,precision,tol", [((1023, 1023, 1022), "fp32", 1e-5), ((1023, 1023, 510), "fp64", 1e-11)])
+def test_largest_grid_far_corner_matches_oracle(N, precision, tol):
     import torch
     from paper_0809_1547_amd import mbf
     nx, ny, nz = N
+    fp64 = precision == "fp64"
+    tdt = torch.float64 if fp64 else torch.float32
     o0 = (nx - SUB, ny - SUB, nz - SUB)          # GPU index of the oracle's origin
-    print(f"max-size grid {N}: material", flush=True)
+    print(f"max-size grid {N} {precision}: material", flush=True)
     # homogeneous eps 2.25, gain in a 20^3 block around the initial field
     eps = np.full((nz, ny, nx), 2.25, dtype=np.float32)
     gain = np.zeros((nz, ny, nx), dtype=np.uint8)
     gain[o0[2] + 45:o0[2] + 65, o0[1] + 45:o0[1] + 65, o0[0] + 45:o0[0] + 65] = 1
-    sim = mbf.Sim(N, boundary="pec", noise=False)
+    sim = mbf.Sim(N, boundary="pec", noise=False, precision=precision)
     sim.set_material(eps, gain)
     sim.set_pump(2e24, "prepumped")
     sub_eps = eps[-SUB:, -SUB:, -SUB:].copy()
     sub_gain = gain[-SUB:, -SUB:, -SUB:].copy()
     del eps, gain
-    ora = O.Oracle(O.default_params((SUB, SUB, SUB), round_f32=True, noise=False))
+    ora = O.Oracle(O.default_params((SUB, SUB, SUB), round_f32=not fp64, noise=False))
     ora.set_material(sub_eps, sub_gain)
     ora.set_pump(2e24, O.PREPUMPED)
     # a seeded random E field in the block [50, 60)^3 of the oracle's grid
     rng = np.random.default_rng(17)
-    dev = torch.zeros((nz + 1, ny + 1, nx + 1), dtype=torch.float32, device="cuda")
+    dev = torch.zeros((nz + 1, ny + 1, nx + 1), dtype=tdt, device="cuda")
     for c in range(3):
         blk = rng.standard_normal((10, 10, 10)).astype(np.float32)
         sub = np.zeros((SUB + 1,) * 3)
         sub[50:60, 50:60, 50:60] = blk
         ora.set_field(c, sub)
         dev.zero_()
-        dev[o0[2] + 50:o0[2] + 60, o0[1] + 50:o0[1] + 60, o0[0] + 50:o0[0] + 60] = torch.from_numpy(blk).cuda()
+        dev[o0[2] + 50:o0[2] + 60, o0[1] + 50:o0[1] + 60, o0[0] + 50:o0[0] + 60] = torch.from_numpy(blk).to(tdt).cuda()
         torch.cuda.synchronize()
         mbf.mbf_write_field(sim.h, c, dev)
         sim.sync()
@@ -69,8 +71,8 @@ def test_largest_grid_far_corner_matches_oracle():
             continue
         err = float(np.max(np.abs(got - want))) / scale
         worst = max(worst, err)
-        assert err <= TOL32, (f, err)
+        assert err <= tol, (f, err)
     Wg, Wo = sim.energy()[0], ora.energy()[0]
     print(f"max-size grid: worst field error {worst:.2e}; energy {Wg:.9e} vs {Wo:.9e}", flush=True)
-    assert abs(Wg - Wo) <= TOL32 * abs(Wo)
+    assert abs(Wg - Wo) <= tol * abs(Wo)
     sim.close()
