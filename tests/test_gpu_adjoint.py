@@ -79,11 +79,15 @@ def test_fp32_adjoint_matches_oracle():
 
 
 def test_checkpoint_interval_does_not_change_the_gradient_and_run_ends_at_nsteps():
+    # nor does the schedule of the forward (the split and fused variants
+    # recompute the segments and record the trajectory as well)
     mbf = _mbf()
     eps, gain = _material((40, 36, 28), seed=3, fill=0.4)
     out = []
-    for K in (90, 7, 32):
+    for K, var in ((90, None), (7, None), (32, None), (32, "two_pass_split"), (7, "fused")):
         sim = mbf.Sim((40, 36, 28), boundary="absorb", seed=9, realization=3, E_sp=1e-3)
+        if var:
+            sim.set_tuning(var, tile_y=4, zseg=2, xcd_remap=2)
         sim.set_material(eps, gain)
         sim.set_pump(2e24)
         sim.set_source(2, 20, 18, 14, amp=0.2)
