@@ -260,6 +260,28 @@ def test_kernel_variants_are_bitwise_identical(bc):
         sim.close()
 
 
+def test_kernel_variants_are_bitwise_identical_in_fp64():
+    n = (70, 37, 29)
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=12, fill=0.35))
+    mbf = _mbf()
+    ref = None
+    for var, ty, zs, remap in [("two_pass", 4, 0, 2), ("two_pass_split", 4, 2, 2), ("two_pass_split", 16, 29, 1),
+                               ("two_pass_split", 2, 1, 0), ("fused", 4, 0, 2)]:
+        sim = mbf.Sim(n, boundary="absorb", E_sp=1e-2, precision="fp64")
+        sim.set_tuning(var, tile_y=ty, zseg=zs, xcd_remap=remap)
+        sim.set_material(eps, gain)
+        sim.set_pump(2e24)
+        sim.set_source(*I.nearest_void_site(gain), amp=0.5)
+        sim.step(60)
+        st = [sim.field(f) for f in range(21)]
+        if ref is None:
+            ref = st
+        else:
+            for a, b in zip(ref, st):
+                assert np.array_equal(a, b), (var, ty, zs)
+        sim.close()
+
+
 def _state(sim):
     return [sim.field(f).copy() for f in range(21)]
 
