@@ -105,6 +105,13 @@ static double site_loss(const orc_sim* s, int is_h, int c, int i, int j, int k) 
     return a;
 }
 
+/* Coefficients of the semi-implicit lossy update of a site with loss a:
+ * X' = ca X + cb (increment), ca = (1 - a)/(1 + a), cb = 1/(1 + a).  Like
+ * every other coefficient they are formed in FP64 and, with round_f32,
+ * rounded once to binary32. */
+static double layer_ca(const orc_sim* s, double a) { return rnd(s, (1.0 - a) / (1.0 + a)); }
+static double layer_cb(const orc_sim* s, double a) { return rnd(s, 1.0 / (1.0 + a)); }
+
 /* ---------------------------------------------------------------- Philox */
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
@@ -492,7 +499,7 @@ static void update_h(orc_sim* s) {
                         s->Hn[c][x] = H3[c][x] - S * c3[c];
                     } else {
                         /* semi-implicit loss: (H' - H) = -S curl - a (H' + H) */
-                        s->Hn[c][x] = ((1.0 - a) / (1.0 + a)) * H3[c][x] - (1.0 / (1.0 + a)) * (S * c3[c]);
+                        s->Hn[c][x] = layer_ca(s, a) * H3[c][x] - layer_cb(s, a) * (S * c3[c]);
                     }
                 }
             }
@@ -574,8 +581,8 @@ static void update_e(orc_sim* s) {
                     if (a == 0.0)
                         s->f[c][x] = s->Eold[c][x] + ie * (S * curl - dP);
                     else
-                        s->f[c][x] = ((1.0 - a) / (1.0 + a)) * s->Eold[c][x] +
-                                     (1.0 / (1.0 + a)) * (ie * (S * curl - dP));
+                        s->f[c][x] = layer_ca(s, a) * s->Eold[c][x] +
+                                     layer_cb(s, a) * (ie * (S * curl - dP));
                 }
             }
     for (int c = 0; c < 3; ++c) memcpy(s->f[3 + c], s->Hn[c], sizeof(double) * s->ntot);
@@ -794,7 +801,7 @@ static void tangent_step(const orc_sim* s, state_t X0, state_t X1, double* const
             for (int i = 0; i < s->nx; ++i)
                 for (int cc = 0; cc < 3; ++cc) {
                     const double a = site_loss(s, 1, cc, i, j, k);
-                    const double da = (1.0 - a) / (1.0 + a), db = 1.0 / (1.0 + a);
+                    const double da = layer_ca(s, a), db = layer_cb(s, a);
                     y[3 + cc][at(s, i, j, k)] = da * v[3 + cc][at(s, i, j, k)] - db * S * curl_plus(s, (double* const*)v, cc, i, j, k);
                 }
     for (int k = 0; k <= s->nz; ++k)
@@ -805,7 +812,7 @@ static void tangent_step(const orc_sim* s, state_t X0, state_t X1, double* const
                     const size_t x = at(s, i, j, k), cell = cell_of(s, i, j, k);
                     const double ie = s->inv_eps[cell];
                     const double a = site_loss(s, 0, cc, i, j, k);
-                    const double ca = (1.0 - a) / (1.0 + a), cb = 1.0 / (1.0 + a);
+                    const double ca = layer_ca(s, a), cb = layer_cb(s, a);
                     double ddP = 0.0;
                     if (s->gain[cell]) {
                         const double E = X0[cc][x], dN = X0[12 + cc][x] - X0[15 + cc][x];
@@ -864,7 +871,7 @@ static void adjoint_step(const orc_sim* s, state_t X0, state_t X1, int64_t step_
                         etot[cc][x] += Wh * c[ORC_C_BETA] * 0.5 * dPf;
                     }
                     const double a = site_loss(s, 0, cc, i, j, k);
-                    u[cc][x] = (1.0 / (1.0 + a)) * s->inv_eps[cell] * etot[cc][x];
+                    u[cc][x] = layer_cb(s, a) * s->inv_eps[cell] * etot[cc][x];
                 }
     /* H: the adjoint of H' collects S curl+ u (the transpose of curl- is curl+) */
     for (int k = 0; k <= s->nz; ++k)
@@ -879,8 +886,8 @@ static void adjoint_step(const orc_sim* s, state_t X0, state_t X1, int64_t step_
                     }
                     htot[cc][x] = w[3 + cc][x] + S * curl_plus(s, u, cc, i, j, k);
                     const double a = site_loss(s, 1, cc, i, j, k);
-                    z[3 + cc][x] = ((1.0 - a) / (1.0 + a)) * htot[cc][x];
-                    vh[cc][x] = (1.0 / (1.0 + a)) * htot[cc][x];
+                    z[3 + cc][x] = layer_ca(s, a) * htot[cc][x];
+                    vh[cc][x] = layer_cb(s, a) * htot[cc][x];
                 }
     /* E: identity or ca etot, minus S curl- (db htot) (the transpose of curl+),
      * and the Bloch terms at interior gain sites */
@@ -894,14 +901,14 @@ static void adjoint_step(const orc_sim* s, state_t X0, state_t X1, int64_t step_
                     const int in = e_interior(s, cc, i, j, k);
                     if (in) {
                         const double a = site_loss(s, 0, cc, i, j, k);
-                        e_adj = ((1.0 - a) / (1.0 + a)) * etot[cc][x];
+                        e_adj = layer_ca(s, a) * etot[cc][x];
                     }
                     e_adj -= S * curl_minus(s, vh, cc, i, j, k);
                     if (in) {
                         const size_t cell = cell_of(s, i, j, k);
                         const double ie = s->inv_eps[cell];
                         const double a = site_loss(s, 0, cc, i, j, k);
-                        const double cb = 1.0 / (1.0 + a);
+                        const double cb = layer_cb(s, a);
                         double dPf = 0.0;
                         if (s->gain[cell]) {
                             dPf = X1[6 + cc][x] - X0[6 + cc][x];

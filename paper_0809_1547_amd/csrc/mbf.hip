@@ -87,8 +87,10 @@ struct mbf_handle {
     Coef co{};
     double Na_si = 0.0;
     mbf_tuning tun{MBF_VARIANT_TWO_PASS, 4, 0, 2, 0};
-    void* prof = nullptr;     // lossy-layer profiles: [axis][integer, half][n_axis + 1]
-    int64_t prof_stride = 0;
+    uint8_t* lev = nullptr;   // lossy-layer profile levels: [axis][integer, half][n_axis + 1]
+    int64_t lev_stride = 0;
+    void* lc = nullptr;       // (ca, cb) per level triple, in the field type
+    uint32_t lc_dim[3] = {1, 1, 1};
     bool has_layer = false;
     int64_t gain_sites = 0;   // interior E-sites of gain cells
     bool have_material = false, have_pump = false;
@@ -132,6 +134,79 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 template <typename T>
 double rnd(double v) {
     return (double)(T)v;
+}
+
+// Coefficients of the graded lossy layer.  The loss of a site is the sum of
+// three profile values, one per axis at the site's integer or half-integer
+// position x: a_max ((L - x)/L)^p near a low wall and a_max ((x - (n - L))/L)^p
+// near a high wall, each rounded once to the field type.  The semi-implicit
+// updates need ca = (1 - a)/(1 + a) and cb = 1/(1 + a); both are formed here
+// in FP64 from the rounded values, summed x, y, z in that order, and rounded
+// once to the field type, for every triple of distinct per-axis values (their
+// levels; level 0 is the value 0).  A site looks its pair up by its three
+// levels, so the kernels never divide.
+int build_layer_table(mbf_handle* h, const mbf_config& c, std::string& err) {
+    const int nmax = std::max({c.nx, c.ny, c.nz});
+    h->lev_stride = nmax + 1;
+    std::vector<uint8_t> lev((size_t)6 * h->lev_stride, 0);
+    std::vector<double> vals[3];
+    for (int a = 0; a < 3; ++a) {
+        vals[a].assign(1, 0.0);
+        if (c.boundary[a] != MBF_ABSORB || c.absorb_rate == 0.0) continue;
+        const int na = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
+        const double L = (double)c.absorb_cells;
+        std::vector<double> pv((size_t)2 * (na + 1));
+        for (int hf = 0; hf < 2; ++hf)
+            for (int q = 0; q <= na; ++q) {
+                const double x = (double)q + (hf ? 0.5 : 0.0);
+                double val = 0.0;
+                if (x < L) val += std::pow((L - x) / L, (double)c.absorb_order);
+                if (x > na - L) val += std::pow((x - (na - L)) / L, (double)c.absorb_order);
+                val = h->esz == 8 ? c.absorb_rate * val : (double)(float)(c.absorb_rate * val);
+                pv[(size_t)hf * (na + 1) + q] = val;
+                if (val != 0.0) vals[a].push_back(val);
+            }
+        std::sort(vals[a].begin() + 1, vals[a].end());
+        vals[a].erase(std::unique(vals[a].begin() + 1, vals[a].end()), vals[a].end());
+        if (vals[a].size() > 255) {
+            err = "absorbing layer too deep (more than 254 distinct profile values on one axis)";
+            return MBF_EINVAL;
+        }
+        for (int hf = 0; hf < 2; ++hf)
+            for (int q = 0; q <= na; ++q) {
+                const double val = pv[(size_t)hf * (na + 1) + q];
+                const auto it = std::lower_bound(vals[a].begin() + 1, vals[a].end(), val);
+                lev[(size_t)(2 * a + hf) * h->lev_stride + q] = val == 0.0 ? 0 : (uint8_t)(it - vals[a].begin());
+            }
+        h->has_layer = h->has_layer || vals[a].size() > 1;
+    }
+    for (int a = 0; a < 3; ++a) h->lc_dim[a] = (uint32_t)vals[a].size();
+    const size_t ntab = (size_t)h->lc_dim[0] * h->lc_dim[1] * h->lc_dim[2];
+    std::vector<uint8_t> tab(2 * ntab * h->esz);
+    for (uint32_t lx = 0; lx < h->lc_dim[0]; ++lx)
+        for (uint32_t ly = 0; ly < h->lc_dim[1]; ++ly)
+            for (uint32_t lz = 0; lz < h->lc_dim[2]; ++lz) {
+                const size_t t = ((size_t)lx * h->lc_dim[1] + ly) * h->lc_dim[2] + lz;
+                const double a = (vals[0][lx] + vals[1][ly]) + vals[2][lz];
+                const double ca = (1.0 - a) / (1.0 + a), cb = 1.0 / (1.0 + a);
+                if (h->esz == 8) {
+                    reinterpret_cast<double*>(tab.data())[2 * t] = ca;
+                    reinterpret_cast<double*>(tab.data())[2 * t + 1] = cb;
+                } else {
+                    reinterpret_cast<float*>(tab.data())[2 * t] = (float)ca;
+                    reinterpret_cast<float*>(tab.data())[2 * t + 1] = (float)cb;
+                }
+            }
+    if (hipMalloc(&h->lev, lev.size()) != hipSuccess || hipMalloc(&h->lc, tab.size()) != hipSuccess) {
+        err = "layer table allocation failed";
+        return MBF_ENOMEM;
+    }
+    if (hipMemcpy(h->lev, lev.data(), lev.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->lc, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "layer table upload failed";
+        return MBF_EHIP;
+    }
+    return MBF_OK;
 }
 
 // Coefficients of the scaled update (rounded once to the field type T).
@@ -232,10 +307,10 @@ mbf::SimView<T> view(mbf_handle* h) {
         if (h->cfg.boundary[q] == MBF_MUR1) v.mur_axes |= 1 << q;
     v.has_layer = h->has_layer ? 1 : 0;
     for (int a = 0; a < 3; ++a)
-        v.lay_L[a] = (h->has_layer && h->cfg.boundary[a] == MBF_ABSORB) ? h->cfg.absorb_cells : -1;
-    for (int a = 0; a < 3; ++a)
-        for (int hf = 0; hf < 2; ++hf)
-            v.prof[a][hf] = reinterpret_cast<const T*>(h->prof) + (2 * a + hf) * h->prof_stride;
+        for (int hf = 0; hf < 2; ++hf) v.lev[a][hf] = h->lev + (2 * a + hf) * h->lev_stride;
+    v.lc = reinterpret_cast<const T*>(h->lc);
+    v.lc_sy = h->lc_dim[1] * h->lc_dim[2];
+    v.lc_sz = h->lc_dim[2];
     v.ctl = h->ctl;
     v.e_part = h->e_part;
     v.l_part = h->l_part;
@@ -821,33 +896,10 @@ int mbf_create(const mbf_config* cfg, void* stream, mbf_handle** out) {
                 ++h->mur_tasks;
             }
     }
-    // lossy-layer profiles at integer and half-integer positions of every axis
-    const int nmax = std::max({c.nx, c.ny, c.nz});
-    h->prof_stride = nmax + 1;
-    std::vector<double> prof((size_t)6 * h->prof_stride, 0.0);
-    for (int a = 0; a < 3; ++a) {
-        if (c.boundary[a] != MBF_ABSORB || c.absorb_rate == 0.0) continue;
-        const int na = a == 0 ? c.nx : (a == 1 ? c.ny : c.nz);
-        const double L = (double)c.absorb_cells;
-        for (int hf = 0; hf < 2; ++hf)
-            for (int q = 0; q <= na; ++q) {
-                const double x = (double)q + (hf ? 0.5 : 0.0);
-                double val = 0.0;
-                if (x < L) val += std::pow((L - x) / L, (double)c.absorb_order);
-                if (x > na - L) val += std::pow((x - (na - L)) / L, (double)c.absorb_order);
-                prof[(size_t)(2 * a + hf) * h->prof_stride + q] = c.absorb_rate * val;
-                h->has_layer = h->has_layer || val > 0.0;
-            }
-    }
-    if (hipMalloc(&h->prof, prof.size() * h->esz) != hipSuccess) return bail(MBF_ENOMEM, "profile allocation failed");
     {
-        std::vector<uint8_t> buf(prof.size() * h->esz);
-        for (size_t q = 0; q < prof.size(); ++q) {
-            if (h->esz == 8) reinterpret_cast<double*>(buf.data())[q] = prof[q];
-            else reinterpret_cast<float*>(buf.data())[q] = (float)prof[q];
-        }
-        if (hipMemcpy(h->prof, buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess)
-            return bail(MBF_EHIP, "profile upload failed");
+        std::string m;
+        const int rc = build_layer_table(h, c, m);
+        if (rc) return bail(rc, m);
     }
     h->co = c.precision == MBF_FP64 ? make_coef<double>(c, 0.0) : make_coef<float>(c, 0.0);
     *out = h;
@@ -861,7 +913,7 @@ void mbf_destroy(mbf_handle* h) {
     free_probes(h);
     hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
     hipFree(h->mat); hipFree(h->lut);
-    hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->prof);
+    hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->lev); hipFree(h->lc);
     hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items); hipFree(h->map);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
@@ -2501,8 +2553,10 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     v.nx = c.nx; v.ny = c.ny; v.nz = c.nz;
     v.sx = h->sx; v.sxy = h->sxy;
     for (int a = 0; a < 3; ++a)
-        for (int hf = 0; hf < 2; ++hf)
-            v.prof[a][hf] = reinterpret_cast<const T*>(h->prof) + (2 * a + hf) * h->prof_stride;
+        for (int hf = 0; hf < 2; ++hf) v.lev[a][hf] = h->lev + (2 * a + hf) * h->lev_stride;
+    v.lc = reinterpret_cast<const T*>(h->lc);
+    v.lc_sy = h->lc_dim[1] * h->lc_dim[2];
+    v.lc_sz = h->lc_dim[2];
     v.has_layer = h->has_layer ? 1 : 0;
     const Coef& k = h->co;
     v.S = (T)k.S; v.a = (T)k.a; v.b = (T)k.b; v.ck = (T)k.ck; v.beta = (T)k.beta;

@@ -50,8 +50,10 @@ struct AdjView {
     const T* lut_inv_eps;
     int nx, ny, nz;
     int64_t sx, sxy;
-    const T* prof[3][2];
-    int has_layer;
+    int has_layer;            // lossy-layer coefficient table, as in SimView
+    const uint8_t* lev[3][2];
+    const T* lc;
+    uint32_t lc_sy, lc_sz;
     // coefficients of the forward step
     T S, a, b, ck, beta, dt32, dt21, dt10, dtWp;
     T ck_esp;            // d c_F / d(N_a/N_ref) = ck E_sp (0 without noise)
@@ -78,15 +80,6 @@ __device__ __forceinline__ AdjSlot<T> adj_slot(const AdjView<T>& v, int q) {
     a.s0 = v.traj + (int64_t)q * v.slot;
     a.s1 = a.s0 + v.slot;
     return a;
-}
-
-template <typename T>
-__device__ __forceinline__ T adj_loss_e(const AdjView<T>& v, int c, int i, int j, int k) {
-    return (gld(v.prof[0][c == 0] + i) + gld(v.prof[1][c == 1] + j)) + gld(v.prof[2][c == 2] + k);
-}
-template <typename T>
-__device__ __forceinline__ T adj_loss_h(const AdjView<T>& v, int c, int i, int j, int k) {
-    return (gld(v.prof[0][c != 0] + i) + gld(v.prof[1][c != 1] + j)) + gld(v.prof[2][c != 2] + k);
 }
 
 // Interior E-site test (updated by Ampere's law).
@@ -124,11 +117,7 @@ __global__ void __launch_bounds__(64 * TY) k_adj_h(const AdjView<T>* __restrict_
         const T cc[3] = {cx, cy, cz};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T da = (T)1;
-            if (v.has_layer) {
-                const T a = adj_loss_h(v, c, i, j, k);
-                da = ((T)1 - a) * recip((T)1 + a);
-            }
+            const T da = lay_coef_h(v, c, i, j, k).ca;
             sto(v.hb[c], x, da * ldo(v.hb[c], x) + v.S * cc[c]);
         }
     }
@@ -181,9 +170,7 @@ __device__ __forceinline__ void adj_load_plane(AdjPlane<T>& p, const AdjView<T>&
 // db htot at H-site c of (i, j, k) from its loaded htot.
 template <typename T>
 __device__ __forceinline__ T adj_db(const AdjView<T>& v, int c, int i, int j, int k, T hb) {
-    T db = (T)1;
-    if (v.has_layer) db = recip((T)1 + adj_loss_h(v, c, i, j, k));
-    return db * hb;
+    return lay_coef_h(v, c, i, j, k).cb * hb;
 }
 
 // E part with the Bloch terms, the parameter terms and the loss term.  Each
@@ -245,12 +232,8 @@ __global__ void __launch_bounds__(64 * TY) k_adj_e(const AdjView<T>* __restrict_
                         curl = (vhx - vhx_z) - (vhz - adj_db(v, 2, i - 1, j, k, P.hz_x));
                     else
                         curl = (vhy - adj_db(v, 1, i - 1, j, k, P.hy_x)) - (vhx - adj_db(v, 0, i, j - 1, k, P.hx_y));
-                    T ca = (T)1, cb = (T)1;
-                    if (v.has_layer) {
-                        const T a = adj_loss_e(v, c, i, j, k);
-                        cb = recip((T)1 + a);
-                        ca = ((T)1 - a) * cb;
-                    }
+                    const LayC<T> lay = lay_coef_e(v, c, i, j, k);
+                    const T ca = lay.ca, cb = lay.cb;
                     const T et = P.u[c] / (cb * ie);
                     const T E = P.E[c], En = P.En[c];
                     T lam = ca * et - v.S * curl;
@@ -313,8 +296,7 @@ __global__ void __launch_bounds__(64) k_adj_seed(AdjView<T> v, int q) {
         T u = (T)0;
         if (inb && e_in(v, c, i, j, k)) {
             const T ie = gld(v.lut_inv_eps + ldo(v.mat, x));
-            T cb = (T)1;
-            if (v.has_layer) cb = recip((T)1 + adj_loss_e(v, c, i, j, k));
+            const T cb = lay_coef_e(v, c, i, j, k).cb;
             u = cb * ie * ((T)2 * ldo(a.s1 + c * v.tap_e, x));
         }
         sto(v.u[c], x, u);

@@ -76,11 +76,15 @@ struct SimView {
     int n_mur;
     uint64_t mur_code;
     int mur_axes;
-    // graded lossy layer: loss per site = prof[x][hx][i] + prof[y][hy][j] + prof[z][hz][k]
-    // (index 1 = half-integer position along that axis)
+    // graded lossy layer: the coefficients (ca, cb) of a site's semi-implicit
+    // update are the pair at entry lev[0][hx][i] * lc_sy + lev[1][hy][j] *
+    // lc_sz + lev[2][hz][k] of lc, where lev[a][h][q] numbers the distinct
+    // profile values of axis a (h = 1: half-integer position; level 0 is the
+    // value 0, so entry 0 is (1, 1) and stands for a site outside the layer)
     int has_layer;
-    int lay_L[3];             // layer depth on a lossy axis, -1 on other axes
-    const T* prof[3][2];
+    const uint8_t* lev[3][2];
+    const T* lc;
+    uint32_t lc_sy, lc_sz;
     // monitors
     Ctl* ctl;
     double* e_part;           // per workgroup energy partial sums
@@ -246,21 +250,44 @@ __device__ __forceinline__ Fields<T> bind_fields(const SimView<T>& v, int par) {
     return f;
 }
 
-// Loss of an E-site of component c (half position along c) and of an H-site
-// of component c (half positions along the two other axes).
+// Layer coefficients of a site: ca = (1 - a)/(1 + a) and cb = 1/(1 + a) for
+// its summed loss a, formed on the host in FP64 and rounded once to the field
+// type.  (1, 1) outside the layer, where the semi-implicit updates below
+// reduce to the plain Yee ones bit for bit (1 * x == x).
 template <typename T>
-__device__ __forceinline__ T loss_e(const SimView<T>& v, int c, int i, int j, int k) {
-    return (gld(v.prof[0][c == 0] + i) + gld(v.prof[1][c == 1] + j)) + gld(v.prof[2][c == 2] + k);
-}
-template <typename T>
-__device__ __forceinline__ T loss_h(const SimView<T>& v, int c, int i, int j, int k) {
-    return (gld(v.prof[0][c != 0] + i) + gld(v.prof[1][c != 1] + j)) + gld(v.prof[2][c != 2] + k);
-}
+struct LayC {
+    T ca, cb;
+};
 
-// Faraday update with the semi-implicit loss of the layer
-// (H' - H = -S curl - a (H' + H)); a = 0 is the plain Yee update.
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+// Table entry of an E-site of component c (half position along c) and of an
+// H-site of component c (half positions along the two other axes).
+template <typename V>
+__device__ __forceinline__ uint32_t lay_e(const V& v, int c, int i, int j, int k) {
+    return (uint32_t)gld(v.lev[0][c == 0] + i) * v.lc_sy + (uint32_t)gld(v.lev[1][c == 1] + j) * v.lc_sz +
+           (uint32_t)gld(v.lev[2][c == 2] + k);
+}
+template <typename V>
+__device__ __forceinline__ uint32_t lay_h(const V& v, int c, int i, int j, int k) {
+    return (uint32_t)gld(v.lev[0][c != 0] + i) * v.lc_sy + (uint32_t)gld(v.lev[1][c != 1] + j) * v.lc_sz +
+           (uint32_t)gld(v.lev[2][c != 2] + k);
+}
+template <typename T>
+__device__ __forceinline__ LayC<T> lay_coef(const T* lc, uint32_t t) {
+    LayC<T> r{(T)1, (T)1};
+    if (t != 0u) {
+        r.ca = ldo(lc, 2u * t);
+        r.cb = ldo(lc, 2u * t + 1u);
+    }
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ auto lay_coef_e(const V& v, int c, int i, int j, int k) {
+    return lay_coef(v.lc, v.has_layer ? lay_e(v, c, i, j, k) : 0u);
+}
+template <typename V>
+__device__ __forceinline__ auto lay_coef_h(const V& v, int c, int i, int j, int k) {
+    return lay_coef(v.lc, v.has_layer ? lay_h(v, c, i, j, k) : 0u);
+}
 
 // Compact index of the calling lane's cell in the Bloch-state arrays.  Must
 // be called by the whole wave that covers x segment bx of row (j, k) (lanes
@@ -276,17 +303,11 @@ __device__ __forceinline__ uint32_t gain_index(const V& v, int bx, int j, int k,
     return base + below;
 }
 
-// True when every index in [lo, hi] along an axis lies outside its lossy layer.
-__device__ __forceinline__ bool clear_of_layer(int L, int n, int lo, int hi) {
-    return L < 0 || (lo >= L && hi <= n - L - 1);
-}
-
+// Faraday update with the semi-implicit loss of the layer
+// (H' - H = -S curl - a (H' + H)); ca = cb = 1 is the plain Yee update.
 template <typename T>
-__device__ __forceinline__ T h_update(T h, T S, T curl, T a) {
-    if (a == (T)0) return h - S * curl;
-    const T cb = recip((T)1 + a);
-    const T ca = ((T)1 - a) * cb;
-    return ca * h - cb * (S * curl);
+__device__ __forceinline__ T h_update(T h, T S, T curl, LayC<T> l) {
+    return l.ca * h - l.cb * (S * curl);
 }
 
 template <typename V>
@@ -423,12 +444,9 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
             const T cy = (exk - ex) - (P.ezx - ez);
             const T cz = (P.eyx - ey) - (P.exy - ex);
             const T hx = P.hx, hy = P.hy, hz = P.hz;
-            T ax = (T)0, ay = (T)0, az = (T)0;
-            if (v.has_layer) {
-                ax = loss_h(v, 0, i, j, k);
-                ay = loss_h(v, 1, i, j, k);
-                az = loss_h(v, 2, i, j, k);
-            }
+            const LayC<T> ax = lay_coef_h(v, 0, i, j, k);
+            const LayC<T> ay = lay_coef_h(v, 1, i, j, k);
+            const LayC<T> az = lay_coef_h(v, 2, i, j, k);
             const T nhx = h_update(hx, v.S, cx, ax);
             const T nhy = h_update(hy, v.S, cy, ay);
             const T nhz = h_update(hz, v.S, cz, az);
@@ -499,22 +517,15 @@ __device__ __forceinline__ BlochIn<T> bloch_load(const Fields<T>& f, int c, uint
 template <typename T>
 __device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f, int c, uint32_t gi,
                                         T e, T curl, T ie, bool upd, bool gain,
-                                        const BlochIn<T>& b, T xi, T src, T loss, T* tslot) {
+                                        const BlochIn<T>& b, T xi, T src, LayC<T> lay, T* tslot) {
     T dP = (T)0;
     T Pn = (T)0;
     if (gain) {
         Pn = v.a * b.P + v.b * b.Pp + v.ck * (b.n1 - b.n2) * e + v.cF * xi;
         dP = Pn - b.P;
     }
-    T en;
-    if (loss == (T)0) {
-        en = e + ie * (v.S * curl - dP);
-    } else {
-        // semi-implicit loss of the layer: (E' - E) = (1/eps)(S curl - dP) - a (E' + E)
-        const T cb = recip((T)1 + loss);
-        const T ca = ((T)1 - loss) * cb;
-        en = ca * e + cb * (ie * (v.S * curl - dP));
-    }
+    // semi-implicit loss of the layer: (E' - E) = (1/eps)(S curl - dP) - a (E' + E)
+    T en = lay.ca * e + lay.cb * (ie * (v.S * curl - dP));
     en += src;
     en = upd ? en : e;
     if (gain) {
@@ -624,14 +635,19 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
         uint8_t m_n = (kz0 + 1 < kz1) ? ldo(v.mat, x + sxy) : (uint8_t)0;
         T hxm = kz0 >= 1 ? ldo(f.hn[0], x - sxy) : (T)0;
         T hym = kz0 >= 1 ? ldo(f.hn[1], x - sxy) : (T)0;
-        // the layer's x and y profile values of this column and row stay
-        // fixed along the march in z (loss_e, summed in the same order)
-        T px0 = (T)0, px1 = (T)0, py0 = (T)0, py1 = (T)0;
+        // the x and y parts of the three sites' layer-table entries stay
+        // fixed along the march in z (lay_e: x at the half position for Ex,
+        // y at the half position for Ey; the row j is wave-uniform)
+        uint32_t txy0 = 0u, txy1 = 0u, txy2 = 0u;
         if (v.has_layer) {
-            px0 = gld(v.prof[0][0] + i);
-            px1 = gld(v.prof[0][1] + i);
-            py0 = gld(v.prof[1][0] + j);
-            py1 = gld(v.prof[1][1] + j);
+            const uint32_t tx0 = (uint32_t)gld(v.lev[0][0] + i) * v.lc_sy;
+            const uint32_t tx1 = (uint32_t)gld(v.lev[0][1] + i) * v.lc_sy;
+            const int jw = __builtin_amdgcn_readfirstlane(j);
+            const uint32_t ty0 = (uint32_t)gld(v.lev[1][0] + jw) * v.lc_sz;
+            const uint32_t ty1 = (uint32_t)gld(v.lev[1][1] + jw) * v.lc_sz;
+            txy0 = tx1 + ty0;
+            txy1 = tx0 + ty1;
+            txy2 = tx0 + ty0;
         }
         EPlane<T> P, Q;
         if constexpr (SPLIT) load_dense(P, f, x, sx, i, j);
@@ -664,31 +680,35 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             }
             T s0, s1, s2;
             source3(v, i, j, k, n, s0, s1, s2);
-            T la0 = (T)0, la1 = (T)0, la2 = (T)0;
+            // table entries of the three sites (0 without a layer)
+            uint32_t tl0 = 0u, tl1 = 0u, tl2 = 0u;
             if (v.has_layer) {
-                const T pz0 = gld(v.prof[2][0] + k), pz1 = gld(v.prof[2][1] + k);
-                la0 = (px1 + py0) + pz0;
-                la1 = (px0 + py1) + pz0;
-                la2 = (px0 + py0) + pz1;
+                const uint32_t tz0 = gld(v.lev[2][0] + k), tz1 = gld(v.lev[2][1] + k);
+                tl0 = txy0 + tz0;
+                tl1 = txy1 + tz0;
+                tl2 = txy2 + tz1;
             }
             T acc = (T)0;
             {
                 const T curl = inx ? (P.hz - P.hzy) - (P.hy - hym) : (T)0;
-                const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0, la0, tslot);
+                const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0,
+                                        lay_coef(v.lc, tl0), tslot);
                 sto(f.en[0], x, en);
                 if (tslot) sto(tslot, x, en);
                 if (inx) acc += en * en;
             }
             {
                 const T curl = iny ? (P.hx - hxm) - (P.hz - P.hzx) : (T)0;
-                const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1, la1, tslot);
+                const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1,
+                                        lay_coef(v.lc, tl1), tslot);
                 sto(f.en[1], x, en);
                 if (tslot) sto(tslot + v.tap_e, x, en);
                 if (iny) acc += en * en;
             }
             {
                 const T curl = inz ? (P.hy - P.hyx) - (P.hx - P.hxy) : (T)0;
-                const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2, la2, tslot);
+                const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2,
+                                        lay_coef(v.lc, tl2), tslot);
                 sto(f.en[2], x, en);
                 if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                 if (inz) acc += en * en;
@@ -764,7 +784,6 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
         const T* __restrict__ Hx0 = f.h[0];
         const T* __restrict__ Hy0 = f.h[1];
         const T* __restrict__ Hz0 = f.h[2];
-        const bool lay = v.has_layer != 0;
         const bool up = j >= 1;                       // row j-1 exists (wave-uniform)
         const bool edge = threadIdx.x == 0 && i >= 1; // lane 0 of a tile past x = 0
         uint32_t x = (uint32_t)ic + sx * (uint32_t)j + sxy * (uint32_t)kz0;
@@ -779,8 +798,8 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             const T ezp = ldo(Ez, xp), eyp = ldo(Ey, xp), exp_ = ldo(Ex, xp);
             const T cx = (ldo(Ez, xp + sx) - ezp) - (ey - eyp);
             const T cy = (ex - exp_) - (ldo(Ez, xp + 1u) - ezp);
-            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay ? loss_h(v, 0, i, j, kz0 - 1) : (T)0);
-            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay ? loss_h(v, 1, i, j, kz0 - 1) : (T)0);
+            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay_coef_h(v, 0, i, j, kz0 - 1));
+            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay_coef_h(v, 1, i, j, kz0 - 1));
         }
         for (int k = kz0; k < kz1; ++k, x += sxy) {
             const uint8_t m = m_next;
@@ -798,12 +817,9 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             const T cx = (ldo(Ez, x + sx) - ez) - (eyk - ey);
             const T cy = (exk - ex) - (ldo(Ez, x + 1u) - ez);
             const T cz = (ldo(Ey, x + 1u) - ey) - (ldo(Ex, x + sx) - ex);
-            T ax = (T)0, ay = (T)0, az = (T)0;
-            if (lay) {
-                ax = loss_h(v, 0, i, j, k);
-                ay = loss_h(v, 1, i, j, k);
-                az = loss_h(v, 2, i, j, k);
-            }
+            const LayC<T> ax = lay_coef_h(v, 0, i, j, k);
+            const LayC<T> ay = lay_coef_h(v, 1, i, j, k);
+            const LayC<T> az = lay_coef_h(v, 2, i, j, k);
             const T nhx = h_update(hx, v.S, cx, ax);
             const T nhy = h_update(hy, v.S, cy, ay);
             const T nhz = h_update(hz, v.S, cz, az);
@@ -830,8 +846,8 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 eymk = ldo(Ey, xm + sxy);
                 const T cxm = (ez - ezm) - (eymk - eym);
                 const T czm = (ldo(Ey, xm + 1u) - eym) - (ex - exm);
-                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay ? loss_h(v, 0, i, j - 1, k) : (T)0);
-                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay ? loss_h(v, 2, i, j - 1, k) : (T)0);
+                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay_coef_h(v, 0, i, j - 1, k));
+                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay_coef_h(v, 2, i, j - 1, k));
             }
             // ---- Hy, Hz at x-1 of the own row
             T nhy_l = __shfl_up(nhy, 1, 64);
@@ -841,8 +857,8 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 const T exl = ldo(Ex, xl), eyl = ldo(Ey, xl), ezl = ldo(Ez, xl);
                 const T cyl = (ldo(Ex, xl + sxy) - exl) - (ez - ezl);
                 const T czl = (ey - eyl) - (ldo(Ex, xl + sx) - exl);
-                nhy_l = h_update(ldo(Hy0, xl), v.S, cyl, lay ? loss_h(v, 1, i - 1, j, k) : (T)0);
-                nhz_l = h_update(ldo(Hz0, xl), v.S, czl, lay ? loss_h(v, 2, i - 1, j, k) : (T)0);
+                nhy_l = h_update(ldo(Hy0, xl), v.S, cyl, lay_coef_h(v, 1, i - 1, j, k));
+                nhz_l = h_update(ldo(Hz0, xl), v.S, czl, lay_coef_h(v, 2, i - 1, j, k));
             }
             // ---- a2-a5 on the own row
             if (act) {
@@ -858,7 +874,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 {
                     const T curl = inx ? (nhz - nhz_m) - (nhy - hyp) : (T)0;
                     const T en = bloch_site(v, f, 0, gi, ex, curl, ie, inx, g && inx, b0, xi[0], s0,
-                                            lay ? loss_e(v, 0, i, j, k) : (T)0, tslot);
+                                            lay_coef_e(v, 0, i, j, k), tslot);
                     sto(f.en[0], x, en);
                     if (tslot) sto(tslot, x, en);
                     if (inx) acc += en * en;
@@ -866,7 +882,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 {
                     const T curl = iny ? (nhx - hxp) - (nhz - nhz_l) : (T)0;
                     const T en = bloch_site(v, f, 1, gi, ey, curl, ie, iny, g && iny, b1, xi[1], s1,
-                                            lay ? loss_e(v, 1, i, j, k) : (T)0, tslot);
+                                            lay_coef_e(v, 1, i, j, k), tslot);
                     sto(f.en[1], x, en);
                     if (tslot) sto(tslot + v.tap_e, x, en);
                     if (iny) acc += en * en;
@@ -874,7 +890,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 {
                     const T curl = inz ? (nhy - nhy_l) - (nhx - nhx_m) : (T)0;
                     const T en = bloch_site(v, f, 2, gi, ez, curl, ie, inz, g && inz, b2, xi[2], s2,
-                                            lay ? loss_e(v, 2, i, j, k) : (T)0, tslot);
+                                            lay_coef_e(v, 2, i, j, k), tslot);
                     sto(f.en[2], x, en);
                     if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                     if (inz) acc += en * en;
