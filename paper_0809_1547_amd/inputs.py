@@ -67,9 +67,13 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
 
     Centres are uniform over the whole box and spheres may be cut by the walls.
     Diameters are Gaussian (mean_d, sd_d) truncated to +-3 sd by redrawing, or
-    all equal to 2*radius when ``radius`` is given.  Insertion stops once
-    ``count`` spheres are placed, or once the summed full-sphere volume reaches
-    ``fill`` times the box volume.
+    all equal to 2*radius when ``radius`` is given.  Each sphere's diameter is
+    drawn once, before its first placement attempt, and kept until a centre
+    for it is found: redrawing the diameter on every rejected attempt would
+    favour small spheres (large ones are rejected more often) and bias the
+    accepted diameters low.  Insertion stops once ``count`` spheres are
+    placed, or once the summed full-sphere volume reaches ``fill`` times the
+    box volume.
 
     Candidate centres are drawn uniformly from the unit voxels not yet known to
     be fully excluded for the smallest possible radius, then tested exactly; the
@@ -99,6 +103,7 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
     half_diag = 0.5 * math.sqrt(3.0)
     vol = 0.0
     attempts = 0
+    r = None                                   # diameter/2 of the sphere being placed
     free = None
     cursor = 0
     batch = 4096
@@ -127,7 +132,8 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
         v = int(free[cursor])
         cursor += 1
         attempts += 1
-        r = draw_radius()
+        if r is None:
+            r = draw_radius()
         if excluded.flat[v]:
             continue
         vk, rem = divmod(v, nx * ny)
@@ -154,9 +160,10 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
         centres.append(c)
         radii.append(r)
         vol += 4.0 / 3.0 * math.pi * r ** 3
+        r_placed, r = r, None
         # voxels whose every point lies closer than r + rmin to this centre can
         # never hold another centre
-        reach = r + rmin - half_diag
+        reach = r_placed + rmin - half_diag
         if reach > 0:
             lo = [max(0, int(math.floor(c[a] - reach - 1))) for a in range(3)]
             hi = [min(n[a], int(math.ceil(c[a] + reach + 1))) for a in range(3)]

@@ -21,8 +21,27 @@ def test_rsa_fill_no_overlap_and_diameters(n, seed):
     assert _min_gap(p) >= 0.0
     d = 2 * p.radii
     assert np.all(np.abs(d - 15.0) <= 3 * 1.5 + 1e-12)
-    assert abs(d.mean() - 15.0) < 1.0
+    assert abs(d.mean() - 15.0) < 5 * SD_TRUNC / math.sqrt(p.count)
     assert np.all((p.centres >= 0) & (p.centres < n))
+
+
+# standard deviation of N(15, 1.5) truncated to +-3 sd
+SD_TRUNC = 1.5 * math.sqrt(1 - 6 * math.exp(-4.5) / math.sqrt(2 * math.pi) / math.erf(3 / math.sqrt(2)))
+
+
+def test_rsa_diameters_follow_the_drawn_distribution():
+    # each sphere keeps the diameter drawn for it until it is placed, so the
+    # accepted diameters are the truncated Gaussian itself: at 128^3 (~460
+    # spheres) the mean lies within 3 standard errors of 15 cells and the
+    # standard deviation within 3 of its own; redrawing the diameter on every
+    # rejected attempt gave a mean of 14.33 cells here (bias towards small
+    # spheres, about 10 standard errors)
+    p = I.rsa_pack(128, seed=0, fill=0.4)
+    d = 2 * p.radii
+    k = p.count
+    assert 430 <= k <= 490
+    assert abs(d.mean() - 15.0) < 3 * SD_TRUNC / math.sqrt(k)
+    assert abs(d.std(ddof=1) - SD_TRUNC) < 3 * SD_TRUNC / math.sqrt(2 * (k - 1))
 
 
 def test_rsa_is_deterministic_per_seed():
