@@ -471,16 +471,43 @@ def test_lasing_spectra_match_oracle():
     assert gs["std_omega"] == pytest.approx(os_["std_omega"], rel=0.02)
 
 
-def test_c2_size_parity_linear_interval():
-    # the 128^3 workload (RSA fill 0.4, absorbing walls, prepumped, noise)
-    # over the first 1000 steps of its linear interval
+# The 128^3 workload (RSA fill 0.4, absorbing walls, prepumped N_a = 2e24,
+# noise at the default amplitude) over its whole linear interval: the steps
+# before the stimulated depletion max_site |dN - dN(E = 0)| / N_a (dN = N1 -
+# N2; the prepumped start is the E = 0 state) reaches 1e-4, measured on the
+# oracle as the run goes.  Every 100 steps all 21 fields are compared.  The
+# run is cut into five tests of 1000 steps that share one pair, so that each
+# stays within a test's time limit; each asserts its own part.
+C2_SEG, C2_SAMPLE, C2_STEPS = 1000, 100, 5000
+
+
+@pytest.fixture(scope="module")
+def c2_run():
     n = 128
     eps, gain = I.voxelize(I.packing_for("c2", n, 0))
-    sim, ora = pair(n, bc=("absorb",) * 3, eps=eps, gain=gain, E_sp=1e-3)
-    errs = []
-    for _ in range(4):
-        sim.step(250)
-        ora.step(250)
+    sim, ora = pair(n, bc=("absorb",) * 3, eps=eps, gain=gain)
+    na = ora.coefficients()[O.C_NA]
+    dn0 = [ora.field(12 + c) - ora.field(15 + c) for c in range(3)]
+    state = {"sim": sim, "ora": ora, "na": na, "dn0": dn0, "log": []}
+    yield state
+    sim.close()
+    ora.close()
+
+
+@pytest.mark.parametrize("seg", range(C2_STEPS // C2_SEG))
+def test_c2_size_parity_linear_interval(c2_run, seg):
+    sim, ora = c2_run["sim"], c2_run["ora"]
+    assert ora.step_index == seg * C2_SEG, "segments run in order"
+    errs, deps = [], []
+    for _ in range(C2_SEG // C2_SAMPLE):
+        sim.step(C2_SAMPLE)
+        ora.step(C2_SAMPLE)
+        dep = max(float(np.max(np.abs(ora.field(12 + c) - ora.field(15 + c) - c2_run["dn0"][c])))
+                  for c in range(3)) / c2_run["na"]
+        deps.append(dep)
         errs.append(worst(sim, ora, range(21)))
-    print("C2 128^3 rel L2 per 250 steps:", ["%.2e" % e for e in errs])
+    c2_run["log"] += list(zip(errs, deps))
+    print("C2 128^3 steps %d-%d: max rel L2 over 21 fields %.2e (last %.2e), depletion %.2e" % (
+        seg * C2_SEG, (seg + 1) * C2_SEG, max(errs), errs[-1], max(deps)))
+    assert max(deps) < 1e-4                  # still inside the linear interval
     assert max(errs) <= TOL32
