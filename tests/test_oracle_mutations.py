@@ -44,8 +44,8 @@ MUTATIONS = [
     ("philox_weyl", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;"),
     ("philox_word_order", "uint32_t y1 = lo1;", "uint32_t y1 = lo0;"),
     ("rate_work_factor_only", "double W = c[ORC_C_BETA] * Ebar * dP;", "double W = 0.5 * c[ORC_C_BETA] * Ebar * dP;"),
-    ("layer_loss_sign", "s->Hn[c][x] = ((1.0 - a) / (1.0 + a)) * H3[c][x]", "s->Hn[c][x] = ((1.0 + a) / (1.0 + a)) * H3[c][x]"),
-    ("layer_e_scale", "(1.0 / (1.0 + a)) * (ie * (S * curl - dP));", "(ie * (S * curl - dP));"),
+    ("layer_loss_sign", "s->Hn[c][x] = layer_ca(s, a) * H3[c][x]", "s->Hn[c][x] = layer_ca(s, -a) * H3[c][x]"),
+    ("layer_e_scale", "layer_cb(s, a) * (ie * (S * curl - dP));", "(ie * (S * curl - dP));"),
     ("prepump_fixed_point", "N[2] = rnd(s, dwp * n0 / d21);", "N[2] = rnd(s, dwp * n0 / d32);"),
     ("adjoint_curl_transpose_sign", "htot[cc][x] = w[3 + cc][x] + S * curl_plus(s, u, cc, i, j, k);",
      "htot[cc][x] = w[3 + cc][x] - S * curl_plus(s, u, cc, i, j, k);"),
@@ -57,7 +57,7 @@ MUTATIONS = [
     ("adjoint_initial_populations", "r[0] = r0; r[3] = dwp * r0 / d32;", "r[0] = r0; r[3] = dwp * r0 / d21;"),
     ("adjoint_noise_amplitude", "*g_na += c[ORC_C_CK] * s->p.E_sp * xi[cc] * pn;",
      "*g_na += c[ORC_C_CK] * xi[cc] * pn;"),
-    ("adjoint_layer_scale", "vh[cc][x] = (1.0 / (1.0 + a)) * htot[cc][x];", "vh[cc][x] = htot[cc][x];"),
+    ("adjoint_layer_scale", "vh[cc][x] = layer_cb(s, a) * htot[cc][x];", "vh[cc][x] = htot[cc][x];"),
     ("tangent_inversion_term", "c[ORC_C_CK] * dN * v[cc][x];", "c[ORC_C_CK] * dN * v[cc][x] * 0.5;"),
 ]
 
