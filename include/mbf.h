@@ -290,6 +290,22 @@ int mbf_spectrum_stats(mbf_handle* h, double level, mbf_spec_stats* out);
 int mbf_spectral_stats(const double* spec, int n_probes, int n_freq, const double* omega, double level,
                        int mem_kind, void* stream, mbf_spec_stats* out);
 
+/* mbf_spectral_stats for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, but nothing is allocated or
+ * freed.  spec[2 * n_probes * n_freq], omega[n_freq] and *out are device
+ * memory (caller-owned; spec 16-byte, omega and out 8-byte aligned).  The
+ * work is queued on `stream` (NULL: the null stream) and the call returns
+ * without waiting; *out holds the result once the stream reaches it.  The
+ * intermediate power spectrum lives in a fixed per-device scratch array of
+ * 65536 FP64 values held by the library until the process ends:
+ * 1 <= n_freq <= 65536 (MBF_EINVAL otherwise), n_probes >= 1, 0 < level < 1.
+ * Every call on a device shares that array (each call overwrites the bins it
+ * uses before reading them): calls ordered on one stream are safe, calls that
+ * overlap on one device (other streams, other threads) race. */
+int mbf_spectral_stats_noalloc(const double* spec, int n_probes, int n_freq, const double* omega, double level,
+                               void* stream, mbf_spec_stats* out);
+
 /* Spectral peaks (Simulations section: the spectrum after a wide-band pulse
  * shows several peaks, the long-lived modes, Fig. 1).  Of the same S_k: the
  * bins with S_k > 0, S_k >= min_rel * max_k S_k and S_{k-1} < S_k >= S_{k+1}

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2671,3 +2672,63 @@ int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int me
 
 }  // extern "C"
 
+// ---------------------------------------- spectral statistics without allocation
+// mbf_spectral_stats_noalloc keeps the probe-summed power spectrum S_k, its
+// only intermediate, in this file-scope device array (one copy per device,
+// held until the process ends) instead of device memory allocated per call.
+// Host code never uses the array's name as an address: the address is taken
+// once per device with hipGetSymbolAddress and kept in scratch_dev.
+namespace {
+
+constexpr int kNoallocMaxBins = 1 << 16;    // 512 KiB of FP64 per device
+constexpr int kNoallocMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kNoallocMaxBins];
+
+std::mutex scratch_mu;
+double* scratch_dev[kNoallocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+int scratch_address(double** out) {
+    int dev = -1;
+    HIPCHK(nullptr, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(nullptr, MBF_ENODEV, "device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, MBF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_dev[dev];
+    return MBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbf_spectral_stats_noalloc(const double* spec, int n_probes, int n_freq, const double* omega, double level,
+                               void* stream, mbf_spec_stats* out) {
+    if (!spec || !omega || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n_probes < 1 || n_freq < 1) return fail(nullptr, MBF_EINVAL, "n_probes and n_freq must be >= 1");
+    if (n_freq > kNoallocMaxBins)
+        return fail(nullptr, MBF_EINVAL, "n_freq exceeds the 65536 bins of the allocation-free scratch");
+    if (!stat_level_ok(level)) return fail(nullptr, MBF_EINVAL, "level must lie in (0, 1)");
+    if (reinterpret_cast<uintptr_t>(spec) % 16 != 0 || reinterpret_cast<uintptr_t>(omega) % 8 != 0 ||
+        reinterpret_cast<uintptr_t>(out) % 8 != 0)
+        return fail(nullptr, MBF_EINVAL, "spec must be 16-byte and omega, out 8-byte aligned");
+    double* pw = nullptr;
+    const int rc = scratch_address(&pw);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(mbf::k_spec_power, dim3((unsigned)((n_freq + 63) / 64)), dim3(64), 0, st, spec, n_probes,
+                       n_freq, pw);
+    hipLaunchKernelGGL(mbf::k_spec_stats, dim3(1), dim3(mbf::kStatThreads), 0, st, pw, n_freq, omega, level, out);
+    HIPCHK(nullptr, hipGetLastError());
+    return MBF_OK;
+}
+
+}  // extern "C"

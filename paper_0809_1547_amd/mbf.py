@@ -138,6 +138,7 @@ def _load():
         "mbf_batch_autotune": (I, [P, I, C.POINTER(mbf_tuning)]),
         "mbf_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
         "mbf_spectral_stats": (I, [VP, I, I, VP, D, I, VP, C.POINTER(mbf_spec_stats)]),
+        "mbf_spectral_stats_noalloc": (I, [VP, I, I, VP, D, VP, VP]),
         "mbf_batch_spectrum_stats": (I, [P, D, C.POINTER(mbf_spec_stats)]),
         "mbf_spectrum_peaks": (I, [P, D, I, VP, C.POINTER(C.c_int)]),
         "mbf_spectral_peaks": (I, [VP, I, I, D, I, I, VP, VP, C.POINTER(C.c_int)]),
@@ -171,7 +172,7 @@ EXPORTED = [
     "mbf_batch_autotune", "mbf_adjoint_run", "mbf_spectrum_stats", "mbf_spectral_stats",
     "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
     "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor", "mbf_gp_solve",
-    "mbf_gp_eigenvalue", "mbf_gp_threshold", "mbf_pack_md",
+    "mbf_gp_eigenvalue", "mbf_gp_threshold", "mbf_pack_md", "mbf_spectral_stats_noalloc",
 ]
 
 
@@ -319,6 +320,29 @@ def mbf_spectral_stats(spec, omega, level: float = 0.5, stream: Optional[int] = 
     _check(lib.mbf_spectral_stats(ps, spec.shape[0], spec.shape[1], pw, float(level), ks,
                                   C.c_void_p(stream or 0), C.byref(o)))
     return _stats_dict(o)
+
+
+def mbf_spectral_stats_noalloc(spec, omega, out, level: float = 0.5, stream: Optional[int] = None) -> None:
+    """mbf_spectral_stats with nothing allocated: spec (n_probes, n_freq, 2)
+    float64, omega (n_freq,) float64 and out (a device buffer of at least
+    ctypes.sizeof(mbf_spec_stats) bytes) are device tensors; the work is
+    queued on `stream` and out holds the statistics once the stream reaches
+    it (``spec_stats_from_device`` reads them)."""
+    if len(spec.shape) != 3 or spec.shape[-1] != 2 or omega.shape[0] != spec.shape[1]:
+        raise ValueError("spec must be (n_probes, n_freq, 2) and omega (n_freq,)")
+    if out.numel() * out.element_size() < C.sizeof(mbf_spec_stats):
+        raise ValueError("out is smaller than mbf_spec_stats")
+    for a in (spec, omega, out):
+        if not getattr(a, "is_cuda", False) or not a.is_contiguous():
+            raise ValueError("spec, omega and out must be contiguous device tensors")
+    _check(lib.mbf_spectral_stats_noalloc(spec.data_ptr(), spec.shape[0], spec.shape[1], omega.data_ptr(),
+                                          float(level), C.c_void_p(stream or 0), C.c_void_p(out.data_ptr())))
+
+
+def spec_stats_from_device(out) -> dict:
+    """The statistics held in a device buffer written by mbf_spectral_stats_noalloc."""
+    raw = out.reshape(-1).view(__import__("torch").uint8)[:C.sizeof(mbf_spec_stats)].cpu().numpy().tobytes()
+    return _stats_dict(mbf_spec_stats.from_buffer_copy(raw))
 
 
 def mbf_spectrum_peaks(h: int, min_rel: float = 0.1, max_peaks: int = 16) -> list:
