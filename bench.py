@@ -1,8 +1,8 @@
 """Throughput benchmark of the Maxwell-Bloch FDTD step on one MI355X.
 
 Workload (default, --workload c5): the paper-scale realization -- 320^3 cells
-(6.4 um box, ~8800 RSA spheres of mean diameter 300 nm, index 2.9, fill 0.4,
-gain in the voids), ground-state start, spontaneous-emission noise, 256 probe
+(6.4 um box, 7162 spheres of mean diameter 300 nm, index 2.9, fill 0.4, packed
+by the library's soft-sphere compression, gain in the voids), ground-state start, spontaneous-emission noise, 256 probe
 sites with running DFT spectra over 450-800 nm at the resolution of the full
 3 ps run, graded absorbing walls -- advanced as a batch of 5 pump levels
 N_a in {1, 2, 3.5, 5, 7} x 1e24 m^-3, one launch of each step kernel per
@@ -59,10 +59,13 @@ def parse():
                          "compression packing of the 320^3 sample; gp: Gross-Pitaevskii bound "
                          "states of a 256-point pump sweep")
     ap.add_argument("--pack-runs", type=int, default=5, help="timed packings of --workload pack")
-    ap.add_argument("--packing", choices=["rsa", "md"], default="rsa",
-                    help="c5 sample: random sequential addition (default) or the library's "
-                         "soft-sphere compression packing")
+    ap.add_argument("--packing", choices=["rsa", "md"], default="md",
+                    help="c5 sample: the library's soft-sphere compression packing (default; random "
+                         "sequential addition stalls near a nominal fill of 0.36 at 320^3) or RSA at 0.36")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick-cpu", action="store_true", help="time only 2 oracle steps of the c5 realization")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="c5: skip the batched (c3, reduced) and adjoint (c4) legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain elementwise kernel of known traffic (counter calibration)")
@@ -209,30 +212,62 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(n, eps, gain, seconds):
-    """The FP64 oracle, as it stands, on a bounded number of steps of one
-    realization of the same workload."""
-    import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    p = O.default_params(n, bc=(O.ABSORB,) * 3, seed=0, realization=0)
+def _omp_threads(k):
+    """Set the OpenMP thread count of the calling thread (the oracle's
+    parallel regions run on libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+
+
+def oracle_window(O, n, eps, gain, bc, init, Na, steps, threads):
+    """Cell-updates/s of the FP64 oracle, as it stands, over `steps` steps of
+    one realization (after one untimed step that pages the arrays in)."""
+    _omp_threads(threads)
+    p = O.default_params(n, bc=(bc,) * 3, seed=0, realization=0)
     o = O.Oracle(p)
     o.set_material(eps, gain)
-    o.set_pump(NA_LEVELS[1], O.GROUND)
-    o.step(1)                      # first touch of the arrays
+    o.set_pump(Na, init)
+    o.step(1)
     t0 = time.perf_counter()
-    steps = 0
-    while True:
-        o.step(1)
-        steps += 1
-        if time.perf_counter() - t0 >= seconds or steps >= 50:
-            break
+    o.step(steps)
     dt = time.perf_counter() - t0
     o.close()
-    return {"value": n ** 3 * steps / dt, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} steps of one {n}^3 realization (N_a = 2e24, FP64, "
-                      f"{threads} OpenMP threads), after one untimed step"}
+    return n ** 3 * steps / dt, dt
+
+
+def cpu_baseline(I, n5, eps5, gain5, quick=False):
+    """The FP64 oracle timed on the machine's host cores: the paper-scale
+    realization (the metric's workload) on every core of the affinity mask,
+    plus windows of the other workloads, on every core and on one core."""
+    import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    mats = {
+        "c1": (32, I.voxelize(I.packing_for("c1", 32, 0)), O.PEC, O.PREPUMPED),
+        "c2": (128, I.voxelize(I.packing_for("c2", 128, 0)), O.ABSORB, O.PREPUMPED),
+        "c4": (96, I.voxelize(I.packing_for("c4", 96, 0)), O.PEC, O.PREPUMPED),
+        "c5": (n5, (eps5, gain5), O.ABSORB, O.GROUND),
+    }
+    # (workload, steps on all cores, steps on one core)
+    plan = [("c1", 500, 100), ("c2", 200, 10), ("c4", 100, 10), ("c5", 10, 1)]
+    if quick:
+        plan = [("c5", 2, 0)]
+    windows = []
+    for name, s_all, s_one in plan:
+        n, (eps, gain), bc, init = mats[name]
+        for threads, steps in ((cores, s_all), (1, s_one)):
+            if steps == 0:
+                continue
+            v, dt = oracle_window(O, n, eps, gain, bc, init, 2e24, steps, threads)
+            windows.append({"workload": name, "n": n, "steps": steps, "cores": threads,
+                            "value": v, "seconds": dt})
+            log(f"oracle {name} {n}^3 x {steps} steps on {threads} core(s): {v:.3e} cu/s ({dt:.1f} s)")
+    _omp_threads(cores)
+    main = next(w for w in windows if w["workload"] == "c5" and w["cores"] == cores)
+    return {"value": main["value"], "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{main['steps']} steps of one {n5}^3 realization of the paper-scale workload "
+                      f"(N_a = 2e24, ground start, absorbing walls, FP64, {cores} OpenMP threads), "
+                      "after one untimed step",
+            "windows": windows}
 
 
 def c5_batch(args, I, mbf, stream):
@@ -246,7 +281,7 @@ def c5_batch(args, I, mbf, stream):
         pk = I.packing_from_centres(n, d, x)
         log(f"compression packing: largest overlap {ov:.2e} cells")
     else:
-        pk = I.rsa_pack(n, seed=0, fill=0.4)
+        pk = I.rsa_pack(n, seed=0, fill=0.36)
     eps, gain = I.voxelize(pk)
     log(f"packing: {pk.count} spheres, voxel fill {1 - gain.mean():.3f} ({time.perf_counter() - t0:.1f} s)")
     probes = I.select_probes(eps, gain, 256, seed=0)
@@ -295,31 +330,100 @@ def c3_batch(args, I, mbf, stream):
     return batch, cells, config, (sizes, mats, levels)
 
 
-def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream):
-    """The same realizations stepped one after another through the plain path
-    (each with its own graph, all on the batch's stream, so that one runs at a
-    time): cell-updates/s, timed with events on that stream."""
+def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream, concurrent=False):
+    """The same realizations stepped through the plain path, each with its own
+    graph: one after another on the batch's stream (concurrent=False, so
+    that one runs at a time), or each on a stream of its own, all launched
+    before any is waited for (concurrent=True).  Cell-updates/s over the
+    wall time between two device-wide synchronisations."""
     import torch
-    sims = []
+    sims, streams = [], []
     for r, N in enumerate(sizes):
-        s = mbf.Sim(N, boundary="pec", seed=0, realization=r, stream=stream.cuda_stream)
+        st = torch.cuda.Stream() if concurrent else stream
+        streams.append(st)
+        s = mbf.Sim(N, boundary="pec", seed=0, realization=r, stream=st.cuda_stream)
         s.set_tuning(**tuning)
         s.set_material(*mats[r])
         s.set_pump(levels[r], "prepumped")
         s.step(32)
         sims.append(s)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    t0 = time.perf_counter()
     for s in sims:
         s.step(steps)
-    e1.record(stream)
     torch.cuda.synchronize()
-    dt = e0.elapsed_time(e1) / 1e3
+    dt = time.perf_counter() - t0
     for s in sims:
         s.close()
     return sum(N ** 3 for N in sizes) * steps / dt
+
+
+def c3_leg(args, I, mbf, steps=256, budget_ms=3000):
+    """The batched workload of many small realizations, reduced to `steps`
+    steps: the autotuned batch against the same 64 realizations run one at a
+    time (serially on one stream) and run side by side (a stream each)."""
+    import torch
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    batch, cells, config, (sizes, mats, levels) = c3_batch(args, I, mbf, stream)
+    tuning = batch.autotune(budget_ms=budget_ms)
+    batch.step(32)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    batched = cells * steps / (time.perf_counter() - w0)
+    batch.close()
+    serial = one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream)
+    conc = one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream, concurrent=True)
+    log(f"c3 leg ({steps} steps, {time.perf_counter() - t0:.1f} s): batched {batched:.3e}, one at a time "
+        f"{serial:.3e}, side by side {conc:.3e} cu/s; tuning {tuning}")
+    return {"workload": config["workload"], "steps": steps, "tuning": tuning,
+            "batched": batched, "one_at_a_time": serial, "side_by_side": conc,
+            "batched_over_one_at_a_time": batched / serial, "batched_over_side_by_side": batched / conc}
+
+
+def adjoint_leg(I, mbf, runs=3):
+    """The adjoint workload (96^3, 1000 steps, K = 50, FP32, PEC, loss box
+    [40, 56)^3): wall time of the reverse sweep (mbf_adjoint_run minus a
+    plain forward run of the same steps) over the plain forward run; the
+    median of `runs` ratios, each from a fresh handle (the adjoint run starts
+    from the pump)."""
+    import torch
+    eps, gain = I.voxelize(I.packing_for("c4", 96, 0))
+
+    def fresh():
+        s = mbf.Sim(96, boundary="pec", seed=0, realization=0)
+        s.set_material(eps, gain)
+        s.set_pump(2e24, "prepumped")
+        s.set_loss_box((40, 40, 40), (56, 56, 56))
+        return s
+    ratios, fw, ad = [], [], []
+    for _ in range(runs + 1):                    # the first pair warms up
+        s = fresh()
+        s.sync()
+        t0 = time.perf_counter()
+        s.adjoint_run(1000, K=50)
+        t_adj = time.perf_counter() - t0
+        s.close()
+        s = fresh()
+        s.step(8)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(1000)
+        s.sync()
+        t_fwd = time.perf_counter() - t0
+        s.close()
+        ratios.append((t_adj - t_fwd) / t_fwd)
+        fw.append(t_fwd)
+        ad.append(t_adj)
+    ratios, fw, ad = ratios[1:], fw[1:], ad[1:]
+    med = float(np.median(ratios))
+    log(f"adjoint leg: reverse sweep / forward = {['%.2f' % r for r in ratios]} (median {med:.2f}); "
+        f"forward {np.median(fw) * 1e3:.1f} ms, forward + adjoint {np.median(ad) * 1e3:.1f} ms")
+    return {"workload": "96^3 x 1000 steps, K = 50, FP32, PEC, loss box [40,56)^3",
+            "reverse_over_forward_median": med, "ratios": ratios,
+            "forward_ms": float(np.median(fw) * 1e3), "forward_plus_adjoint_ms": float(np.median(ad) * 1e3)}
 
 
 PACK_SCHEDULE = dict(s0=0.5, stages=100, iters=20, final_iters=1000, eta=0.15)
@@ -544,14 +648,22 @@ def main():
         batch.close()
         sizes, mats, levels = extra
         solo = one_at_a_time(mbf, sizes, mats, levels, args.steps, tuning, stream)
+        conc = one_at_a_time(mbf, sizes, mats, levels, args.steps, tuning, stream, concurrent=True)
         extra_out["one_at_a_time"] = {"value": solo, "unit": "cell-updates/s",
                                       "ratio_batched_over_solo": value / solo}
-        log(f"one at a time: {solo:.3e} cu/s; batched / one at a time = {value / solo:.2f}")
-    elif not args.no_cpu_baseline:
+        extra_out["side_by_side"] = {"value": conc, "unit": "cell-updates/s",
+                                     "ratio_batched_over_side_by_side": value / conc}
+        log(f"one at a time: {solo:.3e} cu/s, side by side {conc:.3e} cu/s; batched / one at a time = "
+            f"{value / solo:.2f}, batched / side by side = {value / conc:.2f}")
+    else:
         batch.close()
         eps, gain = extra
-        cpu = cpu_baseline(args.n, eps, gain, args.cpu_seconds)
-        log(f"cpu baseline: {cpu}")
+        if not args.no_legs:
+            extra_out["batched_leg"] = c3_leg(args, I, mbf)
+            extra_out["adjoint_leg"] = adjoint_leg(I, mbf)
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline(I, args.n, eps, gain, quick=args.quick_cpu)
+            log(f"cpu baseline: {cpu['value']:.3e} cu/s on {cpu['cores']} cores")
 
     out = {
         "metric": "cell-updates/s",
@@ -579,6 +691,10 @@ def main():
             "avg_launch_ms": avg_kern_s * 1e3,
             "step_alg_bytes": alg[0],
             "step_kernels_ms": [kern_ms[0] / launches, kern_ms[1] / launches],
+            # the whole step (every kernel of a time step, graph-replayed):
+            # its algorithmic bytes over the timed milliseconds per step
+            "step_achieved": alg[0] / (wall_ms / args.steps / 1e3) / 1e9,
+            "step_frac": alg[0] / (wall_ms / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS,
             # cell-updates/s priced at the dense 157 B per cell-update (every
             # cell with three gain sites), over the same peak
             "effective_frac_157B": value * DENSE_BYTES_PER_CU / (HBM_PEAK_GBS * 1e9),

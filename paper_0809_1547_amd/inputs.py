@@ -76,10 +76,13 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
     box volume.
 
     Candidate centres are drawn uniformly from the unit voxels not yet known to
-    be fully excluded for the smallest possible radius, then tested exactly; the
+    be fully excluded for the sphere being placed, then tested exactly; the
     accepted spheres therefore follow the same distribution as plain RSA
     (uniform centre over the box, rejection on overlap), only with far fewer
-    wasted draws near jamming.
+    wasted draws near jamming.  Exclusion is tracked for a few radius classes
+    (class radii from the smallest possible radius upwards); a sphere draws
+    from the map of the largest class radius not above its own, which never
+    excludes a position the sphere could take.
     """
     if isinstance(n, int):
         n = (n, n, n)
@@ -94,18 +97,21 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
         rmin = rmax = float(radius)
     else:
         rmin, rmax = 0.5 * (mean_d - 3 * sd_d), 0.5 * (mean_d + 3 * sd_d)
+    n_cls = 1 if rmax == rmin else 8
+    cls_r = [rmin + (rmax - rmin) * q / n_cls for q in range(n_cls)]
     cell = 2.0 * rmax
     grid_shape = tuple(max(1, int(math.ceil(b / cell))) for b in n)
     buckets: Dict[Tuple[int, int, int], List[int]] = {}
     centres: List[np.ndarray] = []
     radii: List[float] = []
-    excluded = np.zeros((nz, ny, nx), dtype=bool)
+    excluded = np.zeros((n_cls, nz, ny, nx), dtype=bool)
     half_diag = 0.5 * math.sqrt(3.0)
     vol = 0.0
     attempts = 0
-    r = None                                   # diameter/2 of the sphere being placed
-    free = None
-    cursor = 0
+    r = None                                   # radius of the sphere being placed
+    q = 0                                      # its radius class
+    free = [None] * n_cls
+    cursor = [0] * n_cls
     batch = 4096
 
     def draw_radius() -> float:
@@ -123,18 +129,20 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
             break
         if attempts >= max_attempts:
             raise RuntimeError(f"RSA jammed after {attempts} attempts with {len(radii)} spheres")
-        if free is None or cursor >= len(free):
-            idx = np.flatnonzero(~excluded.ravel())
-            if idx.size == 0:
-                raise RuntimeError(f"RSA jammed: no free voxel left with {len(radii)} spheres")
-            free = idx[rng.integers(0, idx.size, size=batch)]
-            cursor = 0
-        v = int(free[cursor])
-        cursor += 1
-        attempts += 1
         if r is None:
             r = draw_radius()
-        if excluded.flat[v]:
+            q = 0 if n_cls == 1 else min(n_cls - 1, int((r - rmin) / (rmax - rmin) * n_cls))
+        exq = excluded[q]
+        if free[q] is None or cursor[q] >= len(free[q]):
+            idx = np.flatnonzero(~exq.ravel())
+            if idx.size == 0:
+                raise RuntimeError(f"RSA jammed: no free voxel left with {len(radii)} spheres")
+            free[q] = idx[rng.integers(0, idx.size, size=batch)]
+            cursor[q] = 0
+        v = int(free[q][cursor[q]])
+        cursor[q] += 1
+        attempts += 1
+        if exq.flat[v]:
             continue
         vk, rem = divmod(v, nx * ny)
         vj, vi = divmod(rem, nx)
@@ -160,18 +168,20 @@ def rsa_pack(n: Tuple[int, int, int] | int, *, seed: int,
         centres.append(c)
         radii.append(r)
         vol += 4.0 / 3.0 * math.pi * r ** 3
-        r_placed, r = r, None
-        # voxels whose every point lies closer than r + rmin to this centre can
-        # never hold another centre
-        reach = r_placed + rmin - half_diag
-        if reach > 0:
+        # voxels whose every point lies closer than r + (class radius) to this
+        # centre can never hold the centre of a sphere of that class
+        for qq in range(n_cls):
+            reach = r + cls_r[qq] - half_diag
+            if reach <= 0:
+                continue
             lo = [max(0, int(math.floor(c[a] - reach - 1))) for a in range(3)]
             hi = [min(n[a], int(math.ceil(c[a] + reach + 1))) for a in range(3)]
             xs = np.arange(lo[0], hi[0]) + 0.5 - c[0]
             ys = np.arange(lo[1], hi[1]) + 0.5 - c[1]
             zs = np.arange(lo[2], hi[2]) + 0.5 - c[2]
             d2 = zs[:, None, None] ** 2 + ys[None, :, None] ** 2 + xs[None, None, :] ** 2
-            excluded[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= d2 < reach * reach
+            excluded[qq, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= d2 < reach * reach
+        r = None
     return Packing(n, np.array(centres, dtype=np.float64).reshape(-1, 3),
                    np.array(radii, dtype=np.float64))
 

@@ -19,7 +19,9 @@ STEPS = 40
 def test_320_cubed_batch_member_matches_oracle():
     from paper_0809_1547_amd import mbf
     print("320^3 full-size parity: packing", flush=True)
-    eps, gain = I.voxelize(I.rsa_pack(N, seed=0, fill=0.4))
+    # random sequential addition stalls near a nominal fill of 0.36 at this
+    # size (the bench's own sample is the compression packing)
+    eps, gain = I.voxelize(I.rsa_pack(N, seed=0, fill=0.36))
     probes = I.select_probes(eps, gain, 256, seed=0)
     cfgs = [mbf.make_config(N, boundary="absorb", seed=0, realization=r, E_sp=1e-2) for r in range(2)]
     batch = mbf.Batch(cfgs)
