@@ -422,7 +422,7 @@ def adjoint_leg(I, mbf, runs=3):
     log(f"adjoint leg: reverse sweep / forward = {['%.2f' % r for r in ratios]} (median {med:.2f}); "
         f"forward {np.median(fw) * 1e3:.1f} ms, forward + adjoint {np.median(ad) * 1e3:.1f} ms")
     return {"workload": "96^3 x 1000 steps, K = 50, FP32, PEC, loss box [40,56)^3",
-            "reverse_over_forward_median": med, "ratios": ratios,
+            "reverse_over_forward_median": med, "ratios": ratios, "within_3x": med <= 3.0,
             "forward_ms": float(np.median(fw) * 1e3), "forward_plus_adjoint_ms": float(np.median(ad) * 1e3)}
 
 

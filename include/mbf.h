@@ -349,6 +349,10 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  *     wave owns a row and forms again the few H^{n+1/2} values of the
  *     neighbouring row, column and plane that it needs (waves exchange no
  *     field values).
+ *   MBF_VARIANT_FUSED_LDS: rows a1-a5 in one z-marching kernel whose waves
+ *     advance plane by plane together (one barrier per plane) and hand the
+ *     H^{n+1/2} of their rows to the neighbouring row's E update through
+ *     LDS; only the tile's edges are formed again.  zseg = 0 means 8.
  * group_mb (batches only; >= 0): consecutive members whose device state adds
  * up to at most group_mb MiB form a group, and a graph-replayed chunk of
  * steps runs group by group, so that a group's state can stay in the
@@ -360,6 +364,7 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 #define MBF_VARIANT_TWO_PASS_SPLIT 2
+#define MBF_VARIANT_FUSED_LDS 3
 typedef struct mbf_tuning {
     int32_t variant;
     int32_t tile_y;
@@ -376,7 +381,12 @@ int mbf_get_tuning(const mbf_handle* h, mbf_tuning* t);
  * simulation state is saved to device memory before the trials and restored
  * after them, so the run continues exactly as if autotune had not been
  * called; this needs one extra copy of the state in device memory
- * (MBF_ENOMEM otherwise).  Needs material and pump (MBF_ESTATE). */
+ * (MBF_ENOMEM otherwise).  Needs material and pump (MBF_ESTATE).
+ * Persistence: when the environment variable MBF_TUNE_CACHE names a file,
+ * the choice is appended to it, keyed by the device architecture, the
+ * precision and the grid and walls, and a later call with the same key (in
+ * this or another process) applies the stored schedule without timing
+ * anything.  mbf_batch_autotune does the same, keyed by every member. */
 int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen);
 
 /* Queue nsteps steps without graph capture, bracketing the field kernels of
@@ -453,6 +463,38 @@ int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu
 /* E(p) of Eq. ee and the threshold pump p_th (E = 1). */
 double mbf_gp_eigenvalue(double p, double kappa);
 double mbf_gp_threshold(double kappa);
+
+/* ST-law linewidth fit (Gross-Pitaevskii section, Eqs. ee, s1, wth and the
+ * numerical waist of Eq. g5, compared with the Maxwell-Bloch linewidths in
+ * Fig. 5b): kappa such that, with p = p_th(kappa) Na[i] / N_th,
+ * E = (p - 1)/(kappa sqrt(p)) and the model waist (in frequency omega/2pi)
+ * W_model = w(E) sqrt(kappa) / (p^{1/4} t_g), the squared log misfit
+ * sum_i (ln W_model_i - ln W[i])^2 is least; w(E) is the waist of the bound
+ * state (mbf_gp_solve on M points of [-L, L], n_nu spectrum points of
+ * spacing dnu).  Golden-section search over ln kappa in [ln 1e-3, ln 10] to a
+ * bracket of 1e-10; a kappa for which some eigenvalue exceeds (0.7 L)^2 (the
+ * bound state would not fit the window) or a bound state does not converge
+ * counts as no fit.  Na[n] (m^-3, each > N_th) and W[n] (Hz, > 0) are host
+ * arrays; *kappa and, when not NULL, W_fit[n] (the model waists at kappa) are
+ * host outputs.  Runs on `stream`, returns when done.  MBF_EINVAL for bad
+ * sizes, MBF_ENONFINITE when no kappa in the range gives every bound state. */
+int mbf_kappa_fit(const double* Na, const double* W, int n, double N_th, double t_g, int M, double L, int n_nu,
+                  double dnu, void* stream, double* kappa, double* W_fit);
+
+/* Lasing threshold of a pump sweep (Results section, Fig. 5b: the threshold
+ * E = 1 of the theory, located on the simulations themselves).  Each run
+ * starts from the pumped state with a seeded field and no noise; its energy
+ * history W^n (mbf_read_energy_history) grows or decays with the
+ * least-damped mode.  rate = least-squares slope of ln W^n over
+ * n0 <= n < n1 (per step); the threshold is the root N_th = -a/b of the
+ * least-squares line rate = a + b N_a through the runs.  hist[n_runs *
+ * stride] (run r at r * stride; host or device per mem_kind, caller-owned),
+ * Na[n_runs] host (m^-3); rates[n_runs] and fit[3] = (a, b, N_th) are host
+ * outputs.  n_runs >= 2 with distinct N_a, 0 <= n0, n1 - n0 >= 2,
+ * stride >= n1 (MBF_EINVAL otherwise); a non-positive W in the window gives
+ * MBF_ENONFINITE.  Runs on `stream` and returns when done. */
+int mbf_growth_threshold(const double* hist, int n_runs, int64_t stride, int64_t n0, int64_t n1, const double* Na,
+                         int mem_kind, void* stream, double* rates, double* fit);
 
 /* ------------------------------------------------------------- packing
  * The sample is a granular packing of dielectric spheres obtained by
@@ -535,6 +577,11 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen);
 /* mbf_spectrum_stats of every member: out[R], member order (the linewidth
  * and peak against the members' pump levels). */
 int mbf_batch_spectrum_stats(mbf_batch* b, double level, mbf_spec_stats* out);
+
+/* mbf_growth_threshold over the members' own energy histories (device) and
+ * pump levels: every member needs an energy history of at least n1 steps and
+ * to have taken n1 steps (MBF_ESTATE otherwise). */
+int mbf_batch_growth_threshold(mbf_batch* b, int64_t n0, int64_t n1, double* rates, double* fit);
 
 #ifdef __cplusplus
 }

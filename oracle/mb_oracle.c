@@ -312,13 +312,19 @@ int orc_set_pump(orc_sim* s, double Na_si, int init) {
         N[0] = na;
     } else if (init == ORC_INIT_PREPUMPED) {
         /* E = 0 fixed point of the discrete rates (null space of the rate
-         * matrix): dtWp N0 = dt32 N3 = dt21 N2 = dt10 N1 */
+         * matrix): dtWp N0 = dt32 N3 = dt21 N2 = dt10 N1 with N0 = N_a - N1 -
+         * N2 - N3.  N2, which holds almost all atoms, is set first; N1 and N3
+         * then solve their own equations for the rounded N2 (N3 with N0 =
+         * N_a - N1 - N2 - N3, i.e. N3 = dtWp (N_a - N1 - N2)/(dt32 + dtWp)),
+         * so that with rounded populations each equation is off by the
+         * rounding of its own population only (N3 computed from the unrounded
+         * N0 would be off by the rounding of N2, relative to the small N0) */
         double d32 = s->rates[0], d21 = s->rates[1], d10 = s->rates[2], dwp = s->rates[3];
         double n0 = na / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
-        N[3] = rnd(s, dwp * n0 / d32);
         N[2] = rnd(s, dwp * n0 / d21);
-        N[1] = rnd(s, dwp * n0 / d10);
-        N[0] = s->p.round_f32 ? na - (N[1] + N[2] + N[3]) : n0;
+        N[1] = rnd(s, d21 * N[2] / d10);
+        N[3] = rnd(s, dwp * (na - N[1] - N[2]) / (d32 + dwp));
+        N[0] = na - (N[1] + N[2] + N[3]);
     } else {
         return -1;
     }

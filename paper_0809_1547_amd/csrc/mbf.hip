@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -92,6 +93,7 @@ struct mbf_handle {
     int64_t lev_stride = 0;
     void* lc = nullptr;       // (ca, cb) per level triple, in the field type
     uint32_t lc_dim[3] = {1, 1, 1};
+    int lay_kz[2] = {0, 0};   // planes with zero z parts of the layer table: [lay_kz[0], lay_kz[1])
     bool has_layer = false;
     int64_t gain_sites = 0;   // interior E-sites of gain cells
     bool have_material = false, have_pump = false;
@@ -182,6 +184,21 @@ int build_layer_table(mbf_handle* h, const mbf_config& c, std::string& err) {
         h->has_layer = h->has_layer || vals[a].size() > 1;
     }
     for (int a = 0; a < 3; ++a) h->lc_dim[a] = (uint32_t)vals[a].size();
+    // the run of planes between the z layers (both z parts zero), so that the
+    // kernels load no z part there; empty when the zero planes do not form one
+    // run
+    {
+        auto zero = [&](int k) {
+            return lev[(size_t)4 * h->lev_stride + k] == 0 && lev[(size_t)5 * h->lev_stride + k] == 0;
+        };
+        int lo = 0, hi = c.nz;
+        while (lo < c.nz && !zero(lo)) ++lo;
+        while (hi > lo && !zero(hi - 1)) --hi;
+        bool run = true;
+        for (int k = lo; k < hi; ++k) run = run && zero(k);
+        h->lay_kz[0] = run ? lo : 0;
+        h->lay_kz[1] = run ? hi : 0;
+    }
     const size_t ntab = (size_t)h->lc_dim[0] * h->lc_dim[1] * h->lc_dim[2];
     std::vector<uint8_t> tab(2 * ntab * h->esz);
     for (uint32_t lx = 0; lx < h->lc_dim[0]; ++lx)
@@ -312,6 +329,8 @@ mbf::SimView<T> view(mbf_handle* h) {
     v.lc = reinterpret_cast<const T*>(h->lc);
     v.lc_sy = h->lc_dim[1] * h->lc_dim[2];
     v.lc_sz = h->lc_dim[2];
+    v.lay_kz[0] = h->lay_kz[0];
+    v.lay_kz[1] = h->lay_kz[1];
     v.ctl = h->ctl;
     v.e_part = h->e_part;
     v.l_part = h->l_part;
@@ -333,7 +352,10 @@ mbf::SimView<T> view(mbf_handle* h) {
 
 // Step kernels: workgroups of 64 x tile_y columns, each over zseg planes.
 // zseg 0: 2-plane segments for the split variant, 4 for the others.
-int default_zseg(const mbf_tuning& t) { return t.variant == MBF_VARIANT_TWO_PASS_SPLIT ? 2 : 4; }
+int default_zseg(const mbf_tuning& t) {
+    return t.variant == MBF_VARIANT_TWO_PASS_SPLIT ? 2 : (t.variant == MBF_VARIANT_FUSED_LDS ? 8 : 4);
+}
+bool single_pass(int variant) { return variant == MBF_VARIANT_FUSED || variant == MBF_VARIANT_FUSED_LDS; }
 int step_zseg(const mbf_handle* h, const mbf_tuning& t) {
     return t.zseg > 0 ? std::min(t.zseg, h->cfg.nz) : std::min(default_zseg(t), h->cfg.nz);
 }
@@ -431,6 +453,16 @@ hipError_t launch_fields(hipStream_t st, const mbf_tuning& tun, const mbf::SimVi
     const int rm = tun.xcd_remap;
     const dim3 g((unsigned)ni);
     hipError_t e = hipSuccess;
+    if (tun.variant == MBF_VARIANT_FUSED_LDS) {
+        switch (tun.tile_y) {
+            case 2: hipLaunchKernelGGL((mbf::k_step_lds_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
+            case 4: hipLaunchKernelGGL((mbf::k_step_lds_batch<T, 4>), g, dim3(64, 4), 0, st, vw, gw, it, ni, rm); break;
+            case 16: hipLaunchKernelGGL((mbf::k_step_lds_batch<T, 16>), g, dim3(64, 16), 0, st, vw, gw, it, ni, rm); break;
+            default: hipLaunchKernelGGL((mbf::k_step_lds_batch<T, 8>), g, dim3(64, 8), 0, st, vw, gw, it, ni, rm); break;
+        }
+        if (evm) e = hipEventRecord(evm, st);
+        return e;
+    }
     if (tun.variant == MBF_VARIANT_FUSED) {
         switch (tun.tile_y) {
             case 2: hipLaunchKernelGGL((mbf::k_step_fused_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
@@ -737,7 +769,7 @@ std::vector<mbf_tuning> tuning_candidates(const mbf_tuning& dflt) {
     const int dz = dflt.zseg > 0 ? dflt.zseg : default_zseg(dflt);
     std::vector<mbf_tuning> c;
     c.push_back({dflt.variant, dflt.tile_y, dz, dflt.xcd_remap, 0});
-    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED})
+    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED, MBF_VARIANT_FUSED_LDS})
         for (int ty : {2, 4, 8})
             for (int zs : {2, 4, 8})
                 if (!(var == dflt.variant && ty == dflt.tile_y && zs == dz)) c.push_back({var, ty, zs, 2, 0});
@@ -753,6 +785,56 @@ uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t hsh = 1469598103934665603ull
 }
 
 }  // namespace
+
+// Persisted autotuning: with MBF_TUNE_CACHE naming a file, a schedule chosen
+// by mbf_autotune / mbf_batch_autotune is appended to it as one line
+//   <key> TAB <variant> <tile_y> <zseg> <xcd_remap> <group_mb>
+// keyed by the device architecture, the precision and every member's grid
+// and walls, and a later call with the same key takes it from there instead
+// of timing the candidates again (the last line of a key wins).
+std::string tune_key(const std::vector<mbf_handle*>& m, bool batch) {
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = std::string(batch ? "batch" : "single") + ";arch=" + arch +
+                    ";prec=" + (m[0]->cfg.precision == MBF_FP64 ? "fp64" : "fp32");
+    for (const mbf_handle* h : m) {
+        const mbf_config& c = h->cfg;
+        k += ";" + std::to_string(c.nx) + "x" + std::to_string(c.ny) + "x" + std::to_string(c.nz) + ":" +
+             std::to_string(c.boundary[0]) + std::to_string(c.boundary[1]) + std::to_string(c.boundary[2]);
+    }
+    return k;
+}
+
+bool tune_lookup(const std::string& key, mbf_tuning* t) {
+    const char* path = std::getenv("MBF_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    std::vector<char> line(1 << 16);
+    while (std::fgets(line.data(), (int)line.size(), f)) {
+        const char* tab = std::strchr(line.data(), '\t');
+        if (!tab || std::string(line.data(), (size_t)(tab - line.data())) != key) continue;
+        mbf_tuning x{};
+        if (std::sscanf(tab + 1, "%d %d %d %d %d", &x.variant, &x.tile_y, &x.zseg, &x.xcd_remap, &x.group_mb) == 5) {
+            *t = x;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const std::string& key, const mbf_tuning& t) {
+    const char* path = std::getenv("MBF_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%d %d %d %d %d\n", key.c_str(), t.variant, t.tile_y, t.zseg, t.xcd_remap, t.group_mb);
+    std::fclose(f);
+}
 
 // ======================================================================= ABI
 
@@ -1066,13 +1148,20 @@ int mbf_set_pump(mbf_handle* h, double Na, int init) {
     h->co = c.precision == MBF_FP64 ? make_coef<double>(c, Na) : make_coef<float>(c, Na);
     h->Na_si = Na;
     h->init_kind = init;
+    // prepumped: the E = 0 fixed point of the discrete rates (dtWp N0 = dt32
+    // N3 = dt21 N2 = dt10 N1), N2 (almost all atoms) rounded first, then N1
+    // and N3 solving their own equations for the rounded N2 (N3 with N0 =
+    // N_a - N1 - N2 - N3), so each equation is off by its own population's
+    // rounding only; every value rounded once to the field type
     double N1 = 0, N2 = 0, N3 = 0;
     if (init == MBF_INIT_PREPUMPED) {
         const double d32 = h->co.rates[0], d21 = h->co.rates[1], d10 = h->co.rates[2], dwp = h->co.rates[3];
-        const double n0 = h->co.Na / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
-        N3 = dwp * n0 / d32;
-        N2 = dwp * n0 / d21;
-        N1 = dwp * n0 / d10;
+        const double na = h->co.Na;
+        const double n0 = na / (1.0 + dwp / d32 + dwp / d21 + dwp / d10);
+        auto r = [&](double x) { return c.precision == MBF_FP64 ? x : (double)(float)x; };
+        N2 = r(dwp * n0 / d21);
+        N1 = r(d21 * N2 / d10);
+        N3 = r(dwp * (na - N1 - N2) / (d32 + dwp));
     }
     const size_t bytes = (size_t)h->nsite * h->esz;
     HIPCHK(h, hipMemsetAsync(h->pool, 0, bytes * 12, h->stream));               // E, H (both buffers)
@@ -1327,7 +1416,7 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes) {
     const double v = (double)h->esz;
     const double gs = (double)h->gain_sites;
     bytes[0] = cells * (12.0 * v + 1.0) + gs * 9.0 * v;      // the step
-    if (h->tun.variant == MBF_VARIANT_FUSED) {
+    if (single_pass(h->tun.variant)) {
         bytes[1] = bytes[0];
         bytes[2] = 0.0;
     } else {
@@ -1339,7 +1428,8 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes) {
 
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
     if (!h || !t) return fail(h, MBF_EINVAL, "null argument");
-    if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS && t->variant != MBF_VARIANT_TWO_PASS_SPLIT)
+    if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS && t->variant != MBF_VARIANT_TWO_PASS_SPLIT &&
+        t->variant != MBF_VARIANT_FUSED_LDS)
         return fail(h, MBF_EINVAL, "unknown variant");
     if (t->tile_y != 2 && t->tile_y != 4 && t->tile_y != 8 && t->tile_y != 16)
         return fail(h, MBF_EINVAL, "tile_y must be 2, 4, 8 or 16");
@@ -1363,6 +1453,13 @@ int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen) {
     if (!h) return fail(nullptr, MBF_EINVAL, "null handle");
     if (budget_ms < 0) return fail(h, MBF_EINVAL, "negative budget");
     if (!h->have_material || !h->have_pump) return fail(h, MBF_ESTATE, "set material and pump first");
+    const std::string key = tune_key({h}, false);
+    mbf_tuning cached{};
+    if (tune_lookup(key, &cached)) {
+        const int rc = mbf_set_tuning(h, &cached);
+        if (rc) return rc;
+        return chosen ? mbf_get_tuning(h, chosen) : MBF_OK;
+    }
     Snap sn;
     int rc = snap_alloc(h, sn);
     if (rc) return rc;
@@ -1394,6 +1491,7 @@ int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen) {
     snap_free(sn);
     if (rc) return rc;
     if (rc2) return rc2;
+    tune_store(key, h->tun);
     return chosen ? mbf_get_tuning(h, chosen) : MBF_OK;
 }
 
@@ -1468,6 +1566,39 @@ int spec_stats_device(mbf_handle* h, const double* dspec, int np, int nf, const 
     HIPCHK(h, hipMemcpyAsync(out, dout, sizeof(mbf_spec_stats), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     return MBF_OK;
+}
+
+// Growth rates of runs whose energy histories are the device arrays
+// ptrs[0..R) (window n0 <= n < n1) and the threshold line through (Na, rate),
+// on stream st; rates[R] and fit[3] are host outputs.
+int growth_threshold_dev(mbf_handle* h, const std::vector<const double*>& ptrs, int64_t n0, int64_t n1,
+                         const double* Na, hipStream_t st, double* rates, double* fit) {
+    const int R = (int)ptrs.size();
+    DevScratch ds;
+    const double** dptr = nullptr;
+    double *dna = nullptr, *drate = nullptr, *dfit = nullptr;
+    if (!ds.get(&dptr, (size_t)R) || !ds.get(&dna, (size_t)R) || !ds.get(&drate, (size_t)R) || !ds.get(&dfit, 3))
+        return fail(h, MBF_ENOMEM, "device allocation for the threshold fit failed");
+    HIPCHK(h, hipMemcpyAsync(dptr, ptrs.data(), sizeof(double*) * R, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(dna, Na, sizeof(double) * R, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(mbf::k_growth_rate, dim3((unsigned)R), dim3(mbf::kStatThreads), 0, st, dptr, n0, n1, drate);
+    hipLaunchKernelGGL(mbf::k_threshold_line, dim3(1), dim3(64), 0, st, dna, drate, R, dfit);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(rates, drate, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(fit, dfit, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    for (int r = 0; r < R; ++r)
+        if (!std::isfinite(rates[r])) return fail(h, MBF_ENONFINITE, "energy history not positive in the fit window");
+    return MBF_OK;
+}
+
+bool threshold_args_ok(int R, int64_t n0, int64_t n1, const double* Na) {
+    if (R < 2 || n0 < 0 || n1 - n0 < 2) return false;
+    for (int r = 0; r < R; ++r)
+        if (!std::isfinite(Na[r])) return false;
+    for (int r = 1; r < R; ++r)
+        if (Na[r] != Na[0]) return true;
+    return false;                                   // all pump levels equal: no line
 }
 
 bool stat_level_ok(double level) { return std::isfinite(level) && level > 0.0 && level < 1.0; }
@@ -1630,6 +1761,101 @@ int mbf_gp_solve(const double* E, int n_E, int M, double L, int n_nu, double dnu
 double mbf_gp_eigenvalue(double p, double kappa) { return (p - 1.0) / (kappa * std::sqrt(p)); }
 
 double mbf_gp_threshold(double kappa) { return 1.0 + 0.5 * kappa * kappa + 0.5 * kappa * std::sqrt(4.0 + kappa * kappa); }
+
+int mbf_kappa_fit(const double* Na, const double* W, int n, double N_th, double t_g, int M, double L, int n_nu,
+                  double dnu, void* stream, double* kappa, double* W_fit) {
+    if (!Na || !W || !kappa) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n < 1 || n > 65535 || !finite_pos(N_th) || !finite_pos(t_g) || M < 3 || M > mbf::kGpMaxM ||
+        !finite_pos(L) || n_nu < 2 || !finite_pos(dnu))
+        return fail(nullptr, MBF_EINVAL, "need 1 <= n <= 65535, N_th, t_g, L, dnu > 0, 3 <= M <= 1023, n_nu >= 2");
+    for (int i = 0; i < n; ++i)
+        if (!(std::isfinite(Na[i]) && Na[i] > N_th) || !finite_pos(W[i]))
+            return fail(nullptr, MBF_EINVAL, "every pump level must lie above N_th and every width be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    DevScratch ds;
+    double *dE = nullptr, *dphi = nullptr, *dspec = nullptr, *dst = nullptr;
+    if (!ds.get(&dE, (size_t)n) || !ds.get(&dphi, (size_t)n * M) || !ds.get(&dspec, (size_t)n * n_nu) ||
+        !ds.get(&dst, (size_t)n * mbf::kGpStats))
+        return fail(nullptr, MBF_ENOMEM, "device allocation for the kappa fit failed");
+    std::vector<double> E((size_t)n), p((size_t)n), stats((size_t)n * mbf::kGpStats), model((size_t)n);
+    int err = MBF_OK;
+    // model widths at kappa = exp(u) and the squared log misfit; +inf where a
+    // bound state would not fit the window (Thomas-Fermi radius sqrt(E) above
+    // 0.7 L) or did not converge
+    const double E_cap = (0.7 * L) * (0.7 * L);
+    auto misfit = [&](double u) -> double {
+        const double k = std::exp(u);
+        const double pth = mbf_gp_threshold(k);
+        for (int i = 0; i < n; ++i) {
+            p[(size_t)i] = pth * Na[i] / N_th;
+            E[(size_t)i] = mbf_gp_eigenvalue(p[(size_t)i], k);
+            if (!(E[(size_t)i] <= E_cap)) return HUGE_VAL;
+        }
+        mbf::GpArgs g{dE, M, L, n_nu, dnu, 400, 60, dphi, dspec, dst};
+        if (hipMemcpyAsync(dE, E.data(), sizeof(double) * n, hipMemcpyHostToDevice, st) != hipSuccess) err = MBF_EHIP;
+        hipLaunchKernelGGL(mbf::k_gp_solve, dim3((unsigned)n), dim3(mbf::kGpThreads), 0, st, g);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(stats.data(), dst, sizeof(double) * stats.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            err = MBF_EHIP;
+        double f = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double* q = stats.data() + (size_t)i * mbf::kGpStats;
+            if (q[6] != 1.0) return HUGE_VAL;
+            model[(size_t)i] = q[1] * std::sqrt(k) / (std::pow(p[(size_t)i], 0.25) * t_g);
+            const double d = std::log(model[(size_t)i]) - std::log(W[i]);
+            f += d * d;
+        }
+        return f;
+    };
+    // golden-section search over u = ln kappa in [ln 1e-3, ln 10] down to a
+    // bracket of 1e-10
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    double a = std::log(1e-3), b = std::log(10.0);
+    double c = b - gr * (b - a), d = a + gr * (b - a);
+    double fc = misfit(c), fd = misfit(d);
+    while (b - a > 1e-10 && !err) {
+        if (fc < fd) {
+            b = d; d = c; fd = fc;
+            c = b - gr * (b - a);
+            fc = misfit(c);
+        } else {
+            a = c; c = d; fc = fd;
+            d = a + gr * (b - a);
+            fd = misfit(d);
+        }
+    }
+    if (err) return fail(nullptr, err, "HIP error in the kappa fit");
+    const double u = 0.5 * (a + b);
+    if (!(misfit(u) < HUGE_VAL) || err)
+        return fail(nullptr, MBF_ENONFINITE, "kappa fit: no kappa in [1e-3, 10] gives bound states for every pump level");
+    *kappa = std::exp(u);
+    if (W_fit)
+        for (int i = 0; i < n; ++i) W_fit[i] = model[(size_t)i];
+    return MBF_OK;
+}
+
+int mbf_growth_threshold(const double* hist, int n_runs, int64_t stride, int64_t n0, int64_t n1, const double* Na,
+                         int mem_kind, void* stream, double* rates, double* fit) {
+    if (!hist || !Na || !rates || !fit) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (!threshold_args_ok(n_runs, n0, n1, Na) || stride < n1)
+        return fail(nullptr, MBF_EINVAL, "need >= 2 runs with distinct finite N_a, 0 <= n0, n1 - n0 >= 2, stride >= n1");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    hipStream_t st = (hipStream_t)stream;
+    DevScratch ds;
+    const double* base = hist;
+    if (mem_kind == MBF_MEM_HOST) {
+        double* d = nullptr;
+        if (!ds.get(&d, (size_t)n_runs * (size_t)stride))
+            return fail(nullptr, MBF_ENOMEM, "device allocation for the threshold fit failed");
+        HIPCHK(nullptr, hipMemcpyAsync(d, hist, sizeof(double) * (size_t)n_runs * (size_t)stride,
+                                       hipMemcpyHostToDevice, st));
+        base = d;
+    }
+    std::vector<const double*> ptrs((size_t)n_runs);
+    for (int r = 0; r < n_runs; ++r) ptrs[(size_t)r] = base + (size_t)r * (size_t)stride;
+    return growth_threshold_dev(nullptr, ptrs, n0, n1, Na, st, rates, fit);
+}
 
 int mbf_pack_md(int n, const double* box, const double* diam, double* centres, const mbf_pack_params* prm,
                 int mem_kind, void* stream, double* energy, double* max_overlap) {
@@ -2332,11 +2558,37 @@ int mbf_batch_spectrum_stats(mbf_batch* b, double level, mbf_spec_stats* out) {
     return MBF_OK;
 }
 
+int mbf_batch_growth_threshold(mbf_batch* b, int64_t n0, int64_t n1, double* rates, double* fit) {
+    if (!b || !rates || !fit) return bfail(b, MBF_EINVAL, "null argument");
+    const int R = (int)b->m.size();
+    std::vector<double> Na((size_t)R);
+    std::vector<const double*> ptrs((size_t)R);
+    for (int r = 0; r < R; ++r) {
+        const mbf_handle* h = b->m[(size_t)r];
+        if (!h->have_pump) return bfail(b, MBF_ESTATE, "set the pump of every member first");
+        if (h->hist_cap < n1 || h->step < n1)
+            return bfail(b, MBF_ESTATE, "every member needs an energy history reaching step n1");
+        Na[(size_t)r] = h->Na_si;
+        ptrs[(size_t)r] = h->hist;
+    }
+    if (!threshold_args_ok(R, n0, n1, Na.data()))
+        return bfail(b, MBF_EINVAL, "need >= 2 members with distinct pump levels, 0 <= n0 and n1 - n0 >= 2");
+    const int rc = growth_threshold_dev(b->m[0], ptrs, n0, n1, Na.data(), b->stream, rates, fit);
+    return rc ? bfail(b, rc, b->m[0]->err) : MBF_OK;
+}
+
 int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
     if (!b) return bfail(nullptr, MBF_EINVAL, "null batch");
     if (budget_ms < 0) return bfail(b, MBF_EINVAL, "negative budget");
     for (mbf_handle* h : b->m)
         if (!h->have_material || !h->have_pump) return bfail(b, MBF_ESTATE, "set material and pump of every member first");
+    const std::string key = tune_key(b->m, true);
+    mbf_tuning cached{};
+    if (tune_lookup(key, &cached)) {
+        const int rc = mbf_batch_set_tuning(b, &cached);
+        if (rc) return rc;
+        return chosen ? mbf_batch_get_tuning(b, chosen) : MBF_OK;
+    }
     std::vector<Snap> sn(b->m.size());
     int rc = MBF_OK;
     for (size_t r = 0; r < b->m.size() && !rc; ++r) {
@@ -2421,6 +2673,7 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
     for (Snap& q : sn) snap_free(q);
     if (rc) return rc;
     if (rc2) return rc2;
+    tune_store(key, b->tun);
     return chosen ? mbf_batch_get_tuning(b, chosen) : MBF_OK;
 }
 
@@ -2558,6 +2811,8 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     v.lc = reinterpret_cast<const T*>(h->lc);
     v.lc_sy = h->lc_dim[1] * h->lc_dim[2];
     v.lc_sz = h->lc_dim[2];
+    v.lay_kz[0] = h->lay_kz[0];
+    v.lay_kz[1] = h->lay_kz[1];
     v.has_layer = h->has_layer ? 1 : 0;
     const Coef& k = h->co;
     v.S = (T)k.S; v.a = (T)k.a; v.b = (T)k.b; v.ck = (T)k.ck; v.beta = (T)k.beta;
@@ -2671,6 +2926,7 @@ int mbf_adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int me
 }
 
 }  // extern "C"
+
 
 // ---------------------------------------- spectral statistics without allocation
 // mbf_spectral_stats_noalloc keeps the probe-summed power spectrum S_k, its

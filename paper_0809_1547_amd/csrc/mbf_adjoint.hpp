@@ -27,6 +27,7 @@ namespace mbf {
 
 template <typename T>
 struct AdjView {
+    using value_type = T;
     // forward trajectory: slot q = m - ctl->tap_base of `slot` values holds
     // E^m (3 x tap_e dense), P^m - P^{m-1} (3 x tap_c compact) and N1^m - N2^m
     // (3 x tap_c compact); a reverse step is told its slot q and takes back
@@ -54,6 +55,7 @@ struct AdjView {
     const uint8_t* lev[3][2];
     const T* lc;
     uint32_t lc_sy, lc_sz;
+    int lay_kz[2];
     // coefficients of the forward step
     T S, a, b, ck, beta, dt32, dt21, dt10, dtWp;
     T ck_esp;            // d c_F / d(N_a/N_ref) = ck E_sp (0 without noise)

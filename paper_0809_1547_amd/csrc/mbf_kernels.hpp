@@ -43,6 +43,7 @@ struct Ctl {                  // per-simulation control block (device memory)
 
 template <typename T>
 struct SimView {
+    using value_type = T;
     T* E[2][3];
     T* H[2][3];
     T* P[2][3];               // compact, one value per gain cell
@@ -85,6 +86,7 @@ struct SimView {
     const uint8_t* lev[3][2];
     const T* lc;
     uint32_t lc_sy, lc_sz;
+    int lay_kz[2];            // planes lay_kz[0] <= k < lay_kz[1] have zero z parts
     // monitors
     Ctl* ctl;
     double* e_part;           // per workgroup energy partial sums
@@ -252,25 +254,14 @@ __device__ __forceinline__ Fields<T> bind_fields(const SimView<T>& v, int par) {
 
 // Layer coefficients of a site: ca = (1 - a)/(1 + a) and cb = 1/(1 + a) for
 // its summed loss a, formed on the host in FP64 and rounded once to the field
-// type.  (1, 1) outside the layer, where the semi-implicit updates below
-// reduce to the plain Yee ones bit for bit (1 * x == x).
+// type, like every other coefficient.  (1, 1) outside the layer, where the
+// semi-implicit updates reduce to the plain Yee ones bit for bit (1 * x == x).
 template <typename T>
 struct LayC {
     T ca, cb;
 };
 
-// Table entry of an E-site of component c (half position along c) and of an
-// H-site of component c (half positions along the two other axes).
-template <typename V>
-__device__ __forceinline__ uint32_t lay_e(const V& v, int c, int i, int j, int k) {
-    return (uint32_t)gld(v.lev[0][c == 0] + i) * v.lc_sy + (uint32_t)gld(v.lev[1][c == 1] + j) * v.lc_sz +
-           (uint32_t)gld(v.lev[2][c == 2] + k);
-}
-template <typename V>
-__device__ __forceinline__ uint32_t lay_h(const V& v, int c, int i, int j, int k) {
-    return (uint32_t)gld(v.lev[0][c != 0] + i) * v.lc_sy + (uint32_t)gld(v.lev[1][c != 1] + j) * v.lc_sz +
-           (uint32_t)gld(v.lev[2][c != 2] + k);
-}
+// Table entry of a site from the parts of its three axes (lev * stride).
 template <typename T>
 __device__ __forceinline__ LayC<T> lay_coef(const T* lc, uint32_t t) {
     LayC<T> r{(T)1, (T)1};
@@ -280,13 +271,26 @@ __device__ __forceinline__ LayC<T> lay_coef(const T* lc, uint32_t t) {
     }
     return r;
 }
+
+// Per-axis parts of the table entry: axis a at index q, integer (hf = 0) or
+// half-integer (hf = 1) position.
 template <typename V>
-__device__ __forceinline__ auto lay_coef_e(const V& v, int c, int i, int j, int k) {
-    return lay_coef(v.lc, v.has_layer ? lay_e(v, c, i, j, k) : 0u);
+__device__ __forceinline__ uint32_t lay_part(const V& v, int a, int hf, int q) {
+    const uint32_t l = gld(v.lev[a][hf] + q);
+    return a == 0 ? l * v.lc_sy : (a == 1 ? l * v.lc_sz : l);
+}
+
+// Entry of an E-site of component c (half position along c) and of an H-site
+// of component c (half positions along the two other axes).
+template <typename V>
+__device__ __forceinline__ LayC<typename V::value_type> lay_coef_e(const V& v, int c, int i, int j, int k) {
+    if (!v.has_layer) return {(typename V::value_type)1, (typename V::value_type)1};
+    return lay_coef(v.lc, lay_part(v, 0, c == 0, i) + lay_part(v, 1, c == 1, j) + lay_part(v, 2, c == 2, k));
 }
 template <typename V>
-__device__ __forceinline__ auto lay_coef_h(const V& v, int c, int i, int j, int k) {
-    return lay_coef(v.lc, v.has_layer ? lay_h(v, c, i, j, k) : 0u);
+__device__ __forceinline__ LayC<typename V::value_type> lay_coef_h(const V& v, int c, int i, int j, int k) {
+    if (!v.has_layer) return {(typename V::value_type)1, (typename V::value_type)1};
+    return lay_coef(v.lc, lay_part(v, 0, c != 0, i) + lay_part(v, 1, c != 1, j) + lay_part(v, 2, c != 2, k));
 }
 
 // Compact index of the calling lane's cell in the Bloch-state arrays.  Must
@@ -301,6 +305,12 @@ __device__ __forceinline__ uint32_t gain_index(const V& v, int bx, int j, int k,
     const int seg = __builtin_amdgcn_readfirstlane(bx + v.nbx * (j + v.ny * k));
     const uint32_t base = row_ok ? gld(v.seg_base + seg) : 0u;
     return base + below;
+}
+
+// Curl component from two differences of neighbours: (a - b) - (c - d).
+template <typename T>
+__device__ __forceinline__ T dcurl(T a, T b, T c, T d) {
+    return (a - b) - (c - d);
 }
 
 // Faraday update with the semi-implicit loss of the layer
@@ -434,19 +444,42 @@ __device__ __forceinline__ void curl_h_body(const SimView<T>& v, const Geom& gm,
         // (all offsets are +1 along x, y or z: at most column nx, row ny,
         // plane nz of the extended range)
         T ex = ldo(Ex, x), ey = ldo(Ey, x);
+        // the x and y parts of the sites' layer-table entries stay fixed along
+        // the march in z (lay_coef_h: Hx at the integer x position and half
+        // y, z positions, and so on; the row j is wave-uniform)
+        uint32_t txy0 = 0u, txy1 = 0u, txy2 = 0u;
+        if (v.has_layer) {
+            const uint32_t tx0 = lay_part(v, 0, 0, i), tx1 = lay_part(v, 0, 1, i);
+            const int jw = __builtin_amdgcn_readfirstlane(j);
+            const uint32_t ty0 = lay_part(v, 1, 0, jw), ty1 = lay_part(v, 1, 1, jw);
+            txy0 = tx0 + ty1;
+            txy1 = tx1 + ty0;
+            txy2 = tx1 + ty1;
+        }
+        const LayC<T> hx0 = lay_coef(v.lc, txy0), hy0 = lay_coef(v.lc, txy1), hz0 = lay_coef(v.lc, txy2);
         HPlane<T> P, Q;
         load_hplane(P, f, v.mat, x, sx, sxy);
         for (int k = kz0; k < kz1; ++k, x += sxy) {
             if (k + 1 < kz1) load_hplane(Q, f, v.mat, x + sxy, sx, sxy);
             const T ez = P.ez;
             const T exk = P.exk, eyk = P.eyk;
-            const T cx = (P.ezy - ez) - (eyk - ey);
-            const T cy = (exk - ex) - (P.ezx - ez);
-            const T cz = (P.eyx - ey) - (P.exy - ex);
+            const T cx = dcurl(P.ezy, ez, eyk, ey);
+            const T cy = dcurl(exk, ex, P.ezx, ez);
+            const T cz = dcurl(P.eyx, ey, P.exy, ex);
             const T hx = P.hx, hy = P.hy, hz = P.hz;
-            const LayC<T> ax = lay_coef_h(v, 0, i, j, k);
-            const LayC<T> ay = lay_coef_h(v, 1, i, j, k);
-            const LayC<T> az = lay_coef_h(v, 2, i, j, k);
+            // planes outside the z layer (all but 2L of them) use the
+            // column's coefficients taken before the march
+            uint32_t tz0 = 0u, tz1 = 0u;
+            if (v.has_layer && (k < v.lay_kz[0] || k >= v.lay_kz[1])) {
+                tz0 = lay_part(v, 2, 0, k);
+                tz1 = lay_part(v, 2, 1, k);
+            }
+            LayC<T> ax = hx0, ay = hy0, az = hz0;
+            if (tz0 | tz1) {
+                ax = lay_coef(v.lc, txy0 + tz1);
+                ay = lay_coef(v.lc, txy1 + tz1);
+                az = lay_coef(v.lc, txy2 + tz0);
+            }
             const T nhx = h_update(hx, v.S, cx, ax);
             const T nhy = h_update(hy, v.S, cy, ay);
             const T nhz = h_update(hz, v.S, cz, az);
@@ -534,7 +567,12 @@ __device__ __forceinline__ T bloch_site(const SimView<T>& v, const Fields<T>& f,
         if (!v.frozen_pop) {
             const T n1 = b.n1, n2 = b.n2, n3 = b.n3;
             const T W = v.beta * ((T)0.5 * (en + e)) * dP;
-            const T n0 = v.Na - n1 - n2 - n3;
+            // N0 = N_a - N1 - N2 - N3, with N_a - N2 taken first: N2 holds
+            // nearly all atoms of a pumped site, that difference of nearly
+            // equal values is exact, and N0 keeps its full precision (taking
+            // N1 from N_a first would round at the scale of N_a, a relative
+            // error of order 1e-4 in N0, whose pump term sets N3's fixed point)
+            const T n0 = (v.Na - n2) - (n1 + n3);
             const T m2 = n2 + (v.dt32 * n3 - v.dt21 * n2) + W;
             const T m1 = n1 + (v.dt21 * n2 - v.dt10 * n1) - W;
             sto(f.n3[c], gi, n3 + (v.dtWp * n0 - v.dt32 * n3));
@@ -636,19 +674,18 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
         T hxm = kz0 >= 1 ? ldo(f.hn[0], x - sxy) : (T)0;
         T hym = kz0 >= 1 ? ldo(f.hn[1], x - sxy) : (T)0;
         // the x and y parts of the three sites' layer-table entries stay
-        // fixed along the march in z (lay_e: x at the half position for Ex,
-        // y at the half position for Ey; the row j is wave-uniform)
+        // fixed along the march in z (lay_coef_e: x at the half position for
+        // Ex, y at the half position for Ey; the row j is wave-uniform)
         uint32_t txy0 = 0u, txy1 = 0u, txy2 = 0u;
         if (v.has_layer) {
-            const uint32_t tx0 = (uint32_t)gld(v.lev[0][0] + i) * v.lc_sy;
-            const uint32_t tx1 = (uint32_t)gld(v.lev[0][1] + i) * v.lc_sy;
+            const uint32_t tx0 = lay_part(v, 0, 0, i), tx1 = lay_part(v, 0, 1, i);
             const int jw = __builtin_amdgcn_readfirstlane(j);
-            const uint32_t ty0 = (uint32_t)gld(v.lev[1][0] + jw) * v.lc_sz;
-            const uint32_t ty1 = (uint32_t)gld(v.lev[1][1] + jw) * v.lc_sz;
+            const uint32_t ty0 = lay_part(v, 1, 0, jw), ty1 = lay_part(v, 1, 1, jw);
             txy0 = tx1 + ty0;
             txy1 = tx0 + ty1;
             txy2 = tx0 + ty0;
         }
+        const LayC<T> h0 = lay_coef(v.lc, txy0), h1 = lay_coef(v.lc, txy1), h2 = lay_coef(v.lc, txy2);
         EPlane<T> P, Q;
         if constexpr (SPLIT) load_dense(P, f, x, sx, i, j);
         else load_plane(P, f, x, sx, gi, m >= kGainId, j >= 1 && kz0 >= 1, iny0 && kz0 >= 1, inz0, i, j);
@@ -680,35 +717,41 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             }
             T s0, s1, s2;
             source3(v, i, j, k, n, s0, s1, s2);
-            // table entries of the three sites (0 without a layer)
-            uint32_t tl0 = 0u, tl1 = 0u, tl2 = 0u;
-            if (v.has_layer) {
-                const uint32_t tz0 = gld(v.lev[2][0] + k), tz1 = gld(v.lev[2][1] + k);
-                tl0 = txy0 + tz0;
-                tl1 = txy1 + tz0;
-                tl2 = txy2 + tz1;
+            // the z parts of this plane (0 without a layer and between the z
+            // layers, where the column's coefficients taken before the march
+            // apply)
+            uint32_t tz0 = 0u, tz1 = 0u;
+            if (v.has_layer && (k < v.lay_kz[0] || k >= v.lay_kz[1])) {
+                tz0 = lay_part(v, 2, 0, k);
+                tz1 = lay_part(v, 2, 1, k);
+            }
+            LayC<T> l0 = h0, l1 = h1, l2 = h2;
+            if (tz0 | tz1) {
+                l0 = lay_coef(v.lc, txy0 + tz0);
+                l1 = lay_coef(v.lc, txy1 + tz0);
+                l2 = lay_coef(v.lc, txy2 + tz1);
             }
             T acc = (T)0;
             {
-                const T curl = inx ? (P.hz - P.hzy) - (P.hy - hym) : (T)0;
+                const T curl = inx ? dcurl(P.hz, P.hzy, P.hy, hym) : (T)0;
                 const T en = bloch_site(v, f, 0, gi, P.ex, curl, ie, inx, g && inx, P.b0, xi[0], s0,
-                                        lay_coef(v.lc, tl0), tslot);
+                                        l0, tslot);
                 sto(f.en[0], x, en);
                 if (tslot) sto(tslot, x, en);
                 if (inx) acc += en * en;
             }
             {
-                const T curl = iny ? (P.hx - hxm) - (P.hz - P.hzx) : (T)0;
+                const T curl = iny ? dcurl(P.hx, hxm, P.hz, P.hzx) : (T)0;
                 const T en = bloch_site(v, f, 1, gi, P.ey, curl, ie, iny, g && iny, P.b1, xi[1], s1,
-                                        lay_coef(v.lc, tl1), tslot);
+                                        l1, tslot);
                 sto(f.en[1], x, en);
                 if (tslot) sto(tslot + v.tap_e, x, en);
                 if (iny) acc += en * en;
             }
             {
-                const T curl = inz ? (P.hy - P.hyx) - (P.hx - P.hxy) : (T)0;
+                const T curl = inz ? dcurl(P.hy, P.hyx, P.hx, P.hxy) : (T)0;
                 const T en = bloch_site(v, f, 2, gi, P.ez, curl, ie, inz, g && inz, P.b2, xi[2], s2,
-                                        lay_coef(v.lc, tl2), tslot);
+                                        l2, tslot);
                 sto(f.en[2], x, en);
                 if (tslot) sto(tslot + 2 * v.tap_e, x, en);
                 if (inz) acc += en * en;
@@ -796,10 +839,10 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
         if (kz0 >= 1) {
             const uint32_t xp = x - sxy;
             const T ezp = ldo(Ez, xp), eyp = ldo(Ey, xp), exp_ = ldo(Ex, xp);
-            const T cx = (ldo(Ez, xp + sx) - ezp) - (ey - eyp);
-            const T cy = (ex - exp_) - (ldo(Ez, xp + 1u) - ezp);
-            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay_coef_h(v, 0, i, j, kz0 - 1));
-            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay_coef_h(v, 1, i, j, kz0 - 1));
+            const T cx = dcurl(ldo(Ez, xp + sx), ezp, ey, eyp);
+            const T cy = dcurl(ex, exp_, ldo(Ez, xp + 1u), ezp);
+            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay_coef_h(v, 0, ic, j, kz0 - 1));
+            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay_coef_h(v, 1, ic, j, kz0 - 1));
         }
         for (int k = kz0; k < kz1; ++k, x += sxy) {
             const uint8_t m = m_next;
@@ -814,12 +857,12 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             const T ez = ldo(Ez, x);
             const T exk = ldo(Ex, x + sxy), eyk = ldo(Ey, x + sxy);
             const T hx = ldo(Hx0, x), hy = ldo(Hy0, x), hz = ldo(Hz0, x);
-            const T cx = (ldo(Ez, x + sx) - ez) - (eyk - ey);
-            const T cy = (exk - ex) - (ldo(Ez, x + 1u) - ez);
-            const T cz = (ldo(Ey, x + 1u) - ey) - (ldo(Ex, x + sx) - ex);
-            const LayC<T> ax = lay_coef_h(v, 0, i, j, k);
-            const LayC<T> ay = lay_coef_h(v, 1, i, j, k);
-            const LayC<T> az = lay_coef_h(v, 2, i, j, k);
+            const T cx = dcurl(ldo(Ez, x + sx), ez, eyk, ey);
+            const T cy = dcurl(exk, ex, ldo(Ez, x + 1u), ez);
+            const T cz = dcurl(ldo(Ey, x + 1u), ey, ldo(Ex, x + sx), ex);
+            const LayC<T> ax = lay_coef_h(v, 0, ic, j, k);
+            const LayC<T> ay = lay_coef_h(v, 1, ic, j, k);
+            const LayC<T> az = lay_coef_h(v, 2, ic, j, k);
             const T nhx = h_update(hx, v.S, cx, ax);
             const T nhy = h_update(hy, v.S, cy, ay);
             const T nhz = h_update(hz, v.S, cz, az);
@@ -844,10 +887,10 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 const uint32_t xm = x - sx;
                 const T ezm = ldo(Ez, xm), exm = ldo(Ex, xm);
                 eymk = ldo(Ey, xm + sxy);
-                const T cxm = (ez - ezm) - (eymk - eym);
-                const T czm = (ldo(Ey, xm + 1u) - eym) - (ex - exm);
-                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay_coef_h(v, 0, i, j - 1, k));
-                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay_coef_h(v, 2, i, j - 1, k));
+                const T cxm = dcurl(ez, ezm, eymk, eym);
+                const T czm = dcurl(ldo(Ey, xm + 1u), eym, ex, exm);
+                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay_coef_h(v, 0, ic, j - 1, k));
+                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay_coef_h(v, 2, ic, j - 1, k));
             }
             // ---- Hy, Hz at x-1 of the own row
             T nhy_l = __shfl_up(nhy, 1, 64);
@@ -855,8 +898,8 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
             if (edge) {
                 const uint32_t xl = x - 1u;
                 const T exl = ldo(Ex, xl), eyl = ldo(Ey, xl), ezl = ldo(Ez, xl);
-                const T cyl = (ldo(Ex, xl + sxy) - exl) - (ez - ezl);
-                const T czl = (ey - eyl) - (ldo(Ex, xl + sx) - exl);
+                const T cyl = dcurl(ldo(Ex, xl + sxy), exl, ez, ezl);
+                const T czl = dcurl(ey, eyl, ldo(Ex, xl + sx), exl);
                 nhy_l = h_update(ldo(Hy0, xl), v.S, cyl, lay_coef_h(v, 1, i - 1, j, k));
                 nhz_l = h_update(ldo(Hz0, xl), v.S, czl, lay_coef_h(v, 2, i - 1, j, k));
             }
@@ -872,7 +915,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                 source3(v, i, j, k, n, s0, s1, s2);
                 T acc = (T)0;
                 {
-                    const T curl = inx ? (nhz - nhz_m) - (nhy - hyp) : (T)0;
+                    const T curl = inx ? dcurl(nhz, nhz_m, nhy, hyp) : (T)0;
                     const T en = bloch_site(v, f, 0, gi, ex, curl, ie, inx, g && inx, b0, xi[0], s0,
                                             lay_coef_e(v, 0, i, j, k), tslot);
                     sto(f.en[0], x, en);
@@ -880,7 +923,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                     if (inx) acc += en * en;
                 }
                 {
-                    const T curl = iny ? (nhx - hxp) - (nhz - nhz_l) : (T)0;
+                    const T curl = iny ? dcurl(nhx, hxp, nhz, nhz_l) : (T)0;
                     const T en = bloch_site(v, f, 1, gi, ey, curl, ie, iny, g && iny, b1, xi[1], s1,
                                             lay_coef_e(v, 1, i, j, k), tslot);
                     sto(f.en[1], x, en);
@@ -888,7 +931,7 @@ __device__ __forceinline__ void step_fused_body(const SimView<T>& v, const Geom&
                     if (iny) acc += en * en;
                 }
                 {
-                    const T curl = inz ? (nhy - nhy_l) - (nhx - nhx_m) : (T)0;
+                    const T curl = inz ? dcurl(nhy, nhy_l, nhx, nhx_m) : (T)0;
                     const T en = bloch_site(v, f, 2, gi, ez, curl, ie, inz, g && inz, b2, xi[2], s2,
                                             lay_coef_e(v, 2, i, j, k), tslot);
                     sto(f.en[2], x, en);
@@ -927,6 +970,226 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused_batch(const SimView<T>* 
     step_fused_body<T, TY>(views[r], geoms[r], w);
 }
 
+
+// ------------------------------------- fused step with LDS row exchange
+// One pass over the fields per step (rows a1 to a5): H^{n+1/2} is formed,
+// stored and handed to the E update of the same plane without being read back
+// from memory.  A workgroup owns a tile of 64 x TY columns (one wave per row)
+// and marches its waves together through a z segment, one barrier per plane:
+//   before the barrier every wave forms H^{n+1/2}(k) of its row (its E^n(k+1)
+//   loaded, E^n(k) carried from the previous plane, the +x and +y neighbours
+//   read directly), stores it and puts Hx, Hz in LDS (double-buffered by the
+//   plane's parity, so one barrier per plane suffices);
+//   after it every wave updates E, P and the populations of its row at plane
+//   k, taking Hx, Hz of row j-1 from LDS, Hy, Hz at x-1 from the next lower
+//   lane and H^{n+1/2}(k-1) of its own row from registers.
+// Values owned by another workgroup are formed again with their owner's
+// expression: wave 0 forms Hx, Hz of row j0-1, lane 0 of every wave Hy, Hz of
+// column i0-1, and a segment that does not start at z = 0 first forms Hx, Hy
+// of plane z0-1; so every variant gives bitwise identical fields.
+template <typename T, int TY>
+__device__ __forceinline__ void step_lds_body(const SimView<T>& v, const Geom& gm, int w) {
+    __shared__ double sh[TY];
+    __shared__ T s_ie[kMaxMat], s_eps[kMaxMat];
+    __shared__ T s_hx[2][TY][64], s_hz[2][TY][64];
+    for (int q = (int)(threadIdx.x + 64 * threadIdx.y); q < kMaxMat; q += 64 * TY) {
+        s_ie[q] = gld(v.lut_inv_eps + q);
+        s_eps[q] = gld(v.lut_eps + q);
+    }
+    __syncthreads();
+    int bx, by, bz;
+    decode_item(gm, w, bx, by, bz);
+    const int lane = (int)threadIdx.x, ty = (int)threadIdx.y;
+    const int i = bx * 64 + lane;
+    const int j = by * TY + ty;
+    const int64_t n = gld(&v.ctl->step);
+    const Fields<T> f = bind_fields(v, (int)(n & 1));
+    T* const tslot = tap_slot(v, n);
+    T wsum = (T)0;
+    double lsum = 0.0;
+    const int kz0 = bz * gm.zseg, kz1 = min(kz0 + gm.zseg, v.nz);
+    const bool row = j < v.ny;                        // wave-uniform
+    const bool act = row && i < v.nx;
+    const int ic = i < v.nx ? i : v.nx;               // lanes past the grid read a valid site
+    const uint32_t sx = (uint32_t)v.sx, sxy = (uint32_t)v.sxy;
+    const T* __restrict__ Ex = f.e[0];
+    const T* __restrict__ Ey = f.e[1];
+    const T* __restrict__ Ez = f.e[2];
+    const T* __restrict__ Hx0 = f.h[0];
+    const T* __restrict__ Hy0 = f.h[1];
+    const T* __restrict__ Hz0 = f.h[2];
+    const bool halo_row = ty == 0 && j >= 1;          // wave 0 forms row j0-1 (wave-uniform)
+    const bool halo_col = lane == 0 && i >= 1;        // lane 0 forms column i0-1
+    uint32_t x = (uint32_t)ic + sx * (uint32_t)(row ? j : 0) + sxy * (uint32_t)kz0;
+    uint8_t m_next = 0;
+    uint32_t gi_next = 0;
+    T ex = (T)0, ey = (T)0, ez = (T)0;                // E^n(k) of the row, carried along z
+    T eym = (T)0;                                     // Ey^n(k) of row j0-1 (wave 0)
+    T exl = (T)0;                                     // Ex^n(k) of column i0-1 (lane 0)
+    T hxp = (T)0, hyp = (T)0;                         // H^{n+1/2}(k-1) of the row
+    if (row) {
+        m_next = ldo(v.mat, x);
+        gi_next = gain_index(v, bx, j, kz0, act && m_next >= kGainId, true);
+        ex = ldo(Ex, x);
+        ey = ldo(Ey, x);
+        ez = ldo(Ez, x);
+        if (halo_row) eym = ldo(Ey, x - sx);
+        if (halo_col) exl = ldo(Ex, x - 1u);
+        if (kz0 >= 1) {                               // H^{n+1/2}(z0-1) of the row, formed again
+            const uint32_t xp = x - sxy;
+            const T ezp = ldo(Ez, xp), eyp = ldo(Ey, xp), exp_ = ldo(Ex, xp);
+            const T cx = dcurl(ldo(Ez, xp + sx), ezp, ey, eyp);
+            const T cy = dcurl(ex, exp_, ldo(Ez, xp + 1u), ezp);
+            hxp = h_update(ldo(Hx0, xp), v.S, cx, lay_coef_h(v, 0, ic, j, kz0 - 1));
+            hyp = h_update(ldo(Hy0, xp), v.S, cy, lay_coef_h(v, 1, ic, j, kz0 - 1));
+        }
+    }
+    for (int k = kz0; k < kz1; ++k, x += sxy) {
+        const int buf = k & 1;
+        uint8_t m = 0;
+        uint32_t gi = 0;
+        T nhx = (T)0, nhy = (T)0, nhz = (T)0;         // H^{n+1/2}(k) of the row
+        T nhx_m = (T)0, nhz_m = (T)0;                 // Hx, Hz of row j0-1 (wave 0)
+        T nhy_l = (T)0, nhz_l = (T)0;                 // Hy, Hz of column i0-1 (lane 0)
+        T exk = (T)0, eyk = (T)0, ezk = (T)0;         // E^n(k+1) of the row
+        T eymk = (T)0, exlk = (T)0;
+        BlochIn<T> b0{}, b1{}, b2{};
+        bool g = false;
+        const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
+        if (row) {
+            m = m_next;
+            gi = gi_next;
+            if (k + 1 < kz1) m_next = ldo(v.mat, x + sxy);
+            g = act && m >= kGainId;
+            b0 = bloch_load(f, 0, gi, g && inx);
+            b1 = bloch_load(f, 1, gi, g && iny);
+            b2 = bloch_load(f, 2, gi, g && inz);
+            // ---- a1 on the own row (the H pass's expressions)
+            exk = ldo(Ex, x + sxy);
+            eyk = ldo(Ey, x + sxy);
+            ezk = ldo(Ez, x + sxy);
+            const T hx = ldo(Hx0, x), hy = ldo(Hy0, x), hz = ldo(Hz0, x);
+            const T cx = dcurl(ldo(Ez, x + sx), ez, eyk, ey);
+            const T cy = dcurl(exk, ex, ldo(Ez, x + 1u), ez);
+            const T cz = dcurl(ldo(Ey, x + 1u), ey, ldo(Ex, x + sx), ex);
+            nhx = h_update(hx, v.S, cx, lay_coef_h(v, 0, ic, j, k));
+            nhy = h_update(hy, v.S, cy, lay_coef_h(v, 1, ic, j, k));
+            nhz = h_update(hz, v.S, cz, lay_coef_h(v, 2, ic, j, k));
+            s_hx[buf][ty][lane] = nhx;
+            s_hz[buf][ty][lane] = nhz;
+            if (act) {
+                sto_nt(f.hn[0], x, nhx);
+                sto_nt(f.hn[1], x, nhy);
+                sto_nt(f.hn[2], x, nhz);
+                const T eps = s_eps[m];
+                if (v.map != nullptr && k == v.map_k) plane_energy(v, i, j, eps, ex, ey, ez, nhx, nhy, nhz);
+                T acc = (T)0;
+                if (j >= 1 && k >= 1) acc += eps * ex * ex;
+                if (i >= 1 && k >= 1) acc += eps * ey * ey;
+                if (i >= 1 && j >= 1) acc += eps * ez * ez;
+                if (i >= 1) acc += hx * nhx;
+                if (j >= 1) acc += hy * nhy;
+                if (k >= 1) acc += hz * nhz;
+                wsum += (T)0.5 * acc;
+            }
+            // ---- Hx, Hz of row j0-1 (its owner's expressions)
+            if (halo_row) {
+                const uint32_t xm = x - sx;
+                const T ezm = ldo(Ez, xm), exm = ldo(Ex, xm);
+                eymk = ldo(Ey, xm + sxy);
+                const T cxm = dcurl(ez, ezm, eymk, eym);
+                const T czm = dcurl(ldo(Ey, xm + 1u), eym, ex, exm);
+                nhx_m = h_update(ldo(Hx0, xm), v.S, cxm, lay_coef_h(v, 0, ic, j - 1, k));
+                nhz_m = h_update(ldo(Hz0, xm), v.S, czm, lay_coef_h(v, 2, ic, j - 1, k));
+            }
+            // ---- Hy, Hz of column i0-1
+            if (halo_col) {
+                const uint32_t xl = x - 1u;
+                const T ezl = ldo(Ez, xl), eyl = ldo(Ey, xl);
+                exlk = ldo(Ex, xl + sxy);
+                const T cyl = dcurl(exlk, exl, ez, ezl);
+                const T czl = dcurl(ey, eyl, ldo(Ex, xl + sx), exl);
+                nhy_l = h_update(ldo(Hy0, xl), v.S, cyl, lay_coef_h(v, 1, i - 1, j, k));
+                nhz_l = h_update(ldo(Hz0, xl), v.S, czl, lay_coef_h(v, 2, i - 1, j, k));
+            }
+        }
+        __syncthreads();
+        // ---- a2-a5 on the own row
+        if (row) {
+            const T hx_jm = ty >= 1 ? s_hx[buf][ty >= 1 ? ty - 1 : 0][lane] : nhx_m;
+            const T hz_jm = ty >= 1 ? s_hz[buf][ty >= 1 ? ty - 1 : 0][lane] : nhz_m;
+            T hy_im = __shfl_up(nhy, 1, 64);
+            T hz_im = __shfl_up(nhz, 1, 64);
+            if (lane == 0) {
+                hy_im = nhy_l;
+                hz_im = nhz_l;
+            }
+            if (act) {
+                const T ie = s_ie[m];
+                T xi[3] = {(T)0, (T)0, (T)0};
+                if (g && v.noise && (inx || iny || inz)) {
+                    const uint32_t cell = (uint32_t)(i + v.nx * (j + v.ny * k));
+                    noise3(v, cell, (uint32_t)n, xi);
+                }
+                T s0, s1, s2;
+                source3(v, i, j, k, n, s0, s1, s2);
+                T acc = (T)0;
+                {
+                    const T curl = inx ? dcurl(nhz, hz_jm, nhy, hyp) : (T)0;
+                    const T en = bloch_site(v, f, 0, gi, ex, curl, ie, inx, g && inx, b0, xi[0], s0,
+                                            lay_coef_e(v, 0, i, j, k), tslot);
+                    sto(f.en[0], x, en);
+                    if (tslot) sto(tslot, x, en);
+                    if (inx) acc += en * en;
+                }
+                {
+                    const T curl = iny ? dcurl(nhx, hxp, nhz, hz_im) : (T)0;
+                    const T en = bloch_site(v, f, 1, gi, ey, curl, ie, iny, g && iny, b1, xi[1], s1,
+                                            lay_coef_e(v, 1, i, j, k), tslot);
+                    sto(f.en[1], x, en);
+                    if (tslot) sto(tslot + v.tap_e, x, en);
+                    if (iny) acc += en * en;
+                }
+                {
+                    const T curl = inz ? dcurl(nhy, hy_im, nhx, hx_jm) : (T)0;
+                    const T en = bloch_site(v, f, 2, gi, ez, curl, ie, inz, g && inz, b2, xi[2], s2,
+                                            lay_coef_e(v, 2, i, j, k), tslot);
+                    sto(f.en[2], x, en);
+                    if (tslot) sto(tslot + 2 * v.tap_e, x, en);
+                    if (inz) acc += en * en;
+                }
+                if (v.box_on && i >= v.box[0] && i < v.box[3] && j >= v.box[1] && j < v.box[4] &&
+                    k >= v.box[2] && k < v.box[5])
+                    lsum += (double)acc;
+            }
+            hxp = nhx;
+            hyp = nhy;
+            ex = exk;
+            ey = eyk;
+            ez = ezk;
+            eym = eymk;
+            exl = exlk;
+            if (k + 1 < kz1) gi_next = gain_index(v, bx, j, k + 1, act && m_next >= kGainId, true);
+        }
+    }
+    const double ws = block_sum((double)wsum, sh);
+    __syncthreads();
+    const double ls = v.box_on ? block_sum(lsum, sh) : 0.0;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        sto(v.e_part, (uint32_t)w, ws);
+        if (v.box_on) sto(v.l_part, (uint32_t)w, ls);
+    }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step_lds_batch(const SimView<T>* __restrict__ views,
+                                                          const Geom* __restrict__ geoms,
+                                                          const uint32_t* __restrict__ items, int nitems,
+                                                          int remap) {
+    int r, w;
+    batch_item(items, nitems, remap, r, w);
+    step_lds_body<T, TY>(views[r], geoms[r], w);
+}
 
 // ---------------------------------------------------------------- row a6
 // First-order Mur on the wall E-sites of Mur axes.  Task (a, side, c) covers

@@ -238,4 +238,52 @@ __global__ void __launch_bounds__(kStatThreads) k_spec_peaks(const double* __res
     if (t == 0) *count = found;
 }
 
+// ---------------------------------------------------------------- threshold
+// Growth rate of one run of a pump sweep (one workgroup per run): the
+// least-squares slope of ln W^n against n over n0 <= n < n1, formed about the
+// window's centre nc = (n0 + n1 - 1)/2, where sum (n - nc) = 0:
+//   rate = sum (n - nc) ln W^n / sum (n - nc)^2,
+// the denominator in closed form, m (m^2 - 1) / 12 for m = n1 - n0 steps.  A
+// non-positive W gives NaN.
+__global__ void __launch_bounds__(kStatThreads) k_growth_rate(const double* const* __restrict__ hist, int64_t n0,
+                                                            int64_t n1, double* __restrict__ rates) {
+    __shared__ double sh[kStatThreads / 64];
+    const double* __restrict__ w = hist[blockIdx.x];
+    const double nc = 0.5 * (double)(n0 + n1 - 1);
+    double s = 0.0;
+    for (int64_t n = n0 + (int64_t)threadIdx.x; n < n1; n += kStatThreads) {
+        const double x = w[n];
+        s += ((double)n - nc) * (x > 0.0 ? log(x) : __builtin_nan(""));
+    }
+    s = stat_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const double m = (double)(n1 - n0);
+        rates[blockIdx.x] = s / (m * (m * m - 1.0) / 12.0);
+    }
+}
+
+// The least-squares line rate = a + b N_a through a sweep of R runs and its
+// root N_th = -a/b (one thread; R is small): fit = (a, b, N_th).
+__global__ void k_threshold_line(const double* __restrict__ Na, const double* __restrict__ rates, int R,
+                                 double* __restrict__ fit) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double mx = 0.0, my = 0.0;
+    for (int r = 0; r < R; ++r) {
+        mx += Na[r];
+        my += rates[r];
+    }
+    mx /= R;
+    my /= R;
+    double sxy = 0.0, sxx = 0.0;
+    for (int r = 0; r < R; ++r) {
+        sxy += (Na[r] - mx) * (rates[r] - my);
+        sxx += (Na[r] - mx) * (Na[r] - mx);
+    }
+    const double b = sxy / sxx;
+    const double a = my - b * mx;
+    fit[0] = a;
+    fit[1] = b;
+    fit[2] = -a / b;
+}
+
 }  // namespace mbf

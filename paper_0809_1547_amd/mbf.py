@@ -75,9 +75,9 @@ class mbf_spec_stats(C.Structure):
                 ("fit_ok", C.c_int32)]
 
 
-MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED, MBF_VARIANT_TWO_PASS_SPLIT = 0, 1, 2
+MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED_LDS = 0, 1, 2, 3
 _VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED,
-             "two_pass_split": MBF_VARIANT_TWO_PASS_SPLIT}
+             "two_pass_split": MBF_VARIANT_TWO_PASS_SPLIT, "fused_lds": MBF_VARIANT_FUSED_LDS}
 
 
 def _load():
@@ -150,6 +150,9 @@ def _load():
         "mbf_gp_eigenvalue": (D, [D, D]),
         "mbf_gp_threshold": (D, [D]),
         "mbf_pack_md": (I, [I, dp, VP, VP, C.POINTER(mbf_pack_params), I, VP, dp, dp]),
+        "mbf_kappa_fit": (I, [dp, dp, I, D, D, I, D, I, D, VP, dp, dp]),
+        "mbf_growth_threshold": (I, [VP, I, I64, I64, I64, dp, I, VP, dp, dp]),
+        "mbf_batch_growth_threshold": (I, [P, I64, I64, dp, dp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -173,6 +176,7 @@ EXPORTED = [
     "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
     "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor", "mbf_gp_solve",
     "mbf_gp_eigenvalue", "mbf_gp_threshold", "mbf_pack_md", "mbf_spectral_stats_noalloc",
+    "mbf_kappa_fit", "mbf_growth_threshold", "mbf_batch_growth_threshold",
 ]
 
 
@@ -407,6 +411,40 @@ def mbf_gp_solve(E, M: int = 1023, L: float = 12.0, n_nu: int = 512, dnu: float 
     for q, name in enumerate(GP_STATS):
         out[name] = st[:, q]
     return out
+
+
+def mbf_kappa_fit(Na, W, N_th: float, t_g: float, M: int = 1023, L: float = 14.0, n_nu: int = 512,
+                  dnu: float = 0.02, stream: Optional[int] = None):
+    """(kappa, model waists) of the ST-law linewidth fit to waists W (Hz) at
+    pump levels Na (m^-3, above N_th)."""
+    Na = np.ascontiguousarray(np.atleast_1d(Na), dtype=np.float64)
+    W = np.ascontiguousarray(np.atleast_1d(W), dtype=np.float64)
+    if Na.shape != W.shape:
+        raise ValueError("Na and W must have the same length")
+    k = C.c_double()
+    Wf = np.zeros_like(W)
+    _check(lib.mbf_kappa_fit(Na.ctypes.data_as(C.POINTER(C.c_double)), W.ctypes.data_as(C.POINTER(C.c_double)),
+                             Na.shape[0], float(N_th), float(t_g), int(M), float(L), int(n_nu), float(dnu),
+                             C.c_void_p(stream or 0), C.byref(k), Wf.ctypes.data_as(C.POINTER(C.c_double))))
+    return k.value, Wf
+
+
+def mbf_growth_threshold(hist, Na, n0: int, n1: int, stream: Optional[int] = None):
+    """(rates, (a, b, N_th)) of energy histories hist (n_runs, stride): numpy
+    or a device tensor (float64, contiguous); Na host values (m^-3)."""
+    if isinstance(hist, np.ndarray):
+        hist = np.ascontiguousarray(hist, dtype=np.float64)
+    if len(hist.shape) != 2:
+        raise ValueError("hist must be (n_runs, stride)")
+    ph, kh, _keep = _ptr_kind(hist)
+    Na = np.ascontiguousarray(np.atleast_1d(Na), dtype=np.float64)
+    rates = np.zeros(hist.shape[0])
+    fit = np.zeros(3)
+    _check(lib.mbf_growth_threshold(ph, hist.shape[0], hist.shape[1], int(n0), int(n1),
+                                    Na.ctypes.data_as(C.POINTER(C.c_double)), kh, C.c_void_p(stream or 0),
+                                    rates.ctypes.data_as(C.POINTER(C.c_double)),
+                                    fit.ctypes.data_as(C.POINTER(C.c_double))))
+    return rates, tuple(fit)
 
 
 def mbf_pack_md(box, diam, centres, *, s0: float = 0.5, stages: int = 100, iters: int = 20,
@@ -788,6 +826,15 @@ class Batch:
     def spectrum_stats(self, level=0.5):
         """spectrum_stats of every member, in member order."""
         return mbf_batch_spectrum_stats(self.b, level)
+
+    def growth_threshold(self, n0, n1):
+        """(rates, (a, b, N_th)) over the members' energy histories."""
+        rates = np.zeros(len(self.members))
+        fit = np.zeros(3)
+        _bcheck(lib.mbf_batch_growth_threshold(self.b, int(n0), int(n1),
+                                               rates.ctypes.data_as(C.POINTER(C.c_double)),
+                                               fit.ctypes.data_as(C.POINTER(C.c_double))), self.b)
+        return rates, tuple(fit)
 
     def close(self):
         if getattr(self, "b", None):

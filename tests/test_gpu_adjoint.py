@@ -84,7 +84,7 @@ def test_checkpoint_interval_does_not_change_the_gradient_and_run_ends_at_nsteps
     mbf = _mbf()
     eps, gain = _material((40, 36, 28), seed=3, fill=0.4)
     out = []
-    for K, var in ((90, None), (7, None), (32, None), (32, "two_pass_split"), (7, "fused")):
+    for K, var in ((90, None), (7, None), (32, None), (32, "two_pass_split"), (7, "fused"), (9, "fused_lds")):
         sim = mbf.Sim((40, 36, 28), boundary="absorb", seed=9, realization=3, E_sp=1e-3)
         if var:
             sim.set_tuning(var, tile_y=4, zseg=2, xcd_remap=2)
@@ -100,12 +100,17 @@ def test_checkpoint_interval_does_not_change_the_gradient_and_run_ends_at_nsteps
     ref.set_source(2, 20, 18, 14, amp=0.2)
     ref.set_loss_box((10, 10, 8), (30, 26, 20))
     ref.step(90)
+    # the fields, the eps gradient (summed per cell in step order) and the N_a
+    # gradient (the reverse steps' own work items) are the same bit for bit;
+    # the loss is a sum of per-work-item partials of the forward kernels, so
+    # its last bits follow the schedule's partition of the grid
     for L, g, gna, step, fields in out:
-        assert L == out[0][0] and gna == out[0][2] and np.array_equal(g, out[0][1])
+        assert L == pytest.approx(out[0][0], rel=1e-14)
+        assert gna == out[0][2] and np.array_equal(g, out[0][1])
         assert step == 90
         for a, b in zip(fields, [ref.field(f) for f in range(21)]):
             assert np.array_equal(a, b)
-    assert L == ref.loss()
+    assert out[0][0] == ref.loss()
 
 
 def test_adjoint_errors():
@@ -147,27 +152,31 @@ def test_c4_adjoint_against_fp64_differences():
     import time
     eps, gain = I.voxelize(I.packing_for("c4", 96, 0))
     nsteps = 1000
-    # cost: the better of two runs each (a fresh handle per adjoint run, since
-    # the run must start from the pump)
-    t_adj = t_fwd = float("inf")
-    for _ in range(2):
+    # cost: three pairs of a fresh adjoint run (it must start from the pump)
+    # and a fresh forward run of the same steps, after one warm-up pair; the
+    # median ratio of reverse sweep to forward must stay within 3
+    ratios = []
+    for it in range(4):
         sim = _c4_sim("fp32", eps, gain)
         sim.sync()
         t0 = time.perf_counter()
         L, g, gna = sim.adjoint_run(nsteps, K=50)
-        t_adj = min(t_adj, time.perf_counter() - t0)
+        t_adj = time.perf_counter() - t0
         sim.close()
-    sim = _c4_sim("fp32", eps, gain)
-    sim.step(8)
-    for _ in range(2):
+        sim = _c4_sim("fp32", eps, gain)
+        sim.step(8)
         sim.sync()
         t0 = time.perf_counter()
         sim.step(nsteps)
         sim.sync()
-        t_fwd = min(t_fwd, time.perf_counter() - t0)
-    sim.close()
+        t_fwd = time.perf_counter() - t0
+        sim.close()
+        if it:
+            ratios.append((t_adj - t_fwd) / t_fwd)
+    med = float(np.median(ratios))
     print(f"C4: forward {t_fwd * 1e3:.1f} ms, forward+adjoint {t_adj * 1e3:.1f} ms, "
-          f"reverse sweep / forward = {(t_adj - t_fwd) / t_fwd:.2f}")
+          f"reverse sweep / forward = {['%.2f' % r for r in ratios]} (median {med:.2f})")
+    assert med <= 3.0
     rng = np.random.default_rng(0)
     cells = []
     while len(cells) < 20:
@@ -216,6 +225,31 @@ def test_torch_autograd_binding():
     sim.set_source(*SRC, amp=0.3)
     sim.set_loss_box(*BOX)
     L2, g2, gna2 = sim.adjoint_run(40, K=9)
-    assert float(L) == L2
+    assert L.item() == L2
     assert np.array_equal(e.grad.numpy(), g2.astype(np.float32))
-    assert float(Na.grad) == gna2
+    assert Na.grad.item() == gna2
+
+
+def test_torch_autograd_binding_on_device():
+    # eps as a device tensor: the library reads it and writes the gradient
+    # through device pointers on torch's current stream (a side stream here);
+    # the result equals the host path's bit for bit
+    import torch
+    from paper_0809_1547_amd.autograd import loss_box_objective
+    eps, gain = _material()
+    setup = dict(n=N, gain=gain, box=BOX, nsteps=40, K=9, init="prepumped", source=(*SRC, 0.3),
+                 precision="fp64", seed=3, realization=1, E_sp=1e-2)
+    eh = torch.tensor(eps, requires_grad=True)
+    Nh = torch.tensor(2e24, dtype=torch.float64, requires_grad=True)
+    Lh = loss_box_objective(eh, Nh, setup)
+    Lh.backward()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ed = torch.tensor(eps, device="cuda", requires_grad=True)
+        Nd = torch.tensor(2e24, dtype=torch.float64, requires_grad=True)
+        Ld = loss_box_objective(ed, Nd, setup)
+        Ld.backward()
+    st.synchronize()
+    assert ed.grad.is_cuda and ed.grad.dtype == ed.dtype
+    assert float(Ld) == float(Lh) and float(Nd.grad) == float(Nh.grad)
+    assert np.array_equal(ed.grad.cpu().numpy(), eh.grad.numpy())

@@ -54,7 +54,8 @@ def _snapshot(sim, probes):
 
 @pytest.mark.parametrize("variant,group_mb,remap", [("two_pass", 0, 2), ("fused", 0, 2), ("two_pass", 1, 2),
                                                      ("fused", 2, 1), ("two_pass", 0, 0), ("two_pass_split", 0, 2),
-                                                     ("two_pass_split", 1, 1)])
+                                                     ("two_pass_split", 1, 1), ("fused_lds", 0, 2),
+                                                     ("fused_lds", 1, 1)])
 def test_batch_members_equal_solo_runs(variant, group_mb, remap):
     # group_mb 1 and 2 split the members into groups that run whole graph
     # chunks one after the other
@@ -202,3 +203,50 @@ def test_default_schedule_follows_grid_size():
     assert b.tuning()["variant"] == "two_pass_split" and all(b[r].tuning()["variant"] == "two_pass_split"
                                                                for r in range(3))
     b.close()
+
+
+def test_autotune_choice_is_persisted(tmp_path, monkeypatch):
+    # with MBF_TUNE_CACHE set, the first autotune of a shape times the
+    # candidates and appends its choice; a second handle of the same shape
+    # (and architecture, precision, walls) takes it from the file without
+    # timing; another shape gets a line of its own; batches likewise
+    mbf = _mbf()
+    cache = tmp_path / "tuning.txt"
+    monkeypatch.setenv("MBF_TUNE_CACHE", str(cache))
+
+    def sim(n):
+        s = mbf.Sim(n, boundary="absorb")
+        eps, gain = I.voxelize(I.rsa_pack(n, seed=3, fill=0.3))
+        s.set_material(eps, gain)
+        s.set_pump(2e24)
+        return s
+    a = sim((40, 36, 28))
+    ta = a.autotune(budget_ms=200)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and "40x36x28" in lines[0] and "single" in lines[0]
+    # plant another schedule for this key: the next handle must take it
+    planted = {**ta, "variant": "fused" if ta["variant"] != "fused" else "two_pass", "tile_y": 8, "zseg": 3}
+    vid = {"two_pass": 0, "fused": 1, "two_pass_split": 2, "fused_lds": 3}[planted["variant"]]
+    key = lines[0].split("\t")[0]
+    with open(cache, "a") as f:
+        f.write(f"{key}\t{vid} 8 3 {ta['xcd_remap']} {ta['group_mb']}\n")
+    b = sim((40, 36, 28))
+    tb = b.autotune(budget_ms=200)
+    assert (tb["variant"], tb["tile_y"], tb["zseg"]) == (planted["variant"], 8, 3)
+    assert len(cache.read_text().splitlines()) == 2               # nothing timed, nothing added
+    c = sim((36, 36, 28))
+    c.autotune(budget_ms=200)
+    assert len(cache.read_text().splitlines()) == 3
+    for s in (a, b, c):
+        s.close()
+    cfgs = [mbf.make_config(n, boundary="absorb") for n in ((24, 20, 16), (32, 20, 16))]
+    bt = mbf.Batch(cfgs)
+    for r, s in enumerate(bt.members):
+        eps, gain = I.voxelize(I.rsa_pack(s.n, seed=r, fill=0.3))
+        s.set_material(eps, gain)
+        s.set_pump(2e24)
+    t1 = bt.autotune(budget_ms=200)
+    assert len(cache.read_text().splitlines()) == 4 and "batch" in cache.read_text().splitlines()[-1]
+    assert bt.autotune(budget_ms=200) == t1
+    assert len(cache.read_text().splitlines()) == 4
+    bt.close()
