@@ -46,6 +46,10 @@ MUTATIONS = [
     ("rate_work_factor_only", "double W = c[ORC_C_BETA] * Ebar * dP;", "double W = 0.5 * c[ORC_C_BETA] * Ebar * dP;"),
     ("layer_loss_sign", "s->Hn[c][x] = layer_ca(s, a) * H3[c][x]", "s->Hn[c][x] = layer_ca(s, -a) * H3[c][x]"),
     ("layer_e_scale", "layer_cb(s, a) * (ie * (S * curl - dP));", "(ie * (S * curl - dP));"),
+    ("layer_h_half_position", "const int half = is_h ? (ax != c) : (ax == c);",
+     "const int half = is_h ? (ax == c) : (ax == c);"),
+    ("layer_high_side_grading", "if (x > n - L) v += pow((x - (n - L)) / L, (double)s->p.absorb_order);",
+     "if (x > n - L) v += pow((n - x) / L, (double)s->p.absorb_order);"),
     ("prepump_fixed_point", "N[2] = rnd(s, dwp * n0 / d21);", "N[2] = rnd(s, dwp * n0 / d32);"),
     ("adjoint_curl_transpose_sign", "htot[cc][x] = w[3 + cc][x] + S * curl_plus(s, u, cc, i, j, k);",
      "htot[cc][x] = w[3 + cc][x] - S * curl_plus(s, u, cc, i, j, k);"),
