@@ -119,7 +119,8 @@ def write_traffic(fetch_dir, write_dir, kernel, workload, tuning):
     fw = CALIB_BYTES / (cw * 1024.0)
     rd, wr = kf * 1024.0 * ff, kw * 1024.0 * fw
     cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {c} -d $OUT/{d} -o run -- "
-           "python3 $REPO/bench.py --workload " + workload + " --steps 8 --warmup 4 --no-cpu-baseline --calib-copy")
+           "python3 $REPO/bench.py --workload " + workload + " --steps 8 --warmup 4 --no-cpu-baseline --no-legs "
+           "--calib-copy")
     out = f"""# HBM traffic of `{kernel}` on the {workload} bench workload
 
 Kernel: `{kname}`
@@ -309,23 +310,31 @@ def c5_batch(args, I, mbf, stream):
 
 def c3_batch(args, I, mbf, stream):
     """Many small realizations of uneven size: 64 packings with N drawn from
-    {48, 64, 80, 96}, prepumped, with noise, at eight pump levels."""
+    {48, 64, 80, 96} behind the graded absorbing layer, prepumped, with
+    noise, at eight pump levels relative to each packing's own threshold
+    (found first by a pulse-excited pump sweep of every packing)."""
+    from paper_0809_1547_amd import sweep
     R = 64
     sizes = I.batch_sizes(R, seed=0)
-    cfgs = [mbf.make_config(N, boundary="pec", seed=0, realization=r) for r, N in enumerate(sizes)]
+    mats = [I.voxelize(I.rsa_pack(N, seed=r, fill=0.4)) for r, N in enumerate(sizes)]
+    t0 = time.perf_counter()
+    n_th, _ = sweep.packing_thresholds(mats, sizes, stream=stream.cuda_stream)
+    log(f"c3 thresholds ({time.perf_counter() - t0:.1f} s): " +
+        ", ".join(f"{N}^3 {np.mean([t for t, m in zip(n_th, sizes) if m == N]):.3g}" for N in sorted(set(sizes))))
+    levels = I.batch_pump_levels(R, n_th)
+    cfgs = [mbf.make_config(N, boundary="absorb", seed=0, realization=r) for r, N in enumerate(sizes)]
     batch = mbf.Batch(cfgs, stream=stream.cuda_stream)
-    levels = I.batch_pump_levels(R, 2e24)     # nominal threshold: throughput does not depend on it
-    mats = []
-    for r, N in enumerate(sizes):
-        eps, gain = I.voxelize(I.rsa_pack(N, seed=r, fill=0.4))
-        mats.append((eps, gain))
-        batch[r].set_material(eps, gain)
+    for r in range(R):
+        batch[r].set_material(*mats[r])
         batch[r].set_pump(levels[r], "prepumped")
     cells = sum(N ** 3 for N in sizes)
     config = {
         "workload": f"{R} realizations of uneven size (N in {{48,64,80,96}}, {cells} cells in all), "
-                    "RSA spheres d=300nm n=2.9 fill 0.4, prepumped, noise, 8 pump levels, PEC walls",
+                    "RSA spheres d=300nm n=2.9 fill 0.4, prepumped, noise, graded absorbing layer, "
+                    "8 pump levels 0.5..4 x each packing's threshold from a pump sweep",
         "sizes": sizes,
+        "n_th_by_size": {str(N): float(np.mean([t for t, m in zip(n_th, sizes) if m == N]))
+                         for N in sorted(set(sizes))},
     }
     return batch, cells, config, (sizes, mats, levels)
 
@@ -341,7 +350,7 @@ def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream, concurrent=Fa
     for r, N in enumerate(sizes):
         st = torch.cuda.Stream() if concurrent else stream
         streams.append(st)
-        s = mbf.Sim(N, boundary="pec", seed=0, realization=r, stream=st.cuda_stream)
+        s = mbf.Sim(N, boundary="absorb", seed=0, realization=r, stream=st.cuda_stream)
         s.set_tuning(**tuning)
         s.set_material(*mats[r])
         s.set_pump(levels[r], "prepumped")

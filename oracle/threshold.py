@@ -5,7 +5,8 @@ threshold and kappa fits, never by the product library.
 
 Threshold (the E = 1 point of the Gross-Pitaevskii section, found on the
 simulations themselves): each run of a pump sweep starts from the pumped
-state with a small seeded field and no noise; in the linear regime its
+state with a small excitation (a seeded field, or a pulse with no DC
+content) and no noise; in the linear regime its
 energy follows the least-damped mode, W^n ~ exp(2 gamma n dt), so
     rate(N_a) = least-squares slope of ln W^n over the steps n0 <= n < n1
 (per step), and the threshold N_th is the root of the least-squares line

@@ -367,10 +367,12 @@ def batch_sizes(count: int = 64, seed: int = 0) -> List[int]:
     return out
 
 
-def batch_pump_levels(count: int, n_th: float) -> List[float]:
+def batch_pump_levels(count: int, n_th) -> List[float]:
     """Pump densities of the batched workload: level p = r mod 8 at
-    0.5 * 8**(p/7) times threshold (8 log-spaced levels, 0.5x to 4x)."""
-    return [0.5 * 8.0 ** ((r % 8) / 7.0) * n_th for r in range(count)]
+    0.5 * 8**(p/7) times threshold (8 log-spaced levels, 0.5x to 4x).
+    n_th is one threshold for every realization or one per realization."""
+    th = np.broadcast_to(np.asarray(n_th, dtype=np.float64), (count,))
+    return [0.5 * 8.0 ** ((r % 8) / 7.0) * float(th[r]) for r in range(count)]
 
 
 def synthetic_spectra(n_probes: int, n_freq: int, *, seed: int,

@@ -1,0 +1,90 @@
+"""Writes lasing64_oracle.json: the oracle's lasing run of a 64^3 random
+laser, the reference of the 64^3 lasing-regime parity test.
+
+Test infrastructure: calls only the oracle (FP64 arithmetic, coefficients
+rounded once to binary32 as the FP32 library forms them) and the seeded input
+generators.  About 8 minutes on 8 cores:
+
+    python tests/golden/make_lasing64.py
+
+The run: 64^3 cells of 20 nm, RSA spheres (d = 300 nm, eps_r = 8.41, fill
+0.4, seed 0) in the gain medium, the graded absorbing layer on every wall,
+ground-state start at N_a = 2.5e25 m^-3 (about twice the threshold of this
+packing), spontaneous-emission noise at the default
+amplitude (seed 0, realization 0), 40000 steps (1.5 ps); running DFT of E at
+64 seeded probe sites over 450-800 nm at the run's resolution.  Stored: the
+probe-summed power spectrum, its statistics, the energy every 1000 steps and
+E at 1024 seeded sites after the last step.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O                                   # noqa: E402
+from oracle import spectra as OS                     # noqa: E402
+from paper_0809_1547_amd import inputs as I          # noqa: E402
+
+N, STEPS, NA = 64, 40000, 2.5e25
+N_PROBES, N_SAMPLES = 64, 1024
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lasing64_oracle.json")
+
+
+def setup():
+    eps, gain = I.voxelize(I.rsa_pack(N, seed=0, fill=0.4))
+    probes = I.select_probes(eps, gain, N_PROBES, seed=0)
+    return eps, gain, probes
+
+
+def sample_sites():
+    # interior E-sites (comp, i, j, k), seeded
+    g = np.random.Generator(np.random.PCG64([0, 64, 7]))
+    out = []
+    while len(out) < N_SAMPLES:
+        c = int(g.integers(0, 3))
+        ijk = [int(v) for v in g.integers(1, N, size=3)]
+        out.append([c] + ijk)
+    return out
+
+
+def main():
+    eps, gain, probes = setup()
+    o = O.Oracle(O.default_params(N, bc=(O.ABSORB,) * 3, round_f32=True, seed=0, realization=0))
+    o.set_material(eps, gain)
+    o.set_pump(NA, O.GROUND)
+    dt = o.coefficients()[O.C_DT]
+    om = I.dft_omegas(450e-9, 800e-9, STEPS, dt)
+    o.set_probes(probes, om)
+    energy = []
+    for c in range(STEPS // 1000):
+        o.step(1000)
+        energy.append(o.energy()[0])
+        print(f"step {(c + 1) * 1000}: W = {energy[-1]:.6e}", flush=True)
+    F = o.spectrum()
+    stats = OS.spectral_stats(F, om, 0.5)
+    sites = sample_sites()
+    E = [o.field(c) for c in range(3)]
+    values = [float(E[c][k, j, i]) for c, i, j, k in sites]
+    o.close()
+    doc = {
+        "run": {"n": N, "steps": STEPS, "Na": NA, "init": "ground", "boundary": "absorb", "seed": 0,
+                "realization": 0, "packing": "rsa seed 0 fill 0.4", "probes": N_PROBES,
+                "band_m": [450e-9, 800e-9]},
+        "omega": [float(w) for w in om],
+        "power_spectrum": [float(s) for s in OS.power_spectrum(F)],
+        "stats": {k: float(v) for k, v in stats.items()},
+        "energy_every_1000": energy,
+        "sample_sites": sites,
+        "sample_E": values,
+    }
+    with open(OUT, "w") as fh:
+        json.dump(doc, fh, indent=0)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,7 +1,8 @@
 """GPU: the lasing-threshold fit of a pump sweep and the ST-law kappa fit
 (Results section, Fig. 5b; Gross-Pitaevskii section, Eqs. ee, s1, wth)
 through the C ABI, against the oracle on the same inputs, and the threshold
-of a batched sweep against the oracle's own runs of the same members."""
+of a batched sweep against the oracle's own runs of the same members, and
+the two-pass threshold sweep of a packing."""
 import math
 
 import numpy as np
@@ -136,3 +137,33 @@ def test_kappa_fit_errors():
     with pytest.raises(mbf.MbfError) as e:
         mbf.mbf_kappa_fit([3e24], [0.0], 2e24, T_G)
     assert e.value.code == mbf.MBF_EINVAL
+
+
+def test_packing_thresholds_bracket_and_refine_against_the_oracle():
+    # the two-pass sweep on one 32^3 packing behind a weak layer: pass 1 finds
+    # the bracket on the ladder, pass 2's rates and line equal the oracle's
+    # runs at the same levels, and N_th is the root, inside the bracket
+    from paper_0809_1547_amd import sweep
+    n = 32
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=5, fill=0.25))
+    layer = dict(absorb_rate=0.02, absorb_cells=4)
+    nth, d = sweep.packing_thresholds([(eps, gain)], [n], **layer)
+    lo, hi = d["brackets"][0]
+    r1 = d["ladder_rates"][0]
+    j = list(d["ladder"]).index(hi)
+    assert r1[j] > 0 and np.all(r1[:j] <= 0)
+    levels = d["levels"][0]
+    ro = []
+    for na in levels:
+        o = O.Oracle(O.default_params(n, bc=(O.ABSORB,) * 3, round_f32=True, noise=False, **layer))
+        o.set_material(eps, gain)
+        o.set_pump(na, O.PREPUMPED)
+        o.set_source(2, n // 2, n // 2, n // 2, amp=1e-3, lambda_s=590e-9)
+        o.step(3000)
+        ro.append(T.growth_rate(o.energy_history(), 1500, 3000))
+        o.close()
+    fo = T.threshold(levels, ro)
+    print("bracket", lo, hi, "rates", d["rates"][0], "oracle", ro, "N_th", nth[0], fo[2])
+    assert np.allclose(d["rates"][0], ro, rtol=1e-3, atol=1e-7)
+    assert nth[0] == pytest.approx(min(max(fo[2], lo), hi), rel=1e-3)
+    assert lo < nth[0] <= hi

@@ -82,6 +82,9 @@ def test_batch_size_and_pump_draws():
     assert s == I.batch_sizes(64, 0)
     lv = I.batch_pump_levels(16, 1.0)
     assert lv[0] == pytest.approx(0.5) and lv[7] == pytest.approx(4.0) and lv[8] == lv[0]
+    th = np.arange(1.0, 17.0)
+    lv = I.batch_pump_levels(16, th)
+    assert lv[9] == pytest.approx(0.5 * 8 ** (1 / 7) * 10.0) and lv[15] == pytest.approx(4.0 * 16.0)
 
 
 def test_dft_grid_resolution():
