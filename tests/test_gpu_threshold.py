@@ -167,3 +167,45 @@ def test_packing_thresholds_bracket_and_refine_against_the_oracle():
     assert np.allclose(d["rates"][0], ro, rtol=1e-3, atol=1e-7)
     assert nth[0] == pytest.approx(min(max(fo[2], lo), hi), rel=1e-3)
     assert lo < nth[0] <= hi
+
+
+def test_kappa_fit_end_to_end_from_a_simulated_pump_sweep():
+    # f1 -> f3 on one 64^3 packing: its threshold from the two-pass sweep,
+    # a batched pump sweep above it (ground start, noise, 40000 steps, 64
+    # probes), the Gaussian-fit linewidths of the members' spectra as
+    # W = sigma_omega / (2 pi) (the theory's spectrum exp(-omega^2 / (8 pi^2
+    # W^2))), and kappa fitted to them with p = p_th N_a / N_th; the library's
+    # fit must equal the oracle's on the same widths and lie inside the
+    # search interval
+    from paper_0809_1547_amd import sweep
+    mbf = _mbf()
+    n, steps = 64, 40000
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=0, fill=0.4))
+    nth, _ = sweep.packing_thresholds([(eps, gain)], [n])
+    nth = float(nth[0])
+    probes = I.select_probes(eps, gain, 64, seed=0)
+    ratios = [1.1, 1.3, 1.5, 1.7, 2.0, 2.3]
+    cfgs = [mbf.make_config(n, boundary="absorb", seed=0, realization=r) for r in range(len(ratios))]
+    b = mbf.Batch(cfgs)
+    for r, s in enumerate(b.members):
+        s.set_material(eps, gain)
+        s.set_pump(ratios[r] * nth, "ground")
+        s.set_probes(probes, I.dft_omegas(450e-9, 800e-9, steps, s.coefficients()[mbf.MBF_C_DT]), decim=32)
+    b.step(steps)
+    b.sync()
+    stats = b.spectrum_stats(0.5)
+    b.close()
+    for r, q in enumerate(stats):
+        print(f"N_a/N_th {ratios[r]}: peak {q['peak_bin']} fit_ok {q['fit_ok']} bins {q['fit_lo']}-{q['fit_hi']} "
+              f"sigma {q['fit_sigma']:.4e} std {q['std_omega']:.4e}")
+    ok = [r for r, q in enumerate(stats) if q["fit_ok"]]
+    assert len(ok) >= 3
+    Na = np.array([ratios[r] * nth for r in ok])
+    W = np.array([stats[r]["fit_sigma"] / (2.0 * math.pi) for r in ok])
+    M, L, nnu, dnu = 255, 14.0, 512, 0.02
+    k, Wf = mbf.mbf_kappa_fit(Na, W, nth, T_G, M=M, L=L, n_nu=nnu, dnu=dnu)
+    ko, Wo = T.kappa_fit(Na, W, nth, T_G, M, L, nnu, dnu)
+    print(f"N_th {nth:.4e}; widths {W}; kappa GPU {k:.6g} oracle {ko:.6g}; model {Wf}")
+    assert k == pytest.approx(ko, rel=1e-6)
+    assert np.allclose(Wf, Wo, rtol=1e-6)
+    assert 1.01e-3 < k < 9.9
