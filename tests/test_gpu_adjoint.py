@@ -251,5 +251,5 @@ def test_torch_autograd_binding_on_device():
         Ld.backward()
     st.synchronize()
     assert ed.grad.is_cuda and ed.grad.dtype == ed.dtype
-    assert float(Ld) == float(Lh) and float(Nd.grad) == float(Nh.grad)
+    assert Ld.item() == Lh.item() and Nd.grad.item() == Nh.grad.item()
     assert np.array_equal(ed.grad.cpu().numpy(), eh.grad.numpy())

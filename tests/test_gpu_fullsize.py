@@ -1,7 +1,7 @@
 """GPU parity at the benchmark's full size and launch configuration: two
 320^3 realizations of the paper-scale packing advanced as one batch (two-pass
 schedule, tile 64 x 4, 2-plane segments, z-segment layers dealt to the XCDs, graph-replayed chunks
-of 32 steps with probes), member 0 against the FP64 oracle over 40 steps."""
+of 32 steps with probes), member 0 against the FP64 oracle over 120 steps."""
 import math
 
 import numpy as np
@@ -13,7 +13,7 @@ from paper_0809_1547_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 N = 320
-STEPS = 40
+STEPS = 120
 
 
 def test_320_cubed_batch_member_matches_oracle():
