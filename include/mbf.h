@@ -353,6 +353,13 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  *     advance plane by plane together (one barrier per plane) and hand the
  *     H^{n+1/2} of their rows to the neighbouring row's E update through
  *     LDS; only the tile's edges are formed again.  zseg = 0 means 8.
+ *   MBF_VARIANT_FUSED_PERSISTENT: the kernel of MBF_VARIANT_FUSED as one
+ *     persistent launch per step for all members: a grid sized to what the
+ *     device holds at once takes the work items from eight device-side
+ *     queues in work-table order (queue x serves the entries the dispatch
+ *     order meant for XCD x; workgroup b serves queue b mod 8) until they are
+ *     drained, and the last workgroup to finish resets the queues for the
+ *     next launch, so it replays in graphs like the others.
  * group_mb (batches only; >= 0): consecutive members whose device state adds
  * up to at most group_mb MiB form a group, and a graph-replayed chunk of
  * steps runs group by group, so that a group's state can stay in the
@@ -365,6 +372,7 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
 #define MBF_VARIANT_FUSED 1
 #define MBF_VARIANT_TWO_PASS_SPLIT 2
 #define MBF_VARIANT_FUSED_LDS 3
+#define MBF_VARIANT_FUSED_PERSISTENT 4
 typedef struct mbf_tuning {
     int32_t variant;
     int32_t tile_y;

@@ -107,6 +107,7 @@ struct mbf_handle {
     void* d_view = nullptr;
     mbf::Geom* d_geom = nullptr;
     uint32_t* d_items = nullptr;
+    uint32_t* d_queue = nullptr;   // work queues of the persistent fused step (9 counters, zero between launches)
     int items_cap = 0;
     bool tab = false;
     uint64_t tab_version = 0;
@@ -355,7 +356,9 @@ mbf::SimView<T> view(mbf_handle* h) {
 int default_zseg(const mbf_tuning& t) {
     return t.variant == MBF_VARIANT_TWO_PASS_SPLIT ? 2 : (t.variant == MBF_VARIANT_FUSED_LDS ? 8 : 4);
 }
-bool single_pass(int variant) { return variant == MBF_VARIANT_FUSED || variant == MBF_VARIANT_FUSED_LDS; }
+bool single_pass(int variant) {
+    return variant == MBF_VARIANT_FUSED || variant == MBF_VARIANT_FUSED_LDS || variant == MBF_VARIANT_FUSED_PERSISTENT;
+}
 int step_zseg(const mbf_handle* h, const mbf_tuning& t) {
     return t.zseg > 0 ? std::min(t.zseg, h->cfg.nz) : std::min(default_zseg(t), h->cfg.nz);
 }
@@ -444,15 +447,53 @@ hipError_t launch_two_pass(hipStream_t st, int ty, const mbf::SimView<T>* vw, co
     return e;
 }
 
+// Workgroups of the persistent fused step for a work table of ni items: what
+// the device holds at once (occupancy x compute units, asked once per device
+// and tile height), a multiple of 8 so that every one of the eight queues
+// has workgroups, and no more than the items need.
+template <typename T, int TY>
+int persist_grid(int ni) {
+    static int per_dev[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (per_dev[dev] == 0) {
+        int nb = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)mbf::k_step_fused_persist<T, TY>,
+                                                         64 * TY, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 1;
+        per_dev[dev] = nb * cus;
+    }
+    const int need = (ni + 7) / 8 * 8;
+    return std::max(8, std::min(per_dev[dev], need) / 8 * 8);
+}
+
 // The field kernels of one step (both passes, or the fused pass) over the
 // work table it[0..ni) of the views vw and geometries gw; evm (optional) is
-// recorded between the two passes.
+// recorded between the two passes; queue holds the persistent variant's
+// counters (zero between launches).
 template <typename T>
 hipError_t launch_fields(hipStream_t st, const mbf_tuning& tun, const mbf::SimView<T>* vw,
-                         const mbf::Geom* gw, const uint32_t* it, int ni, hipEvent_t evm) {
+                         const mbf::Geom* gw, const uint32_t* it, int ni, hipEvent_t evm, uint32_t* queue) {
     const int rm = tun.xcd_remap;
     const dim3 g((unsigned)ni);
     hipError_t e = hipSuccess;
+    if (tun.variant == MBF_VARIANT_FUSED_PERSISTENT) {
+        if (!queue) return hipErrorInvalidValue;
+        switch (tun.tile_y) {
+            case 2: hipLaunchKernelGGL((mbf::k_step_fused_persist<T, 2>), dim3((unsigned)persist_grid<T, 2>(ni)),
+                                       dim3(64, 2), 0, st, vw, gw, it, ni, queue); break;
+            case 4: hipLaunchKernelGGL((mbf::k_step_fused_persist<T, 4>), dim3((unsigned)persist_grid<T, 4>(ni)),
+                                       dim3(64, 4), 0, st, vw, gw, it, ni, queue); break;
+            case 16: hipLaunchKernelGGL((mbf::k_step_fused_persist<T, 16>), dim3((unsigned)persist_grid<T, 16>(ni)),
+                                        dim3(64, 16), 0, st, vw, gw, it, ni, queue); break;
+            default: hipLaunchKernelGGL((mbf::k_step_fused_persist<T, 8>), dim3((unsigned)persist_grid<T, 8>(ni)),
+                                        dim3(64, 8), 0, st, vw, gw, it, ni, queue); break;
+        }
+        if (evm) e = hipEventRecord(evm, st);
+        return e;
+    }
     if (tun.variant == MBF_VARIANT_FUSED_LDS) {
         switch (tun.tile_y) {
             case 2: hipLaunchKernelGGL((mbf::k_step_lds_batch<T, 2>), g, dim3(64, 2), 0, st, vw, gw, it, ni, rm); break;
@@ -494,8 +535,10 @@ int self_tables(mbf_handle* h, const mbf::Geom& g) {
     h->tab = false;
     if (!h->d_view) {
         if (hipMalloc(&h->d_view, sizeof(mbf::SimView<double>)) != hipSuccess ||
-            hipMalloc(&h->d_geom, sizeof(mbf::Geom)) != hipSuccess)
+            hipMalloc(&h->d_geom, sizeof(mbf::Geom)) != hipSuccess ||
+            hipMalloc(&h->d_queue, sizeof(uint32_t) * 9) != hipSuccess)
             return fail(h, MBF_ENOMEM, "step table allocation failed");
+        HIPCHK(h, hipMemset(h->d_queue, 0, sizeof(uint32_t) * 9));
     }
     if (g.nblk > h->items_cap) {
         hipFree(h->d_items);
@@ -536,7 +579,7 @@ int launch_step(mbf_handle* h, hipEvent_t ev0 = nullptr, hipEvent_t evm = nullpt
     v.n_part = gm.nblk;
     if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
     HIPCHK(h, (launch_fields<T>(h->stream, h->tun, reinterpret_cast<const mbf::SimView<T>*>(h->d_view),
-                                h->d_geom, h->d_items, gm.nblk, evm)));
+                                h->d_geom, h->d_items, gm.nblk, evm, h->d_queue)));
     if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
     if (h->mur_tasks > 0) {
         const int nmax = std::max({h->cfg.nx, h->cfg.ny, h->cfg.nz}) + 1;
@@ -769,7 +812,8 @@ std::vector<mbf_tuning> tuning_candidates(const mbf_tuning& dflt) {
     const int dz = dflt.zseg > 0 ? dflt.zseg : default_zseg(dflt);
     std::vector<mbf_tuning> c;
     c.push_back({dflt.variant, dflt.tile_y, dz, dflt.xcd_remap, 0});
-    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED, MBF_VARIANT_FUSED_LDS})
+    for (int var : {MBF_VARIANT_TWO_PASS, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED, MBF_VARIANT_FUSED_LDS,
+                    MBF_VARIANT_FUSED_PERSISTENT})
         for (int ty : {2, 4, 8})
             for (int zs : {2, 4, 8})
                 if (!(var == dflt.variant && ty == dflt.tile_y && zs == dz)) c.push_back({var, ty, zs, 2, 0});
@@ -997,7 +1041,7 @@ void mbf_destroy(mbf_handle* h) {
     hipFree(h->pool); hipFree(h->gpool); hipFree(h->seg_base);
     hipFree(h->mat); hipFree(h->lut);
     hipFree(h->ctl); hipFree(h->e_part); hipFree(h->l_part); hipFree(h->hist); hipFree(h->lev); hipFree(h->lc);
-    hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items); hipFree(h->map);
+    hipFree(h->d_view); hipFree(h->d_geom); hipFree(h->d_items); hipFree(h->d_queue); hipFree(h->map);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
 }
@@ -1429,7 +1473,7 @@ int mbf_step_bytes(const mbf_handle* h, double* bytes) {
 int mbf_set_tuning(mbf_handle* h, const mbf_tuning* t) {
     if (!h || !t) return fail(h, MBF_EINVAL, "null argument");
     if (t->variant != MBF_VARIANT_FUSED && t->variant != MBF_VARIANT_TWO_PASS && t->variant != MBF_VARIANT_TWO_PASS_SPLIT &&
-        t->variant != MBF_VARIANT_FUSED_LDS)
+        t->variant != MBF_VARIANT_FUSED_LDS && t->variant != MBF_VARIANT_FUSED_PERSISTENT)
         return fail(h, MBF_EINVAL, "unknown variant");
     if (t->tile_y != 2 && t->tile_y != 4 && t->tile_y != 8 && t->tile_y != 16)
         return fail(h, MBF_EINVAL, "tile_y must be 2, 4, 8 or 16");
@@ -2198,6 +2242,7 @@ struct mbf_batch {
     void* d_views = nullptr;
     mbf::Geom* d_geoms = nullptr;
     uint32_t* d_items = nullptr;
+    uint32_t* d_queue = nullptr;   // work queues of the persistent fused step (9 counters, zero between launches)
     int nitems = 0;
     struct Group {
         int r0, r1;               // members [r0, r1)
@@ -2237,7 +2282,7 @@ void batch_drop_graph(mbf_batch* b) {
 void batch_free_tables(mbf_batch* b) {
     hipFree(b->d_views); hipFree(b->d_geoms); hipFree(b->d_items);
     b->d_views = nullptr; b->d_geoms = nullptr; b->d_items = nullptr;
-    b->nitems = 0;
+    b->nitems = 0;   // the queue (d_queue) lives as long as the batch
     b->tables = false;
 }
 
@@ -2284,6 +2329,11 @@ int batch_tables(mbf_batch* b) {
     // q of a launch to XCD q mod 8, so entry q is the item that XCD should run
     for (const mbf_batch::Group& gr : b->groups)
         dispatch_order(items, gr.i0, gr.i1, geoms, b->tun.xcd_remap);
+    if (!b->d_queue) {
+        if (hipMalloc(&b->d_queue, sizeof(uint32_t) * 9) != hipSuccess)
+            return bfail(b, MBF_ENOMEM, "batch table allocation failed");
+        BHIPCHK(b, hipMemset(b->d_queue, 0, sizeof(uint32_t) * 9));
+    }
     if (hipMalloc(&b->d_views, sizeof(mbf::SimView<T>) * R) != hipSuccess ||
         hipMalloc(&b->d_geoms, sizeof(mbf::Geom) * R) != hipSuccess ||
         hipMalloc(&b->d_items, sizeof(uint32_t) * items.size()) != hipSuccess) {
@@ -2316,7 +2366,7 @@ int batch_launch_step(mbf_batch* b, int gi, hipEvent_t ev0 = nullptr, hipEvent_t
     const int ni = gr.i1 - gr.i0;
     hipStream_t st = b->stream;
     if (ev0) BHIPCHK(b, hipEventRecord(ev0, st));
-    BHIPCHK(b, (launch_fields<T>(st, b->tun, vw, gw, it, ni, evm)));
+    BHIPCHK(b, (launch_fields<T>(st, b->tun, vw, gw, it, ni, evm, b->d_queue)));
     if (ev1) BHIPCHK(b, hipEventRecord(ev1, st));
     const mbf::SimView<T>* views = reinterpret_cast<const mbf::SimView<T>*>(b->d_views) + gr.r0;
     const unsigned nm = (unsigned)(gr.r1 - gr.r0);
@@ -2477,6 +2527,7 @@ void mbf_batch_destroy(mbf_batch* b) {
     if (b->stream) hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
     batch_free_tables(b);
+    hipFree(b->d_queue);
     for (mbf_handle* h : b->m) mbf_destroy(h);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
     delete b;

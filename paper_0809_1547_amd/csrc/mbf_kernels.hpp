@@ -971,6 +971,38 @@ __global__ void __launch_bounds__(64 * TY) k_step_fused_batch(const SimView<T>* 
 }
 
 
+// Persistent form of the fused step: a grid sized to what the device holds at
+// once drains the launch's work table from eight queues (queue x serves the
+// entries x, x + 8, x + 16, ... that the dispatch order meant for XCD x, and
+// workgroup b serves queue b mod 8, the XCD the hardware deals it to), so the
+// XCD-aware order of the table survives.  Work items are independent within
+// a step, so any order gives the same fields.  The queue counters are bumped
+// by one lane with device-scope atomics; the last workgroup to leave zeroes
+// all nine counters (eight queues and the leave count) for the next launch.
+// Every workgroup leaves once its queue is empty, so the grid always drains.
+template <typename T, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step_fused_persist(const SimView<T>* __restrict__ views,
+                                                              const Geom* __restrict__ geoms,
+                                                              const uint32_t* __restrict__ items, int nitems,
+                                                              uint32_t* __restrict__ queue) {
+    __shared__ int s_pos;
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    const int qx = (int)(blockIdx.x & 7u);
+    for (;;) {
+        __syncthreads();                  // every wave is done with the previous item
+        if (lead) s_pos = qx + 8 * (int)atomicAdd(queue + qx, 1u);
+        __syncthreads();
+        const int p = s_pos;
+        if (p >= nitems) break;
+        const uint32_t e = items[p];
+        const int r = (int)(e >> 24), w = (int)(e & 0xFFFFFFu);
+        step_fused_body<T, TY>(views[r], geoms[r], w);
+    }
+    if (lead && atomicAdd(queue + 8, 1u) == gridDim.x - 1u) {
+        for (int q = 0; q < 9; ++q) atomicExch(queue + q, 0u);
+    }
+}
+
 // ------------------------------------- fused step with LDS row exchange
 // One pass over the fields per step (rows a1 to a5): H^{n+1/2} is formed,
 // stored and handed to the E update of the same plane without being read back

@@ -76,8 +76,10 @@ class mbf_spec_stats(C.Structure):
 
 
 MBF_VARIANT_TWO_PASS, MBF_VARIANT_FUSED, MBF_VARIANT_TWO_PASS_SPLIT, MBF_VARIANT_FUSED_LDS = 0, 1, 2, 3
+MBF_VARIANT_FUSED_PERSISTENT = 4
 _VARIANTS = {"two_pass": MBF_VARIANT_TWO_PASS, "fused": MBF_VARIANT_FUSED,
-             "two_pass_split": MBF_VARIANT_TWO_PASS_SPLIT, "fused_lds": MBF_VARIANT_FUSED_LDS}
+             "two_pass_split": MBF_VARIANT_TWO_PASS_SPLIT, "fused_lds": MBF_VARIANT_FUSED_LDS,
+             "fused_persistent": MBF_VARIANT_FUSED_PERSISTENT}
 
 
 def _load():

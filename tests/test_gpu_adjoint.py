@@ -84,7 +84,8 @@ def test_checkpoint_interval_does_not_change_the_gradient_and_run_ends_at_nsteps
     mbf = _mbf()
     eps, gain = _material((40, 36, 28), seed=3, fill=0.4)
     out = []
-    for K, var in ((90, None), (7, None), (32, None), (32, "two_pass_split"), (7, "fused"), (9, "fused_lds")):
+    for K, var in ((90, None), (7, None), (32, None), (32, "two_pass_split"), (7, "fused"), (9, "fused_lds"),
+                   (11, "fused_persistent")):
         sim = mbf.Sim((40, 36, 28), boundary="absorb", seed=9, realization=3, E_sp=1e-3)
         if var:
             sim.set_tuning(var, tile_y=4, zseg=2, xcd_remap=2)

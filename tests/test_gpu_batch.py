@@ -55,7 +55,8 @@ def _snapshot(sim, probes):
 @pytest.mark.parametrize("variant,group_mb,remap", [("two_pass", 0, 2), ("fused", 0, 2), ("two_pass", 1, 2),
                                                      ("fused", 2, 1), ("two_pass", 0, 0), ("two_pass_split", 0, 2),
                                                      ("two_pass_split", 1, 1), ("fused_lds", 0, 2),
-                                                     ("fused_lds", 1, 1)])
+                                                     ("fused_lds", 1, 1), ("fused_persistent", 0, 2),
+                                                     ("fused_persistent", 1, 1)])
 def test_batch_members_equal_solo_runs(variant, group_mb, remap):
     # group_mb 1 and 2 split the members into groups that run whole graph
     # chunks one after the other

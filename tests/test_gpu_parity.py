@@ -250,7 +250,9 @@ def test_kernel_variants_are_bitwise_identical(bc):
                                ("fused", 2, 3, 1), ("fused", 4, 0, 0), ("fused", 8, 8, 1),
                                ("fused", 16, 29, 0), ("fused", 4, 1, 2),
                                ("fused_lds", 2, 3, 1), ("fused_lds", 4, 0, 0), ("fused_lds", 8, 8, 2),
-                               ("fused_lds", 16, 29, 0), ("fused_lds", 4, 1, 2), ("fused_lds", 8, 16, 2)]:
+                               ("fused_lds", 16, 29, 0), ("fused_lds", 4, 1, 2), ("fused_lds", 8, 16, 2),
+                               ("fused_persistent", 2, 3, 1), ("fused_persistent", 4, 0, 2),
+                               ("fused_persistent", 16, 29, 0), ("fused_persistent", 8, 1, 2)]:
         sim = mbf.Sim(n, boundary=bc, E_sp=1e-2)
         sim.set_tuning(var, tile_y=ty, zseg=zs, xcd_remap=remap)
         sim.set_material(eps, gain)
@@ -274,7 +276,7 @@ def test_kernel_variants_are_bitwise_identical_in_fp64():
     ref = None
     for var, ty, zs, remap in [("two_pass", 4, 0, 2), ("two_pass_split", 4, 2, 2), ("two_pass_split", 16, 29, 1),
                                ("two_pass_split", 2, 1, 0), ("fused", 4, 0, 2), ("fused_lds", 8, 0, 2),
-                               ("fused_lds", 4, 3, 1)]:
+                               ("fused_lds", 4, 3, 1), ("fused_persistent", 4, 0, 2)]:
         sim = mbf.Sim(n, boundary="absorb", E_sp=1e-2, precision="fp64")
         sim.set_tuning(var, tile_y=ty, zseg=zs, xcd_remap=remap)
         sim.set_material(eps, gain)

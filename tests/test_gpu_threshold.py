@@ -209,3 +209,34 @@ def test_kappa_fit_end_to_end_from_a_simulated_pump_sweep():
     assert k == pytest.approx(ko, rel=1e-6)
     assert np.allclose(Wf, Wo, rtol=1e-6)
     assert 1.01e-3 < k < 9.9
+
+
+def test_batch_growth_threshold_errors():
+    mbf = _mbf()
+    n = (24, 20, 16)
+    eps, gain = I.homogeneous(n, 1.0, 1)
+
+    def batch(hist, levels, steps):
+        b = mbf.Batch([mbf.make_config(n, noise=False, realization=r, energy_history=hist)
+                       for r in range(len(levels))])
+        for r, s in enumerate(b.members):
+            s.set_material(eps, gain)
+            s.set_pump(levels[r], "prepumped")
+            s.set_source(2, 12, 10, 8, amp=1e-3, lambda_s=590e-9)
+        b.step(steps)
+        b.sync()
+        return b
+    cases = [(0, [1e24, 2e24], 64, 10, 64, mbf.MBF_ESTATE),      # no energy history
+             (128, [1e24, 2e24], 64, 10, 100, mbf.MBF_ESTATE),   # window past the run
+             (128, [2e24, 2e24], 64, 10, 64, mbf.MBF_EINVAL),    # equal pump levels
+             (128, [1e24, 2e24], 64, 10, 11, mbf.MBF_EINVAL)]    # window of one step
+    for hist, levels, steps, n0, n1, code in cases:
+        b = batch(hist, levels, steps)
+        with pytest.raises(mbf.MbfError) as e:
+            b.growth_threshold(n0, n1)
+        assert e.value.code == code, (hist, levels, steps, n0, n1)
+        b.close()
+    b = batch(128, [1e24, 2e24, 3e24], 64)
+    rates, fit = b.growth_threshold(10, 64)
+    assert np.all(np.isfinite(rates)) and np.isfinite(fit[2])
+    b.close()
