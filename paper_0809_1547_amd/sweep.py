@@ -70,7 +70,8 @@ def packing_thresholds(mats: Sequence[Tuple[np.ndarray, np.ndarray]], sizes: Seq
     Pass 1 runs every packing at each density of `ladder` and takes the first
     density with a positive growth rate and the one below it (0 below the
     first) as a bracket; pass 2 runs REFINE densities spread evenly over the
-    bracket, fits the line and takes its root, kept inside the bracket.
+    bracket, fits the line and takes its root, kept inside the bracket (the
+    bracket's midpoint when the line is flat).
     Returns (N_th per packing, details dict).  Raises ValueError when a
     packing grows at no density of the ladder."""
     R = len(sizes)
@@ -87,6 +88,8 @@ def packing_thresholds(mats: Sequence[Tuple[np.ndarray, np.ndarray]], sizes: Seq
     lv2 = [np.linspace(lo if lo > 0 else 0.25 * hi, hi, REFINE) for lo, hi in brackets]
     r2, fits = _run(mats, sizes, lv2, boundary=boundary, steps=steps, window=window, amp=amp,
                     lambda_s=lambda_s, stream=stream, phys=phys)
-    nth = np.array([min(max(f[2], lo), hi) for f, (lo, hi) in zip(fits, brackets)])
+    # the root, kept inside the bracket (its midpoint if the line is flat)
+    nth = np.array([min(max(f[2], lo), hi) if np.isfinite(f[2]) else 0.5 * (lo + hi)
+                    for f, (lo, hi) in zip(fits, brackets)])
     return nth, {"ladder": lad, "ladder_rates": r1, "brackets": brackets, "levels": lv2, "rates": r2,
                  "fits": fits}
