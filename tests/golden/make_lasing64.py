@@ -3,7 +3,7 @@ laser, the reference of the 64^3 lasing-regime parity test.
 
 Test infrastructure: calls only the oracle (FP64 arithmetic, coefficients
 rounded once to binary32 as the FP32 library forms them) and the seeded input
-generators.  About 8 minutes on 8 cores:
+generators.  About 16 minutes on 8 cores:
 
     python tests/golden/make_lasing64.py
 
@@ -11,7 +11,8 @@ The run: 64^3 cells of 20 nm, RSA spheres (d = 300 nm, eps_r = 8.41, fill
 0.4, seed 0) in the gain medium, the graded absorbing layer on every wall,
 ground-state start at N_a = 2.5e25 m^-3 (about twice the threshold of this
 packing), spontaneous-emission noise at the default
-amplitude (seed 0, realization 0), 40000 steps (1.5 ps); running DFT of E at
+amplitude (seed 0, realization 0), 78675 steps (3 ps, the length of the paper's
+runs); running DFT of E at
 64 seeded probe sites over 450-800 nm at the run's resolution.  Stored: the
 probe-summed power spectrum, its statistics, the energy every 1000 steps and
 E at 1024 seeded sites after the last step.
@@ -29,7 +30,7 @@ import oracle as O                                   # noqa: E402
 from oracle import spectra as OS                     # noqa: E402
 from paper_0809_1547_amd import inputs as I          # noqa: E402
 
-N, STEPS, NA = 64, 40000, 2.5e25
+N, STEPS, NA = 64, 78675, 2.5e25
 N_PROBES, N_SAMPLES = 64, 1024
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lasing64_oracle.json")
 
@@ -64,6 +65,7 @@ def main():
         o.step(1000)
         energy.append(o.energy()[0])
         print(f"step {(c + 1) * 1000}: W = {energy[-1]:.6e}", flush=True)
+    o.step(STEPS % 1000)
     F = o.spectrum()
     stats = OS.spectral_stats(F, om, 0.5)
     sites = sample_sites()
@@ -82,7 +84,7 @@ def main():
         "sample_E": values,
     }
     with open(OUT, "w") as fh:
-        json.dump(doc, fh, indent=0)
+        json.dump(doc, fh, separators=(",", ":"))
     print("wrote", OUT)
 
 
