@@ -504,6 +504,19 @@ int mbf_kappa_fit(const double* Na, const double* W, int n, double N_th, double 
 int mbf_growth_threshold(const double* hist, int n_runs, int64_t stride, int64_t n0, int64_t n1, const double* Na,
                          int mem_kind, void* stream, double* rates, double* fit);
 
+/* Knee of a pump sweep (Results section, Fig. 5b: the linewidth collapses
+ * where the sample starts to lase; the theory's threshold E = 1), for y =
+ * a width (or its log) against x = N_a: two least-squares lines, one through
+ * points [0, s) and one through [s, n) (at least two each), with the split s
+ * that leaves the least summed squared residual (the first on ties); the
+ * knee is where the two lines cross, kept between x[s-1] and x[s] (their
+ * midpoint if the lines do not cross there at a finite point).  x[n], y[n]
+ * host or device per mem_kind (caller-owned); out[7] host output: knee, s,
+ * aL, bL, aR, bR, residual sum (y = a + b x on each side).  4 <= n <= 1024
+ * and x strictly increasing (MBF_EINVAL), finite values (MBF_ENONFINITE).
+ * Runs on `stream` and returns when done. */
+int mbf_knee_fit(const double* x, const double* y, int n, int mem_kind, void* stream, double* out);
+
 /* ------------------------------------------------------------- packing
  * The sample is a granular packing of dielectric spheres obtained by
  * molecular dynamics (Simulations section; the method is not given there).

@@ -42,6 +42,38 @@ def threshold(Na: np.ndarray, rates: np.ndarray):
     return float(a), float(b), float(-a / b)
 
 
+def knee(x, y):
+    """Two straight lines joined at a knee (the linewidth-vs-pump collapse of
+    Fig. 5b): for every split s, points [0, s) and [s, n) with at least two
+    each, the least-squares line of each part and the summed squared
+    residuals; the split with the smallest sum (the first on ties) and the
+    crossing of its two lines, kept between x[s-1] and x[s] (their midpoint
+    when the lines do not cross at a finite point).  Returns (knee, s,
+    (aL, bL), (aR, bR), residual sum)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.shape[0]
+
+    def line(i0, i1):
+        b, a = np.polyfit(x[i0:i1], y[i0:i1], 1)
+        r = y[i0:i1] - (a + b * x[i0:i1])
+        return a, b, float(np.sum(r * r))
+    best, best_sse = None, None
+    for s in range(2, n - 1):
+        sse = line(0, s)[2] + line(s, n)[2]
+        if best_sse is None or sse < best_sse:
+            best, best_sse = s, sse
+    aL, bL, _ = line(0, best)
+    aR, bR, _ = line(best, n)
+    lo, hi = x[best - 1], x[best]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        k = (aR - aL) / (bL - bR)
+    if not np.isfinite(k):
+        k = 0.5 * (lo + hi)
+    k = min(max(k, lo), hi)
+    return float(k), best, (aL, bL), (aR, bR), best_sse
+
+
 def model_waist(Na, kappa: float, N_th: float, t_g: float, M: int, L: float, n_nu: int, dnu: float):
     """W_model(N_a) in Hz (frequency omega / 2 pi) for every N_a above
     threshold (E(p) > 1)."""

@@ -1901,6 +1901,38 @@ int mbf_growth_threshold(const double* hist, int n_runs, int64_t stride, int64_t
     return growth_threshold_dev(nullptr, ptrs, n0, n1, Na, st, rates, fit);
 }
 
+int mbf_knee_fit(const double* x, const double* y, int n, int mem_kind, void* stream, double* out) {
+    if (!x || !y || !out) return fail(nullptr, MBF_EINVAL, "null argument");
+    if (n < 4 || n > mbf::kKneeMax) return fail(nullptr, MBF_EINVAL, "need 4 <= n <= 1024 points");
+    if (mem_kind != MBF_MEM_HOST && mem_kind != MBF_MEM_DEVICE) return fail(nullptr, MBF_EINVAL, "bad mem_kind");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> xh((size_t)n), yh((size_t)n);
+    if (mem_kind == MBF_MEM_DEVICE) {
+        HIPCHK(nullptr, hipMemcpyAsync(xh.data(), x, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipMemcpyAsync(yh.data(), y, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipStreamSynchronize(st));
+    } else {
+        std::memcpy(xh.data(), x, sizeof(double) * (size_t)n);
+        std::memcpy(yh.data(), y, sizeof(double) * (size_t)n);
+    }
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(xh[(size_t)i]) || !std::isfinite(yh[(size_t)i]))
+            return fail(nullptr, MBF_ENONFINITE, "x and y must be finite");
+        if (i > 0 && !(xh[(size_t)i] > xh[(size_t)i - 1])) return fail(nullptr, MBF_EINVAL, "x must increase strictly");
+    }
+    DevScratch ds;
+    double *dx = nullptr, *dy = nullptr, *dout = nullptr;
+    if (!ds.get(&dx, (size_t)n) || !ds.get(&dy, (size_t)n) || !ds.get(&dout, 7))
+        return fail(nullptr, MBF_ENOMEM, "device allocation for the knee fit failed");
+    HIPCHK(nullptr, hipMemcpyAsync(dx, xh.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIPCHK(nullptr, hipMemcpyAsync(dy, yh.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(mbf::k_knee_fit, dim3(1), dim3(256), 0, st, dx, dy, n, dout);
+    HIPCHK(nullptr, hipGetLastError());
+    HIPCHK(nullptr, hipMemcpyAsync(out, dout, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+    return MBF_OK;
+}
+
 int mbf_pack_md(int n, const double* box, const double* diam, double* centres, const mbf_pack_params* prm,
                 int mem_kind, void* stream, double* energy, double* max_overlap) {
     if (!box || !prm || !energy || !max_overlap || (n > 0 && (!diam || !centres)))

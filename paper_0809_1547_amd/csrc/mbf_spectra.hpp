@@ -286,4 +286,70 @@ __global__ void k_threshold_line(const double* __restrict__ Na, const double* __
     fit[2] = -a / b;
 }
 
+// ------------------------------------------------ knee of a pump sweep
+// Two straight lines fitted to y against x (x increasing), joined at a knee:
+// for every split s, with points [0, s) and [s, n) at least two each, the
+// least-squares line of each part (centred sums in index order) and the sum
+// of the two parts' squared residuals; the split with the smallest sum (the
+// first on ties) and the crossing of its two lines, kept between x[s-1] and
+// x[s] (their midpoint when the lines do not cross there at a finite point).
+// One workgroup; out: knee, s, aL, bL, aR, bR, residual sum.
+constexpr int kKneeMax = 1024;
+
+struct KneeLine {
+    double a, b, sse;
+};
+
+__device__ inline KneeLine knee_line(const double* __restrict__ x, const double* __restrict__ y, int i0, int i1) {
+    const double m = (double)(i1 - i0);
+    double mx = 0.0, my = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        mx += x[i];
+        my += y[i];
+    }
+    mx /= m;
+    my /= m;
+    double sxy = 0.0, sxx = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double dx = x[i] - mx;
+        sxy += dx * (y[i] - my);
+        sxx += dx * dx;
+    }
+    KneeLine l;
+    l.b = sxy / sxx;
+    l.a = my - l.b * mx;
+    l.sse = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double r = y[i] - (l.a + l.b * x[i]);
+        l.sse += r * r;
+    }
+    return l;
+}
+
+__global__ void __launch_bounds__(256) k_knee_fit(const double* __restrict__ x, const double* __restrict__ y, int n,
+                                                  double* __restrict__ out) {
+    __shared__ double s_sse[kKneeMax];
+    for (int s = 2 + (int)threadIdx.x; s <= n - 2; s += (int)blockDim.x) {
+        const KneeLine L = knee_line(x, y, 0, s), R = knee_line(x, y, s, n);
+        s_sse[s] = L.sse + R.sse;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int best = 2;
+    for (int s = 3; s <= n - 2; ++s)
+        if (s_sse[s] < s_sse[best]) best = s;
+    const KneeLine L = knee_line(x, y, 0, best), R = knee_line(x, y, best, n);
+    const double lo = x[best - 1], hi = x[best];
+    double k = (R.a - L.a) / (L.b - R.b);
+    if (!isfinite(k)) k = 0.5 * (lo + hi);
+    k = fmin(fmax(k, lo), hi);
+    out[0] = k;
+    out[1] = (double)best;
+    out[2] = L.a;
+    out[3] = L.b;
+    out[4] = R.a;
+    out[5] = R.b;
+    out[6] = s_sse[best];
+}
+
 }  // namespace mbf

@@ -155,6 +155,7 @@ def _load():
         "mbf_kappa_fit": (I, [dp, dp, I, D, D, I, D, I, D, VP, dp, dp]),
         "mbf_growth_threshold": (I, [VP, I, I64, I64, I64, dp, I, VP, dp, dp]),
         "mbf_batch_growth_threshold": (I, [P, I64, I64, dp, dp]),
+        "mbf_knee_fit": (I, [VP, VP, I, I, VP, dp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -178,7 +179,7 @@ EXPORTED = [
     "mbf_batch_spectrum_stats", "mbf_spectrum_peaks", "mbf_spectral_peaks", "mbf_add_cw_source",
     "mbf_set_plane_monitor", "mbf_reset_plane_monitor", "mbf_read_plane_monitor", "mbf_gp_solve",
     "mbf_gp_eigenvalue", "mbf_gp_threshold", "mbf_pack_md", "mbf_spectral_stats_noalloc",
-    "mbf_kappa_fit", "mbf_growth_threshold", "mbf_batch_growth_threshold",
+    "mbf_kappa_fit", "mbf_growth_threshold", "mbf_batch_growth_threshold", "mbf_knee_fit",
 ]
 
 
@@ -429,6 +430,29 @@ def mbf_kappa_fit(Na, W, N_th: float, t_g: float, M: int = 1023, L: float = 14.0
                              Na.shape[0], float(N_th), float(t_g), int(M), float(L), int(n_nu), float(dnu),
                              C.c_void_p(stream or 0), C.byref(k), Wf.ctypes.data_as(C.POINTER(C.c_double))))
     return k.value, Wf
+
+
+KNEE_FIELDS = ("knee", "split", "aL", "bL", "aR", "bR", "sse")
+
+
+def mbf_knee_fit(x, y, stream: Optional[int] = None) -> dict:
+    """Two-line knee of y against x (numpy arrays or device tensors, float64,
+    x increasing): dict of KNEE_FIELDS."""
+    if isinstance(x, np.ndarray) or not getattr(x, "is_cuda", False):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(-1))
+    if x.shape[0] != y.shape[0]:
+        raise ValueError("x and y must have the same length")
+    px, kx, _a = _ptr_kind(x)
+    py, ky, _b = _ptr_kind(y)
+    if kx != ky:
+        raise ValueError("x and y must live in the same memory")
+    out = np.zeros(7)
+    _check(lib.mbf_knee_fit(px, py, int(x.shape[0]), kx, C.c_void_p(stream or 0),
+                            out.ctypes.data_as(C.POINTER(C.c_double))))
+    d = dict(zip(KNEE_FIELDS, (float(v) for v in out)))
+    d["split"] = int(d["split"])
+    return d
 
 
 def mbf_growth_threshold(hist, Na, n0: int, n1: int, stream: Optional[int] = None):

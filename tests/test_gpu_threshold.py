@@ -1,4 +1,5 @@
-"""GPU: the lasing-threshold fit of a pump sweep and the ST-law kappa fit
+"""GPU: the lasing-threshold fit of a pump sweep, the knee of a width-vs-pump
+curve and the ST-law kappa fit
 (Results section, Fig. 5b; Gross-Pitaevskii section, Eqs. ee, s1, wth)
 through the C ABI, against the oracle on the same inputs, and the threshold
 of a batched sweep against the oracle's own runs of the same members, and
@@ -209,6 +210,15 @@ def test_kappa_fit_end_to_end_from_a_simulated_pump_sweep():
     assert k == pytest.approx(ko, rel=1e-6)
     assert np.allclose(Wf, Wo, rtol=1e-6)
     assert 1.01e-3 < k < 9.9
+    # the knee of the spectral width (ln std) against the pump: where the
+    # emission collapses into lasing lines, at or above the growth threshold
+    na_all = np.array([q * nth for q in ratios])
+    lstd = np.log([q["std_omega"] for q in stats])
+    dk = mbf.mbf_knee_fit(na_all, lstd)
+    kk = T.knee(na_all, lstd)
+    print(f"width knee {dk['knee'] / nth:.3f} N_th (oracle {kk[0] / nth:.3f})")
+    assert dk["split"] == kk[1] and dk["knee"] == pytest.approx(kk[0], rel=1e-9)
+    assert nth <= dk["knee"] <= ratios[-1] * nth
 
 
 def test_batch_growth_threshold_errors():
@@ -240,3 +250,36 @@ def test_batch_growth_threshold_errors():
     rates, fit = b.growth_threshold(10, 64)
     assert np.all(np.isfinite(rates)) and np.isfinite(fit[2])
     b.close()
+
+
+@pytest.mark.parametrize("n,seed", [(4, 0), (7, 1), (33, 2), (200, 3), (1024, 4)])
+def test_knee_fit_matches_oracle(n, seed):
+    # a broad plateau falling into a narrow one, with seeded scatter
+    import torch
+    mbf = _mbf()
+    g = np.random.default_rng(seed)
+    x = np.sort(g.uniform(1e24, 8e24, n))
+    x += np.arange(n) * 1e12                      # strictly increasing
+    xk = np.quantile(x, 0.4)
+    y = np.where(x < xk, 30.0 - 1e-24 * (x - xk), 30.0 - 6e-24 * (x - xk)) + 0.2 * g.standard_normal(n)
+    d = mbf.mbf_knee_fit(x, y)
+    k, s, (aL, bL), (aR, bR), sse = T.knee(x, y)
+    assert d["split"] == s
+    assert d["knee"] == pytest.approx(k, rel=1e-9)
+    assert d["bL"] == pytest.approx(bL, rel=1e-8, abs=1e-40) and d["bR"] == pytest.approx(bR, rel=1e-8, abs=1e-40)
+    assert d["sse"] == pytest.approx(sse, rel=1e-8, abs=1e-20)
+    assert x[s - 1] <= d["knee"] <= x[s]
+    st = torch.cuda.Stream()
+    dd = mbf.mbf_knee_fit(torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda"), stream=st.cuda_stream)
+    assert dd == d
+
+
+def test_knee_fit_errors():
+    mbf = _mbf()
+    x = np.arange(6.0)
+    for args, code in (((x[:3], x[:3]), mbf.MBF_EINVAL), ((np.zeros(1025), np.zeros(1025)), mbf.MBF_EINVAL),
+                       ((x[::-1].copy(), x), mbf.MBF_EINVAL), ((np.array([0.0, 1, 1, 2]), x[:4]), mbf.MBF_EINVAL),
+                       ((x, np.array([0, 1, np.nan, 3, 4, 5.0])), mbf.MBF_ENONFINITE)):
+        with pytest.raises(mbf.MbfError) as e:
+            mbf.mbf_knee_fit(*args)
+        assert e.value.code == code

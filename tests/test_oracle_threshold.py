@@ -115,3 +115,39 @@ def test_kappa_fit_of_near_threshold_widths_follows_eq_wth():
     W = np.array([math.sqrt(kappa) / (2.0 * math.sqrt(2.0) * math.pi * T_G) / (pth * x / Nth) ** 0.25 for x in Na])
     k, _ = T.kappa_fit(Na, W, Nth, T_G, 1023, 12.0, 400, 0.02)
     assert k == pytest.approx(kappa, rel=5e-3)
+
+
+# ------------------------------------------------------------------ knee
+
+def test_knee_of_two_exact_lines_is_their_crossing():
+    # a broad width below threshold falling linearly, a narrow one above: the
+    # split between the last point of the first line and the first of the
+    # second leaves no residual, and the knee is the lines' crossing
+    x = np.array([1.0, 1.5, 2.0, 2.5, 3.1, 3.6, 4.2, 5.0])
+    xk = 2.8
+    y = np.where(x < xk, 10.0 - 0.5 * (x - xk), 10.0 - 6.0 * (x - xk))
+    k, s, (aL, bL), (aR, bR), sse = T.knee(x, y)
+    assert s == 4 and sse < 1e-24
+    assert k == pytest.approx(xk, abs=1e-12)
+    assert bL == pytest.approx(-0.5) and bR == pytest.approx(-6.0)
+    # shifting y or scaling x moves nothing but the knee's scale
+    assert T.knee(x, y + 3.0)[0] == pytest.approx(xk, abs=1e-12)
+    assert T.knee(2.0 * x, y)[0] == pytest.approx(2.0 * xk, abs=1e-12)
+
+
+def test_knee_is_kept_between_the_split_points():
+    # noisy points: whatever the crossing of the two fitted lines, the knee
+    # lies between the two points either side of the chosen split
+    g = np.random.default_rng(3)
+    for trial in range(20):
+        x = np.sort(g.uniform(0, 10, 12))
+        y = np.where(x < 5, 1.0, 1.0 - (x - 5)) + 0.3 * g.standard_normal(12)
+        k, s, *_ = T.knee(x, y)
+        assert 2 <= s <= len(x) - 2
+        assert x[s - 1] <= k <= x[s]
+
+
+def test_knee_of_a_straight_line_takes_the_first_split():
+    x = np.arange(6.0)
+    k, s, _, _, sse = T.knee(x, 2.0 * x + 1.0)
+    assert s == 2 and sse < 1e-24 and x[1] <= k <= x[2]
