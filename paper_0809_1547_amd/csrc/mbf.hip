@@ -1513,21 +1513,45 @@ int mbf_autotune(mbf_handle* h, int budget_ms, mbf_tuning* chosen) {
     double best_ms = 1e300;
     const auto t0 = std::chrono::steady_clock::now();
     int tried = 0;
+    auto trial = [&](const mbf_tuning& cand, double& t) -> int {
+        int q = mbf_set_tuning(h, &cand);
+        double ms[2] = {0.0, 0.0};
+        int64_t cnt = 0;
+        if (!q) q = mbf_step_timed(h, 1, ms, &cnt);        // first launch of this shape
+        if (!q) q = mbf_step_timed(h, 3, ms, &cnt);
+        if (!q) q = snap_copy(h, sn, false);
+        t = ms[0] + ms[1];
+        return q;
+    };
+    std::vector<std::pair<double, mbf_tuning>> timed;
     for (const mbf_tuning& cand : tuning_candidates(default_tuning((int64_t)h->cfg.nx * h->cfg.ny * h->cfg.nz))) {
         if (rc) break;
         const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (tried > 0 && el > budget_ms) break;
-        rc = mbf_set_tuning(h, &cand);
-        double ms[2];
-        int64_t cnt = 0;
-        if (!rc) rc = mbf_step_timed(h, 1, ms, &cnt);       // first launch of this shape
-        if (!rc) rc = mbf_step_timed(h, 3, ms, &cnt);
-        if (!rc) rc = snap_copy(h, sn, false);
+        double t = 0.0;
+        rc = trial(cand, t);
         if (rc) break;
         ++tried;
-        if (ms[0] + ms[1] < best_ms) {
-            best_ms = ms[0] + ms[1];
+        timed.push_back({t, cand});
+        if (t < best_ms) {
+            best_ms = t;
             best = cand;
+        }
+    }
+    // the three fastest timed once more; the best mean of two trials wins
+    if (!rc && timed.size() > 1) {
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const std::pair<double, mbf_tuning>& x, const std::pair<double, mbf_tuning>& y) {
+                             return x.first < y.first;
+                         });
+        double best_mean = 1e300;
+        for (size_t q = 0; q < std::min<size_t>(3, timed.size()) && !rc; ++q) {
+            double t = 0.0;
+            rc = trial(timed[q].second, t);
+            if (!rc && 0.5 * (t + timed[q].first) < best_mean) {
+                best_mean = 0.5 * (t + timed[q].first);
+                best = timed[q].second;
+            }
         }
     }
     const int rc2 = mbf_set_tuning(h, rc ? &keep : &best);
@@ -2710,6 +2734,7 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > budget_ms;
     };
     std::vector<mbf_tuning> tried;
+    std::vector<std::pair<double, mbf_tuning>> timed;
     auto consider = [&](const mbf_tuning& cand) {
         for (const mbf_tuning& t : tried)
             if (t.variant == cand.variant && t.tile_y == cand.tile_y && t.zseg == cand.zseg &&
@@ -2718,6 +2743,7 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
         tried.push_back(cand);
         double ms = 0.0;
         rc = trial(cand, ms);
+        if (!rc) timed.push_back({ms, cand});
         if (!rc && ms < best_ms) {
             best_ms = ms;
             best = cand;
@@ -2748,6 +2774,24 @@ int mbf_batch_autotune(mbf_batch* b, int budget_ms, mbf_tuning* chosen) {
         mbf_tuning cand = sched;
         cand.group_mb = g;
         consider(cand);
+    }
+    // one trial can be a few percent off, and the fastest of many single
+    // trials is often the luckiest: the three fastest are timed once more
+    // and the best mean of their two trials wins
+    if (!rc && timed.size() > 1) {
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const std::pair<double, mbf_tuning>& x, const std::pair<double, mbf_tuning>& y) {
+                             return x.first < y.first;
+                         });
+        double best_mean = 1e300;
+        for (size_t q = 0; q < std::min<size_t>(3, timed.size()) && !rc; ++q) {
+            double ms = 0.0;
+            rc = trial(timed[q].second, ms);
+            if (!rc && 0.5 * (ms + timed[q].first) < best_mean) {
+                best_mean = 0.5 * (ms + timed[q].first);
+                best = timed[q].second;
+            }
+        }
     }
     const int rc2 = mbf_batch_set_tuning(b, rc ? &keep : &best);
     if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = bfail(b, MBF_EHIP, "synchronise failed");
