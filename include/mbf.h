@@ -491,9 +491,10 @@ int mbf_kappa_fit(const double* Na, const double* W, int n, double N_th, double 
 
 /* Lasing threshold of a pump sweep (Results section, Fig. 5b: the threshold
  * E = 1 of the theory, located on the simulations themselves).  Each run
- * starts from the pumped state with a seeded field and no noise; its energy
- * history W^n (mbf_read_energy_history) grows or decays with the
- * least-damped mode.  rate = least-squares slope of ln W^n over
+ * starts from the pumped state without noise, excited by a small field with
+ * no static part (a soft pulse has none; a random field does, and its
+ * undamped energy hides the decay below threshold); its energy history W^n
+ * (mbf_read_energy_history) grows or decays with the least-damped mode.  rate = least-squares slope of ln W^n over
  * n0 <= n < n1 (per step); the threshold is the root N_th = -a/b of the
  * least-squares line rate = a + b N_a through the runs.  hist[n_runs *
  * stride] (run r at r * stride; host or device per mem_kind, caller-owned),
