@@ -226,10 +226,14 @@ def test_loss_box_and_energy_monitors():
     assert gw == pytest.approx(ow, rel=TOL32) and gi == pytest.approx(oi, rel=TOL32)
 
 
-def test_smallest_grid():
+@pytest.mark.parametrize("variant", [None, "fused_lds", "fused_persistent"])
+def test_smallest_grid(variant):
+    # one work item: the persistent launch's other seven queues are empty
     n = (2, 2, 2)
     eps, gain = I.homogeneous(n, 2.0, 1)
     sim, ora = pair(n, bc=("mur",) * 3, eps=eps, gain=gain, E_sp=1.0)
+    if variant:
+        sim.set_tuning(variant, tile_y=4, zseg=0, xcd_remap=2)
     sim.step(40)
     ora.step(40)
     assert worst(sim, ora, range(21)) <= TOL32
