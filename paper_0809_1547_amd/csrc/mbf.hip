@@ -2938,8 +2938,6 @@ int adjoint_run(mbf_handle* h, int64_t nsteps, int K, void* grad_eps, int mem_ki
     v.lc = reinterpret_cast<const T*>(h->lc);
     v.lc_sy = h->lc_dim[1] * h->lc_dim[2];
     v.lc_sz = h->lc_dim[2];
-    v.lay_kz[0] = h->lay_kz[0];
-    v.lay_kz[1] = h->lay_kz[1];
     v.has_layer = h->has_layer ? 1 : 0;
     const Coef& k = h->co;
     v.S = (T)k.S; v.a = (T)k.a; v.b = (T)k.b; v.ck = (T)k.ck; v.beta = (T)k.beta;

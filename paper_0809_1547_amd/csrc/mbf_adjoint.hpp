@@ -55,7 +55,6 @@ struct AdjView {
     const uint8_t* lev[3][2];
     const T* lc;
     uint32_t lc_sy, lc_sz;
-    int lay_kz[2];
     // coefficients of the forward step
     T S, a, b, ck, beta, dt32, dt21, dt10, dtWp;
     T ck_esp;            // d c_F / d(N_a/N_ref) = ck E_sp (0 without noise)
