@@ -693,7 +693,11 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
             // software pipelining: the next plane's loads (its compact index
             // from the material byte read one plane earlier) go out before this
             // plane's arithmetic and stores, so two planes are in flight per
-            // wave; with SPLIT the plane's own Bloch state goes out first
+            // wave; with SPLIT the plane's own Bloch state goes out first.  The
+            // wave issues them at raised priority, so that a wave about to
+            // issue loads goes ahead of the others' arithmetic (0.3% on the
+            // batch of 320^3 grids; the same in the H pass costs 0.9%)
+            __builtin_amdgcn_s_setprio(2);
             if constexpr (SPLIT) {
                 P.b0 = bloch_load(f, 0, gi, m >= kGainId && j >= 1 && k >= 1);
                 P.b1 = bloch_load(f, 1, gi, m >= kGainId && iny0 && k >= 1);
@@ -707,6 +711,7 @@ __device__ __forceinline__ void curl_e_body(const SimView<T>& v, const Geom& gm,
                 if constexpr (SPLIT) load_dense(Q, f, x + sxy, sx, i, j);
                 else load_plane(Q, f, x + sxy, sx, gi_n, m_n >= kGainId, j >= 1, iny0, inz0, i, j);
             }
+            __builtin_amdgcn_s_setprio(0);
             const bool g = m >= kGainId;
             const bool inx = (j >= 1 && k >= 1), iny = (i >= 1 && k >= 1), inz = (i >= 1 && j >= 1);
             const T ie = s_ie[m];
