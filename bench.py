@@ -1,7 +1,7 @@
 """Throughput benchmark of the Maxwell-Bloch FDTD step on one MI355X.
 
 Workload (default, --workload c5): the paper-scale realization -- 320^3 cells
-(6.4 um box, 7162 spheres of mean diameter 300 nm, index 2.9, fill 0.4, packed
+(6.4 um box, 7245 spheres of diameter 300 +- 30 nm, index 2.9, fill 0.4, packed
 by the library's soft-sphere compression, gain in the voids), ground-state start, spontaneous-emission noise, 256 probe
 sites with running DFT spectra over 450-800 nm at the resolution of the full
 3 ps run, graded absorbing walls -- advanced as a batch of 5 pump levels
@@ -304,6 +304,11 @@ def c5_batch(args, I, mbf, stream):
         "cells_per_realization": n ** 3,
         "batch": args.batch,
         "pump_levels_m3": [NA_LEVELS[r % len(NA_LEVELS)] for r in range(args.batch)],
+        # the sample as built: sphere count, achieved diameter mean and sd, voxel fill
+        "spheres": pk.count,
+        "diameter_nm_mean_sd": [round(float(np.mean(2.0 * pk.radii)) * I.DX * 1e9, 2),
+                                round(float(np.std(2.0 * pk.radii)) * I.DX * 1e9, 2)],
+        "voxel_fill": round(float(1.0 - gain.mean()), 4),
     }
     return batch, n ** 3 * args.batch, config, (eps, gain)
 
