@@ -16,8 +16,11 @@ plain path; both rates are printed.
 Prints ONE JSON line: cell-updates/s of the graph-replayed batched steps,
 the roofline of the dominant kernel (HBM bound: algorithmic bytes per launch
 / average launch duration, from HIP events around every launch on its stream
-in a following pass of up to 64 steps) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+in a following pass of up to 64 steps), the FP64 CPU oracle timed on a
+bounded sample of the same workload (plus windows of the other workloads),
+and three legs: the batch of small realizations against the same members
+one at a time and side by side, the adjoint's cost over the forward, and
+whole runs of the cache-resident single-grid workloads.
 
 `python bench.py --summarize-profile DIR` prints, as markdown, the kernel
 table or the per-dispatch counter means of the rocprofv3 database(s) under
@@ -236,6 +239,38 @@ def oracle_window(O, n, eps, gain, bc, init, Na, steps, threads):
     return n ** 3 * steps / dt, dt
 
 
+def oracle_adjoint_window(O, I, threads, n=12, steps=1000):
+    """The oracle's adjoint (FP64) at n^3: the wall time of its whole
+    forward + reverse run over `steps` steps from the pump (PEC, two spheres,
+    the soft pulse, loss box [4, 8)^3), beside a plain forward run of the same
+    steps; cell-updates/s counts the forward steps."""
+    _omp_threads(threads)
+    eps, gain = I.voxelize(I.rsa_pack(n, seed=0, count=2, radius=2.5))
+
+    def fresh():
+        o = O.Oracle(O.default_params(n, bc=(O.PEC,) * 3, seed=0, realization=0))
+        o.set_material(eps, gain)
+        o.set_pump(2e24, O.PREPUMPED)
+        o.set_source(2, n // 2, n // 2, n // 2, amp=0.3, lambda_s=560e-9, tau_p=0.5e-15, t0=1.5e-15)
+        o.set_loss_box((4, 4, 4), (8, 8, 8))
+        return o
+    o = fresh()
+    t0 = time.perf_counter()
+    o.adjoint_run(steps)
+    t_adj = time.perf_counter() - t0
+    o.close()
+    o = fresh()
+    t0 = time.perf_counter()
+    o.step(steps)
+    t_fwd = time.perf_counter() - t0
+    o.close()
+    log(f"oracle adjoint {n}^3 x {steps} steps on {threads} core(s): {t_adj:.2f} s "
+        f"(forward alone {t_fwd:.3f} s)")
+    return {"workload": "c4-adjoint", "n": n, "steps": steps, "cores": threads,
+            "value": n ** 3 * steps / t_adj, "seconds": t_adj, "forward_seconds": t_fwd,
+            "reverse_over_forward": (t_adj - t_fwd) / t_fwd}
+
+
 def cpu_baseline(I, n5, eps5, gain5, quick=False):
     """The FP64 oracle timed on the machine's host cores: the paper-scale
     realization (the metric's workload) on every core of the affinity mask,
@@ -248,8 +283,12 @@ def cpu_baseline(I, n5, eps5, gain5, quick=False):
         "c4": (96, I.voxelize(I.packing_for("c4", 96, 0)), O.PEC, O.PREPUMPED),
         "c5": (n5, (eps5, gain5), O.ABSORB, O.GROUND),
     }
+    # the batched workload's four grid sizes (graded absorbing layer)
+    for n3 in (48, 64, 80, 96):
+        mats[f"c3/{n3}"] = (n3, I.voxelize(I.packing_for("c3", n3, 0)), O.ABSORB, O.PREPUMPED)
     # (workload, steps on all cores, steps on one core)
-    plan = [("c1", 500, 100), ("c2", 200, 10), ("c4", 100, 10), ("c5", 10, 1)]
+    plan = [("c1", 500, 100), ("c2", 200, 10), ("c3/48", 100, 10), ("c3/64", 100, 10), ("c3/80", 100, 10),
+            ("c3/96", 100, 10), ("c4", 100, 10), ("c5", 10, 1)]
     if quick:
         plan = [("c5", 2, 0)]
     windows = []
@@ -262,6 +301,9 @@ def cpu_baseline(I, n5, eps5, gain5, quick=False):
             windows.append({"workload": name, "n": n, "steps": steps, "cores": threads,
                             "value": v, "seconds": dt})
             log(f"oracle {name} {n}^3 x {steps} steps on {threads} core(s): {v:.3e} cu/s ({dt:.1f} s)")
+    if not quick:
+        for threads in (cores, 1):
+            windows.append(oracle_adjoint_window(O, I, threads))
     _omp_threads(cores)
     main = next(w for w in windows if w["workload"] == "c5" and w["cores"] == cores)
     return {"value": main["value"], "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
@@ -395,6 +437,43 @@ def c3_leg(args, I, mbf, steps=256, budget_ms=3000):
     return {"workload": config["workload"], "steps": steps, "tuning": tuning,
             "batched": batched, "one_at_a_time": serial, "side_by_side": conc,
             "batched_over_one_at_a_time": batched / serial, "batched_over_side_by_side": batched / conc}
+
+
+def configs_leg(I, mbf, runs=10, warm=3):
+    """The cache-resident workloads on the GPU: C1 (32^3 x 500, PEC), C2
+    (128^3 x 5000, graded absorbing layer) and C4 (96^3 x 1000, PEC), each
+    pre-pumped at N_a = 2e24 with noise, FP32, the default schedule for its
+    size.  Each config's whole run is timed with events on the handle's
+    stream (graph-replayed chunks), `warm` untimed runs first, then the median
+    of `runs` (the state carries on from run to run)."""
+    import torch
+    out = []
+    for name, n, steps, bc in (("c1", 32, 500, "pec"), ("c2", 128, 5000, "absorb"), ("c4", 96, 1000, "pec")):
+        eps, gain = I.voxelize(I.packing_for(name, n, 0))
+        stream = torch.cuda.Stream()
+        s = mbf.Sim(n, boundary=bc, precision="fp32", seed=0, realization=0, stream=stream.cuda_stream)
+        s.set_material(eps, gain)
+        s.set_pump(2e24, "prepumped")
+        ms = []
+        for q in range(warm + runs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            e1.synchronize()
+            if q >= warm:
+                ms.append(e0.elapsed_time(e1))
+        s.energy()                        # raises on a non-finite energy
+        tun = s.tuning()
+        s.close()
+        med = float(np.median(ms))
+        out.append({"workload": name, "n": n, "steps": steps, "boundary": bc,
+                    "value": n ** 3 * steps / (med / 1e3), "unit": "cell-updates/s",
+                    "ms_median": med, "ms_min": float(min(ms)), "ms_max": float(max(ms)), "runs": runs,
+                    "tuning": tun})
+        log(f"{name} {n}^3 x {steps}: median {med:.2f} ms ({n ** 3 * steps / (med / 1e3):.3e} cu/s) over "
+            f"{runs} runs")
+    return out
 
 
 def adjoint_leg(I, mbf, runs=3):
@@ -675,9 +754,16 @@ def main():
         if not args.no_legs:
             extra_out["batched_leg"] = c3_leg(args, I, mbf)
             extra_out["adjoint_leg"] = adjoint_leg(I, mbf)
+            extra_out["configs_leg"] = configs_leg(I, mbf)
         if not args.no_cpu_baseline:
             cpu = cpu_baseline(I, args.n, eps, gain, quick=args.quick_cpu)
             log(f"cpu baseline: {cpu['value']:.3e} cu/s on {cpu['cores']} cores")
+            # each config's GPU rate over the oracle's on every core
+            for c in extra_out.get("configs_leg", []):
+                w = [x for x in cpu["windows"] if x["workload"] == c["workload"] and x["cores"] == cpu["cores"]]
+                if w:
+                    c["oracle_all_cores"] = w[0]["value"]
+                    c["gpu_over_oracle"] = c["value"] / w[0]["value"]
 
     out = {
         "metric": "cell-updates/s",
