@@ -52,7 +52,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=192)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--n", type=int, default=320, help="cells per side")
     ap.add_argument("--batch", type=int, default=5)
@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-cpu", action="store_true", help="time only 2 oracle steps of the c5 realization")
     ap.add_argument("--no-legs", action="store_true",
-                    help="c5: skip the batched (c3, reduced) and adjoint (c4) legs")
+                    help="c5: skip the batched (c3, reduced), adjoint (c4) and single-grid (c1, c2, c4) legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain elementwise kernel of known traffic (counter calibration)")
