@@ -386,19 +386,19 @@ def c3_batch(args, I, mbf, stream):
     return batch, cells, config, (sizes, mats, levels)
 
 
-def one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream, concurrent=False):
+def one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=False):
     """The same realizations stepped through the plain path, each with its own
-    graph: one after another on the batch's stream (concurrent=False, so
-    that one runs at a time), or each on a stream of its own, all launched
-    before any is waited for (concurrent=True).  Cell-updates/s over the
-    wall time between two device-wide synchronisations."""
+    graph and its grid's own default schedule: one after another on the
+    batch's stream (concurrent=False, so that one runs at a time), or each on
+    a stream of its own, all launched before any is waited for
+    (concurrent=True).  Cell-updates/s over the wall time between two
+    device-wide synchronisations."""
     import torch
     sims, streams = [], []
     for r, N in enumerate(sizes):
         st = torch.cuda.Stream() if concurrent else stream
         streams.append(st)
         s = mbf.Sim(N, boundary="absorb", seed=0, realization=r, stream=st.cuda_stream)
-        s.set_tuning(**tuning)
         s.set_material(*mats[r])
         s.set_pump(levels[r], "prepumped")
         s.step(32)
@@ -430,8 +430,8 @@ def c3_leg(args, I, mbf, steps=256, budget_ms=3000):
     torch.cuda.synchronize()
     batched = cells * steps / (time.perf_counter() - w0)
     batch.close()
-    serial = one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream)
-    conc = one_at_a_time(mbf, sizes, mats, levels, steps, tuning, stream, concurrent=True)
+    serial = one_at_a_time(mbf, sizes, mats, levels, steps, stream)
+    conc = one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=True)
     log(f"c3 leg ({steps} steps, {time.perf_counter() - t0:.1f} s): batched {batched:.3e}, one at a time "
         f"{serial:.3e}, side by side {conc:.3e} cu/s; tuning {tuning}")
     return {"workload": config["workload"], "steps": steps, "tuning": tuning,
@@ -740,8 +740,8 @@ def main():
     if args.workload == "c3":
         batch.close()
         sizes, mats, levels = extra
-        solo = one_at_a_time(mbf, sizes, mats, levels, args.steps, tuning, stream)
-        conc = one_at_a_time(mbf, sizes, mats, levels, args.steps, tuning, stream, concurrent=True)
+        solo = one_at_a_time(mbf, sizes, mats, levels, args.steps, stream)
+        conc = one_at_a_time(mbf, sizes, mats, levels, args.steps, stream, concurrent=True)
         extra_out["one_at_a_time"] = {"value": solo, "unit": "cell-updates/s",
                                       "ratio_batched_over_solo": value / solo}
         extra_out["side_by_side"] = {"value": conc, "unit": "cell-updates/s",

@@ -367,7 +367,9 @@ int mbf_write_field(mbf_handle* h, int field_id, const void* src, int mem_kind);
  * Results do not depend on it.
  * Default schedule (also the autotuner's first candidate): tile_y 4, zseg 0,
  * xcd_remap 2, group_mb 0, MBF_VARIANT_TWO_PASS_SPLIT for a grid of at least
- * 4 Mi cells (for a batch: its largest member), MBF_VARIANT_TWO_PASS below. */
+ * 4 Mi cells (for a batch: its largest member), MBF_VARIANT_TWO_PASS below;
+ * a single grid below 4 Mi cells takes the longest zseg of 4, 2 and 1 that
+ * still cuts it into at least 1024 work items (1 if none does). */
 #define MBF_VARIANT_TWO_PASS 0
 #define MBF_VARIANT_FUSED 1
 #define MBF_VARIANT_TWO_PASS_SPLIT 2

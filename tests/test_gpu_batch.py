@@ -153,12 +153,14 @@ def test_autotune_keeps_the_trajectory():
     for r, s in enumerate(MEMBERS):
         _setup(batch[r], s, r)
     batch.step(5)
+    first = batch.tuning()
     chosen = batch.autotune(budget_ms=300)
     assert batch.tuning() == chosen
     batch.step(35)
     for r, s in enumerate(MEMBERS):
         solo = mbf.Sim(None, _cfg=_cfg(s, 40))
         _setup(solo, s, r)
+        solo.set_tuning(**first)   # a single grid's own default may cut it finer than a batch's
         solo.step(5)
         solo.set_tuning(**chosen)
         solo.step(35)
@@ -190,11 +192,15 @@ def test_member_schedule_change_does_not_break_batched_steps():
 
 def test_default_schedule_follows_grid_size():
     # the split two-pass variant over 2-plane segments from 4 Mi cells on,
-    # the whole-plane two-pass variant over 4-plane segments below (the
-    # tuning reads back the segment length in effect); a batch goes by its
-    # largest member
+    # the whole-plane two-pass variant below, over the longest of 4, 2 and 1
+    # planes that still makes 1024 work items of 64 x 4 columns (the tuning
+    # reads back the segment length in effect); a batch goes by its largest
+    # member
     mbf = _mbf()
-    for n, want, zs in (((96, 96, 96), "two_pass", 4), ((160, 160, 163), "two_pass", 4),
+    for n, want, zs in (((32, 32, 32), "two_pass", 1), ((64, 64, 64), "two_pass", 1),
+                        ((64, 64, 128), "two_pass", 2), ((80, 80, 80), "two_pass", 2),
+                        ((96, 96, 96), "two_pass", 4), ((65, 64, 256), "two_pass", 4),
+                        ((160, 160, 163), "two_pass", 4),
                         ((160, 160, 164), "two_pass_split", 2), ((320, 320, 320), "two_pass_split", 2)):
         s = mbf.Sim(n)
         t = s.tuning()

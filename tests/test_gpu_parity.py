@@ -249,6 +249,7 @@ def test_kernel_variants_are_bitwise_identical(bc):
     ref = None
     for var, ty, zs, remap in [("two_pass", 8, 0, 0), ("two_pass", 2, 3, 0), ("two_pass", 16, 29, 1),
                                ("two_pass", 4, 40, 0), ("two_pass", 4, 4, 2), ("two_pass", 2, 1, 2),
+                               ("two_pass", 4, 1, 2),
                                ("two_pass_split", 4, 2, 2), ("two_pass_split", 8, 0, 0),
                                ("two_pass_split", 16, 29, 1), ("two_pass_split", 2, 1, 2),
                                ("fused", 2, 3, 1), ("fused", 4, 0, 0), ("fused", 8, 8, 1),
