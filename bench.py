@@ -386,13 +386,13 @@ def c3_batch(args, I, mbf, stream):
     return batch, cells, config, (sizes, mats, levels)
 
 
-def one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=False):
+def one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=False, reps=1):
     """The same realizations stepped through the plain path, each with its own
     graph and its grid's own default schedule: one after another on the
     batch's stream (concurrent=False, so that one runs at a time), or each on
     a stream of its own, all launched before any is waited for
     (concurrent=True).  Cell-updates/s over the wall time between two
-    device-wide synchronisations."""
+    device-wide synchronisations; the median of `reps` such windows."""
     import torch
     sims, streams = [], []
     for r, N in enumerate(sizes):
@@ -403,38 +403,44 @@ def one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=False):
         s.set_pump(levels[r], "prepumped")
         s.step(32)
         sims.append(s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in sims:
-        s.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    rates = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in sims:
+            s.step(steps)
+        torch.cuda.synchronize()
+        rates.append(sum(N ** 3 for N in sizes) * steps / (time.perf_counter() - t0))
     for s in sims:
         s.close()
-    return sum(N ** 3 for N in sizes) * steps / dt
+    return float(np.median(rates))
 
 
-def c3_leg(args, I, mbf, steps=256, budget_ms=3000):
+def c3_leg(args, I, mbf, steps=256, budget_ms=3000, reps=5):
     """The batched workload of many small realizations, reduced to `steps`
     steps: the autotuned batch against the same 64 realizations run one at a
-    time (serially on one stream) and run side by side (a stream each)."""
+    time (serially on one stream) and run side by side (a stream each); each
+    rate the median of `reps` windows of `steps` steps."""
     import torch
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     batch, cells, config, (sizes, mats, levels) = c3_batch(args, I, mbf, stream)
     tuning = batch.autotune(budget_ms=budget_ms)
     batch.step(32)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    batch.step(steps)
-    torch.cuda.synchronize()
-    batched = cells * steps / (time.perf_counter() - w0)
+    rates = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        batch.step(steps)
+        torch.cuda.synchronize()
+        rates.append(cells * steps / (time.perf_counter() - w0))
+    batched = float(np.median(rates))
     batch.close()
-    serial = one_at_a_time(mbf, sizes, mats, levels, steps, stream)
-    conc = one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=True)
+    serial = one_at_a_time(mbf, sizes, mats, levels, steps, stream, reps=reps)
+    conc = one_at_a_time(mbf, sizes, mats, levels, steps, stream, concurrent=True, reps=reps)
     log(f"c3 leg ({steps} steps, {time.perf_counter() - t0:.1f} s): batched {batched:.3e}, one at a time "
         f"{serial:.3e}, side by side {conc:.3e} cu/s; tuning {tuning}")
-    return {"workload": config["workload"], "steps": steps, "tuning": tuning,
+    return {"workload": config["workload"], "steps": steps, "windows": reps, "tuning": tuning,
             "batched": batched, "one_at_a_time": serial, "side_by_side": conc,
             "batched_over_one_at_a_time": batched / serial, "batched_over_side_by_side": batched / conc}
 
