@@ -1,11 +1,14 @@
 """Writes lasing64_oracle.json: the oracle's lasing run of a 64^3 random
-laser, the reference of the 64^3 lasing-regime parity test.
+laser, the reference of the 64^3 lasing-regime parity test; with --hot,
+lasing64_hot_oracle.json, the same sample pre-pumped at N_a = 3.2e26 m^-3
+(about 26 times its threshold).
 
 Test infrastructure: calls only the oracle (FP64 arithmetic, coefficients
 rounded once to binary32 as the FP32 library forms them) and the seeded input
-generators.  About 16 minutes on 8 cores:
+generators.  About 16 minutes on 8 cores each:
 
     python tests/golden/make_lasing64.py
+    python tests/golden/make_lasing64.py --hot
 
 The run: 64^3 cells of 20 nm, RSA spheres (d = 300 nm, eps_r = 8.41, fill
 0.4, seed 0) in the gain medium, the graded absorbing layer on every wall,
@@ -30,9 +33,14 @@ import oracle as O                                   # noqa: E402
 from oracle import spectra as OS                     # noqa: E402
 from paper_0809_1547_amd import inputs as I          # noqa: E402
 
-N, STEPS, NA = 64, 78675, 2.5e25
+N, STEPS = 64, 78675
 N_PROBES, N_SAMPLES = 64, 1024
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lasing64_oracle.json")
+HOT = "--hot" in sys.argv[1:]
+# (N_a, start): twice the packing's threshold from the ground state, or 26
+# times it pre-pumped
+NA, INIT = (3.2e26, "prepumped") if HOT else (2.5e25, "ground")
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                   "lasing64_hot_oracle.json" if HOT else "lasing64_oracle.json")
 
 
 def setup():
@@ -56,7 +64,7 @@ def main():
     eps, gain, probes = setup()
     o = O.Oracle(O.default_params(N, bc=(O.ABSORB,) * 3, round_f32=True, seed=0, realization=0))
     o.set_material(eps, gain)
-    o.set_pump(NA, O.GROUND)
+    o.set_pump(NA, O.PREPUMPED if INIT == "prepumped" else O.GROUND)
     dt = o.coefficients()[O.C_DT]
     om = I.dft_omegas(450e-9, 800e-9, STEPS, dt)
     o.set_probes(probes, om)
@@ -73,7 +81,7 @@ def main():
     values = [float(E[c][k, j, i]) for c, i, j, k in sites]
     o.close()
     doc = {
-        "run": {"n": N, "steps": STEPS, "Na": NA, "init": "ground", "boundary": "absorb", "seed": 0,
+        "run": {"n": N, "steps": STEPS, "Na": NA, "init": INIT, "boundary": "absorb", "seed": 0,
                 "realization": 0, "packing": "rsa seed 0 fill 0.4", "probes": N_PROBES,
                 "band_m": [450e-9, 800e-9]},
         "omega": [float(w) for w in om],
